@@ -1,0 +1,62 @@
+"""CPU tests of the oracle against its pins, and proof that the pins catch
+plausible mistakes planted in the oracle (compiled variants, CPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+
+
+@pytest.mark.parametrize("pin", pins.ALL_PINS, ids=lambda p: p.__name__)
+def test_oracle_pin(orc, pin):
+    msg = pin(orc)
+    assert msg is None, msg
+
+
+# mutant id -> (what it plants, the pins that must notice)
+MUTANTS = {
+    1: ("Algorithm 1 radius update taken literally (r' <- d[x])",
+        [pins.pin_golden_alg1, pins.pin_kd_equals_bf]),
+    2: ("Algorithm 1 far bound taken literally (adds on top of the parent bound)",
+        [pins.pin_golden_alg1, pins.pin_kd_equals_bf, pins.pin_1d_window]),
+    3: ("strict bound test: equal-distance subtrees pruned",
+        [pins.pin_kd_equals_bf, pins.pin_grid_shells]),
+    4: ("tie-break reversed (larger index first)",
+        [pins.pin_grid_shells]),
+    5: ("partition sends x == split to the left",
+        [pins.pin_tree_invariants]),
+    7: ("distance accumulated with a fused multiply-add",
+        [pins.pin_fp32_sum_order]),
+    8: ("sample positions shifted",
+        [pins.pin_split_rule]),
+}
+
+
+@pytest.mark.parametrize("mid", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(tmp_path, mid):
+    what, catchers = MUTANTS[mid]
+    lib = oracle.load(oracle.compile_oracle(str(tmp_path / f"m{mid}.so"), mid))
+    failures = [p.__name__ for p in catchers if p(lib) is not None]
+    assert failures, f"no pin noticed mutant {mid}: {what}"
+
+
+def test_oracle_cfg1_kd_equals_bf(orc):
+    """The 65,536-point uniform workload: KD32 == BF32 on all 4,096 queries."""
+    from paper_1607_08220_amd import inputs
+    w = inputs.workload("tiny_uniform")
+    T = oracle.build(w.points, w.leaf, lib=orc)
+    a = T.query(w.queries, w.k)
+    b = oracle.bf32(w.points, w.queries, w.k, lib=orc)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_oracle_depth_matches_log(orc):
+    """Depth of the sampled-median tree is close to ceil(log2(n / bucket)); the
+    paper reports depth 21 for 50 M points with bucket 32 (Section V-B2), which
+    is ceil(log2(5e7 / 32))."""
+    from paper_1607_08220_amd import inputs
+    assert int(np.ceil(np.log2(5e7 / 32))) == 21
+    X = inputs.clustered(1 << 18, seed=5)
+    T = oracle.build(X, 32, lib=orc)
+    base = int(np.ceil(np.log2(len(X) / 32)))
+    assert base <= T.depth <= base + 3, T.depth
