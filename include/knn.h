@@ -1,0 +1,168 @@
+/*
+ * knn.h -- exact k-nearest-neighbour search with a kd-tree on one MI355X
+ * (gfx950), after Patwary et al., "PANDA: Extreme Scale Parallel K-Nearest
+ * Neighbor on Distributed Architectures" (arXiv 1607.08220).
+ *
+ * The library builds the paper's local kd-tree (Section III-A) on the GPU and
+ * answers batched k-NN queries with the traversal of Algorithm 1
+ * (Section III-B/III-C).  Every call enqueues HIP kernels on the caller's
+ * stream; all point, query and output pointers are DEVICE pointers.
+ *
+ * Result definition (shared by every entry point).  For a query q and points
+ * x_0..x_{n-1} the distance is the FP32 squared Euclidean distance
+ *     D(q, x) = fl(...fl(fl(t_0*t_0) + fl(t_1*t_1)) ... + fl(t_{d-1}*t_{d-1})),
+ *     t_j = fl(q_j - x_j),
+ * IEEE binary32 round-to-nearest-even, separate multiply and add, summed left
+ * to right.  The candidates are the indices i with i != self and D < r2_max;
+ * the answer is the k smallest keys (D, i) in ascending lexicographic order,
+ * padded with (index -1, distance +inf) when fewer than k candidates exist.
+ * This result does not depend on the shape of the tree.
+ *
+ * Return codes: KNN_OK (0) or a negative KNN_E* code; knn_last_error() gives
+ * a message for the calling thread.  No exceptions cross this interface.
+ */
+#ifndef KNN_H
+#define KNN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KNN_OK 0
+#define KNN_EINVAL -1   /* bad argument (null pointer, size or parameter out of range) */
+#define KNN_ENOMEM -2   /* device or host allocation failed */
+#define KNN_EDEVICE -3  /* a HIP call failed; knn_last_error() holds its message */
+#define KNN_EDEPTH -4   /* the tree would be deeper than max_depth */
+
+#define KNN_MAX_DIM 16  /* dimensions supported: 1..KNN_MAX_DIM */
+#define KNN_MAX_K 64    /* neighbours per query: 1..KNN_MAX_K */
+
+typedef struct knn_tree knn_tree; /* opaque; owns all device memory of one tree */
+
+/* Construction parameters (Section III-A1).  Zero selects the default. */
+typedef struct {
+    int32_t leaf_size;      /* bucket size: nodes with more points are split (default 32) */
+    int32_t max_depth;      /* deepest allowed leaf level, root = 0 (default 64) */
+    int32_t subtree_points; /* nodes of at most this many points are finished by one
+                               wavefront in LDS (default: derived from dim, at most 1024) */
+} knn_build_params;
+
+/* Query parameters.  Zero selects the default. */
+typedef struct {
+    int32_t order;  /* 0 (default): process queries grouped by the leaf that contains them;
+                       1: process queries in input order */
+    int32_t pad_;
+    int64_t* stats; /* NULL, or a device pointer to 3 int64 counters the traversal adds to:
+                       nodes entered from above, leaves scanned, points scanned (the
+                       traversal counts of Section V-B2); slower, for measurement only */
+} knn_query_params;
+
+typedef struct {
+    int64_t n;            /* points */
+    int32_t dim;
+    int32_t leaf_size;
+    int32_t depth;        /* deepest leaf level (root = 0) */
+    int32_t subtree_points;
+    int64_t nodes;        /* inner nodes + leaves */
+    int64_t leaves;
+    int64_t device_bytes; /* device memory held by the tree */
+} knn_tree_info_t;
+
+/* Host copy of a tree (knn_tree_export).  The caller allocates every array
+ * with the sizes from knn_tree_info (N = nodes, n, d = dim); NULL skips one.
+ * Node 0 is the root.  Inner node v splits dimension dim[v] at split[v]:
+ * points with x[dim] < split are in child left[v], the others in left[v] + 1.
+ * Leaves have dim[v] = -1 and hold packed positions [start[v], start[v] +
+ * count[v]).  start/count are also filled for inner nodes (their range). */
+typedef struct {
+    int32_t* dim;    /* [N] */
+    float* split;    /* [N] */
+    int32_t* left;   /* [N], -1 for leaves */
+    int32_t* parent; /* [N], -1 for the root */
+    int32_t* start;  /* [N] */
+    int32_t* count;  /* [N] */
+    float* lo;       /* [N * d] tight bounding box, row per node */
+    float* hi;       /* [N * d] */
+    int32_t* perm;   /* [n]  packed position -> original point index */
+    float* packed;   /* [n * d] coordinates in packed (bucket-contiguous) order */
+} knn_tree_host;
+
+/*
+ * knn_build -- construct the kd-tree of Section III-A over n points.
+ *   points  device pointer, row-major [n, dim] FP32 (finite values)
+ *   n       1 .. 2^30 (node ids are int32)
+ *   dim     1 .. KNN_MAX_DIM
+ *   leaf_size >= 1 (0 = default 32)
+ *   stream  a hipStream_t (NULL = default stream)
+ *   out     receives the new tree; the caller frees it with knn_tree_free
+ * Each node is split along the dimension of maximum variance of a sample of
+ * min(1024, count) of its points (Section III-A1, split dimension), at the
+ * sample point whose count of node points below it is closest to half
+ * (Section III-A1, split point; a histogram over the sorted sample), by a
+ * stable partition (Section III-A ii/iii) until nodes hold at most leaf_size
+ * points (Section III-A1, bucket size); buckets are stored contiguously
+ * (Section III-A iv).  The tree copies what it needs: `points` may be reused
+ * once the call returns.  The call synchronizes `stream` before returning.
+ * Errors: KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH (no tree is returned).
+ */
+int knn_build(const float* points, int64_t n, int32_t dim, int32_t leaf_size, void* stream,
+              knn_tree** out);
+
+/* knn_build with all construction parameters (p may be NULL for defaults). */
+int knn_build_ex(const float* points, int64_t n, int32_t dim, const knn_build_params* p,
+                 void* stream, knn_tree** out);
+
+/*
+ * knn_query -- the k nearest neighbours of m queries (Algorithm 1).
+ *   t         a tree from knn_build
+ *   queries   device pointer, row-major [m, dim] FP32
+ *   m         >= 0 (0 is a no-op)
+ *   k         1 .. KNN_MAX_K (k > n pads)
+ *   out_idx   device pointer [m, k] int32: original point indices
+ *   out_dist2 device pointer [m, k] FP32: squared distances, ascending by (D, idx)
+ * Work is enqueued on `stream` and not waited for; the tree must outlive it.
+ * Concurrent queries on one tree (any streams) are allowed.
+ * Errors: KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE.
+ */
+int knn_query(const knn_tree* t, const float* queries, int64_t m, int32_t k, int32_t* out_idx,
+              float* out_dist2, void* stream);
+
+/*
+ * knn_query_ex -- knn_query with Algorithm 1's search radius and self exclusion.
+ *   self_ids  device pointer [m] int32 or NULL; self_ids[i] >= 0 removes that one
+ *             point index from query i's candidates (-1 = none)
+ *   r2_max    squared search radius r^2: only D < r2_max qualify (+inf = none)
+ *   p         query parameters or NULL
+ */
+int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+                 const int32_t* self_ids, float r2_max, const knn_query_params* p,
+                 int32_t* out_idx, float* out_dist2, void* stream);
+
+/* Free a tree and its device memory (waits for the device first).  NULL is OK. */
+int knn_tree_free(knn_tree* t);
+
+/* Sizes and shape of a tree. */
+int knn_tree_info(const knn_tree* t, knn_tree_info_t* info);
+
+/* Copy the tree to host arrays (synchronous); used to check its invariants. */
+int knn_tree_export(const knn_tree* t, knn_tree_host* h);
+
+/* Message describing the last failure of the calling thread. */
+const char* knn_last_error(void);
+
+/* Per-phase device times of the most recent build and query on this thread,
+ * in milliseconds, taken with HIP events on the call's stream while profiling
+ * is enabled (knn_set_profiling(1)).  Phases:
+ *   build: 0 ingest, 1 level passes (sample, histogram, split, partition),
+ *          2 subtree finish in LDS, 3 node compaction and boxes, 4 total
+ *   query: 5 locate home leaves, 6 group queries by leaf, 7 traversal, 8 total */
+#define KNN_PHASES 9
+int knn_set_profiling(int32_t enable);
+int knn_get_profile(float* ms_out /* [KNN_PHASES] */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KNN_H */

@@ -1,0 +1,262 @@
+"""Exact kd-tree k-NN on MI355X (gfx950): Python binding of libknn.so.
+
+Argument marshalling only: every step runs in the HIP kernels of libknn.so
+(built by ``python -m paper_1607_08220_amd.build``).  PyTorch supplies device
+memory and the current stream.  If the library is missing the import of any
+function below raises; there is no CPU fallback.
+
+    import torch, paper_1607_08220_amd as knn
+    tree = knn.knn_build(points_cuda_f32, leaf_size=32)
+    idx, d2 = knn.knn_query(tree, queries_cuda_f32, k=8)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libknn.so")
+
+KNN_OK, KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH = 0, -1, -2, -3, -4
+KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES = 16, 64, 9
+PHASES = ("build_ingest", "build_levels", "build_finish", "build_compact", "build_total",
+          "query_locate", "query_group", "query_traverse", "query_total")
+
+
+class KnnError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"knn error {code}: {msg}")
+        self.code = code
+
+
+class _BuildParams(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("subtree_points", ctypes.c_int32)]
+
+
+class _QueryParams(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("stats", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("subtree_points", ctypes.c_int32),
+                ("nodes", ctypes.c_int64), ("leaves", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class _Host(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("dim", "split", "left", "parent", "start", "count", "lo", "hi", "perm",
+                 "packed")]
+
+
+_lib = None
+EXPORTED = ("knn_build", "knn_build_ex", "knn_query", "knn_query_ex", "knn_tree_free",
+            "knn_tree_info", "knn_tree_export", "knn_last_error", "knn_set_profiling",
+            "knn_get_profile")
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libknn.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_1607_08220_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.knn_build.argtypes = [vp, i64, i32, i32, vp, ctypes.POINTER(vp)]
+    lib.knn_build_ex.argtypes = [vp, i64, i32, ctypes.POINTER(_BuildParams), vp,
+                                 ctypes.POINTER(vp)]
+    lib.knn_query.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    lib.knn_query_ex.argtypes = [vp, vp, i64, i32, vp, ctypes.c_float,
+                                 ctypes.POINTER(_QueryParams), vp, vp, vp]
+    lib.knn_tree_free.argtypes = [vp]
+    lib.knn_tree_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    lib.knn_tree_export.argtypes = [vp, ctypes.POINTER(_Host)]
+    lib.knn_last_error.argtypes = []
+    lib.knn_last_error.restype = ctypes.c_char_p
+    lib.knn_set_profiling.argtypes = [i32]
+    lib.knn_get_profile.argtypes = [ctypes.POINTER(ctypes.c_float)]
+    for name in EXPORTED:
+        if name != "knn_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != KNN_OK:
+        raise KnnError(rc, load_library().knn_last_error().decode())
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dev_f32(t, name, cols=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32 or t.dim() != 2 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 [rows, dim] tensor")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{name} has {t.shape[1]} columns, expected {cols}")
+    return t
+
+
+class Tree:
+    """A kd-tree resident in device memory (owns it until free())."""
+
+    def __init__(self, handle: int, dim: int, device):
+        self._h = ctypes.c_void_p(handle)
+        self.dim = dim
+        self.device = device
+
+    @property
+    def handle(self):
+        if not self._h.value:
+            raise ValueError("tree already freed")
+        return self._h
+
+    def info(self) -> dict:
+        return knn_tree_info(self)
+
+    def query(self, queries, k, self_ids=None, r2_max=math.inf, order=0, out=None):
+        return knn_query_ex(self, queries, k, self_ids=self_ids, r2_max=r2_max, order=order,
+                            out=out)
+
+    def export(self) -> dict:
+        return knn_tree_export(self)
+
+    def free(self):
+        if self._h.value:
+            _check(load_library().knn_tree_free(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def knn_build_ex(points, leaf_size: int = 0, max_depth: int = 0, subtree_points: int = 0) -> Tree:
+    """Build the kd-tree over ``points`` (CUDA float32 [n, dim])."""
+    lib = load_library()
+    _dev_f32(points, "points")
+    p = _BuildParams(leaf_size, max_depth, subtree_points)
+    out = ctypes.c_void_p()
+    _check(lib.knn_build_ex(ctypes.c_void_p(points.data_ptr()), points.shape[0], points.shape[1],
+                            ctypes.byref(p), _stream(points), ctypes.byref(out)))
+    return Tree(out.value, points.shape[1], points.device)
+
+
+def knn_build(points, leaf_size: int = 32) -> Tree:
+    lib = load_library()
+    _dev_f32(points, "points")
+    out = ctypes.c_void_p()
+    _check(lib.knn_build(ctypes.c_void_p(points.data_ptr()), points.shape[0], points.shape[1],
+                         leaf_size, _stream(points), ctypes.byref(out)))
+    return Tree(out.value, points.shape[1], points.device)
+
+
+def _outputs(queries, k, out):
+    import torch
+    m = queries.shape[0]
+    if out is None:
+        return (torch.empty((m, k), dtype=torch.int32, device=queries.device),
+                torch.empty((m, k), dtype=torch.float32, device=queries.device))
+    idx, d2 = out
+    if idx.shape != (m, k) or d2.shape != (m, k) or idx.dtype != torch.int32 \
+            or d2.dtype != torch.float32 or not idx.is_contiguous() or not d2.is_contiguous():
+        raise ValueError("out must be (int32 [m,k], float32 [m,k]) contiguous tensors")
+    return idx, d2
+
+
+def knn_query(tree: Tree, queries, k: int, out=None):
+    """k nearest neighbours: (int32 [m,k] indices, float32 [m,k] squared distances)."""
+    lib = load_library()
+    _dev_f32(queries, "queries", tree.dim)
+    idx, d2 = _outputs(queries, k, out)
+    _check(lib.knn_query(tree.handle, ctypes.c_void_p(queries.data_ptr()), queries.shape[0], k,
+                         ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                         _stream(queries)))
+    return idx, d2
+
+
+def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = math.inf,
+                 order: int = 0, out=None, stats=None):
+    """knn_query with self exclusion (int32 [m], -1 = none), radius and order.
+    ``stats``: optional CUDA int64 [3] tensor the traversal adds its visit
+    counts to (nodes entered, leaves scanned, points scanned)."""
+    import torch
+    lib = load_library()
+    _dev_f32(queries, "queries", tree.dim)
+    idx, d2 = _outputs(queries, k, out)
+    sp = None
+    if self_ids is not None:
+        if not (isinstance(self_ids, torch.Tensor) and self_ids.is_cuda
+                and self_ids.dtype == torch.int32 and self_ids.is_contiguous()
+                and self_ids.shape == (queries.shape[0],)):
+            raise TypeError("self_ids must be a contiguous CUDA int32 [m] tensor")
+        sp = ctypes.c_void_p(self_ids.data_ptr())
+    st = None
+    if stats is not None:
+        if not (isinstance(stats, torch.Tensor) and stats.is_cuda and stats.dtype == torch.int64
+                and stats.numel() >= 3 and stats.is_contiguous()):
+            raise TypeError("stats must be a contiguous CUDA int64 tensor of 3 counters")
+        st = stats.data_ptr()
+    p = _QueryParams(order, 0, st)
+    _check(lib.knn_query_ex(tree.handle, ctypes.c_void_p(queries.data_ptr()), queries.shape[0],
+                            k, sp, ctypes.c_float(r2_max), ctypes.byref(p),
+                            ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                            _stream(queries)))
+    return idx, d2
+
+
+def knn_tree_info(tree: Tree) -> dict:
+    info = _Info()
+    _check(load_library().knn_tree_info(tree.handle, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in _Info._fields_}
+
+
+def knn_tree_export(tree: Tree) -> dict:
+    """Host copy of the tree as numpy arrays (see knn_tree_host in knn.h)."""
+    info = knn_tree_info(tree)
+    N, n, d = info["nodes"], info["n"], info["dim"]
+    arrs = dict(dim=np.empty(N, np.int32), split=np.empty(N, np.float32),
+                left=np.empty(N, np.int32), parent=np.empty(N, np.int32),
+                start=np.empty(N, np.int32), count=np.empty(N, np.int32),
+                lo=np.empty((N, d), np.float32), hi=np.empty((N, d), np.float32),
+                perm=np.empty(n, np.int32), packed=np.empty((n, d), np.float32))
+    h = _Host(**{k: v.ctypes.data for k, v in arrs.items()})
+    _check(load_library().knn_tree_export(tree.handle, ctypes.byref(h)))
+    arrs["right"] = np.where(arrs["left"] >= 0, arrs["left"] + 1, -1)
+    arrs["depth"] = info["depth"]
+    return arrs
+
+
+def knn_tree_free(tree: Tree):
+    tree.free()
+
+
+def knn_last_error() -> str:
+    return load_library().knn_last_error().decode()
+
+
+def knn_set_profiling(enable: bool):
+    _check(load_library().knn_set_profiling(1 if enable else 0))
+
+
+def knn_get_profile() -> dict:
+    buf = (ctypes.c_float * KNN_PHASES)()
+    _check(load_library().knn_get_profile(buf))
+    return {name: float(buf[i]) for i, name in enumerate(PHASES)}

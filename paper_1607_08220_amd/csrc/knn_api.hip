@@ -1,0 +1,243 @@
+// C-ABI entry points of libknn.so: argument checks, error reporting, tree
+// lifetime, export and profiling.  The arithmetic lives in knn_build.hip and
+// knn_query.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "knn_internal.h"
+
+namespace knn {
+
+namespace {
+thread_local std::string g_err;
+thread_local Profiler g_prof;
+
+constexpr int64_t kMaxPoints = int64_t(1) << 30;  // node ids stay below 2^31
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return KNN_ENOMEM;
+    return KNN_EDEVICE;
+}
+
+Profiler& profiler() { return g_prof; }
+
+void prof_mark(hipStream_t s, int slot)
+{
+    if (!g_prof.on) return;
+    if (!g_prof.ev[slot]) (void)hipEventCreate(&g_prof.ev[slot]);
+    if (hipEventRecord(g_prof.ev[slot], s) == hipSuccess) g_prof.have[slot] = true;
+}
+
+static int32_t pow2_floor(int32_t v)
+{
+    int32_t p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+// Largest per-wavefront subtree that fits the device's LDS per block.
+static int32_t subtree_points_for(int32_t d, int32_t requested)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    size_t lds_max = 64 * 1024;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.sharedMemPerBlock > 0)
+        lds_max = prop.sharedMemPerBlock;
+    int32_t w = requested > 0 ? pow2_floor(std::min(requested, kSampleMax)) : default_subtree_points(d);
+    while (w > 64 && finish_lds_bytes_per_wave(d, w) * 4 > lds_max) w >>= 1;
+    return std::max(w, 64);
+}
+
+}  // namespace knn
+
+using namespace knn;
+
+extern "C" {
+
+const char* knn_last_error(void) { return g_err.c_str(); }
+
+int knn_build_ex(const float* points, int64_t n, int32_t dim, const knn_build_params* p,
+                 void* stream, knn_tree** out)
+{
+    if (!out) return fail(KNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!points) return fail(KNN_EINVAL, "points is NULL");
+    if (n < 1 || n > kMaxPoints) return fail(KNN_EINVAL, "n must be in [1, 2^30]");
+    if (dim < 1 || dim > KNN_MAX_DIM) return fail(KNN_EINVAL, "dim must be in [1, 16]");
+    knn_build_params q = p ? *p : knn_build_params{0, 0, 0};
+    if (q.leaf_size < 0 || q.max_depth < 0 || q.subtree_points < 0)
+        return fail(KNN_EINVAL, "negative build parameter");
+    const int32_t leaf = q.leaf_size ? q.leaf_size : kDefaultLeaf;
+    const int32_t max_depth = q.max_depth ? q.max_depth : kDefaultMaxDepth;
+    if (max_depth > 4096) return fail(KNN_EINVAL, "max_depth too large");
+    const int32_t W = subtree_points_for(dim, q.subtree_points);
+    return build_tree(points, n, dim, leaf, max_depth, W, static_cast<hipStream_t>(stream), out);
+}
+
+int knn_build(const float* points, int64_t n, int32_t dim, int32_t leaf_size, void* stream,
+              knn_tree** out)
+{
+    if (leaf_size < 0) return fail(KNN_EINVAL, "leaf_size must be >= 1");
+    knn_build_params p{leaf_size, 0, 0};
+    return knn_build_ex(points, n, dim, &p, stream, out);
+}
+
+int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+                 const int32_t* self_ids, float r2_max, const knn_query_params* p,
+                 int32_t* out_idx, float* out_dist2, void* stream)
+{
+    if (!t) return fail(KNN_EINVAL, "tree is NULL");
+    if (m < 0) return fail(KNN_EINVAL, "m must be >= 0");
+    if (k < 1 || k > KNN_MAX_K) return fail(KNN_EINVAL, "k must be in [1, 64]");
+    if (m > (int64_t(1) << 31) / KNN_MAX_K) return fail(KNN_EINVAL, "m too large");
+    if (std::isnan(r2_max)) return fail(KNN_EINVAL, "r2_max is NaN");
+    if (m == 0) return KNN_OK;
+    if (!queries || !out_idx || !out_dist2) return fail(KNN_EINVAL, "NULL query or output pointer");
+    const int32_t order = p ? p->order : 0;
+    if (order != 0 && order != 1) return fail(KNN_EINVAL, "order must be 0 or 1");
+    DeviceGuard g(t->device);
+    unsigned long long* stats = p ? reinterpret_cast<unsigned long long*>(p->stats) : nullptr;
+    return query_tree(t, queries, m, k, self_ids, r2_max, order, out_idx, out_dist2, stats,
+                      static_cast<hipStream_t>(stream));
+}
+
+int knn_query(const knn_tree* t, const float* queries, int64_t m, int32_t k, int32_t* out_idx,
+              float* out_dist2, void* stream)
+{
+    return knn_query_ex(t, queries, m, k, nullptr, INFINITY, nullptr, out_idx, out_dist2, stream);
+}
+
+int knn_tree_free(knn_tree* t)
+{
+    if (!t) return KNN_OK;
+    DeviceGuard g(t->device);
+    int rc = KNN_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
+    if (t->pts) (void)hipFree(t->pts);
+    if (t->nodes) (void)hipFree(t->nodes);
+    if (t->bbox) (void)hipFree(t->bbox);
+    delete t;
+    return rc;
+}
+
+int knn_tree_info(const knn_tree* t, knn_tree_info_t* info)
+{
+    if (!t || !info) return fail(KNN_EINVAL, "NULL argument");
+    info->n = t->n;
+    info->dim = t->d;
+    info->leaf_size = t->leaf;
+    info->depth = t->depth;
+    info->subtree_points = t->sub_pts;
+    info->nodes = t->n_nodes;
+    info->leaves = (t->n_nodes + 1) / 2;  // a full binary tree
+    info->device_bytes = t->bytes;
+    return KNN_OK;
+}
+
+int knn_tree_export(const knn_tree* t, knn_tree_host* h)
+{
+    if (!t || !h) return fail(KNN_EINVAL, "NULL argument");
+    DeviceGuard g(t->device);
+    const int64_t N = t->n_nodes, n = t->n;
+    const int d = t->d;
+    std::vector<NodeRec> nodes(N);
+    std::vector<float> bbox((size_t)N * 2 * d);
+    std::vector<float> pts((size_t)n * (d + 1));
+    KNN_HIP(hipDeviceSynchronize());
+    KNN_HIP(hipMemcpy(nodes.data(), t->nodes, sizeof(NodeRec) * N, hipMemcpyDeviceToHost));
+    KNN_HIP(hipMemcpy(bbox.data(), t->bbox, sizeof(float) * bbox.size(), hipMemcpyDeviceToHost));
+    KNN_HIP(hipMemcpy(pts.data(), t->pts, sizeof(float) * pts.size(), hipMemcpyDeviceToHost));
+    std::vector<int32_t> start(N), count(N);
+    // children always carry larger ids than their parent
+    for (int64_t v = N - 1; v >= 0; --v) {
+        const NodeRec& r = nodes[v];
+        if (r.dim < 0) {
+            start[v] = r.a;
+            count[v] = -r.dim;
+        } else {
+            if (r.a <= v || r.a + 1 >= N) return fail(KNN_EDEVICE, "corrupt node record");
+            start[v] = start[r.a];
+            count[v] = count[r.a] + count[r.a + 1];
+        }
+    }
+    for (int64_t v = 0; v < N; ++v) {
+        const NodeRec& r = nodes[v];
+        if (h->dim) h->dim[v] = r.dim >= 0 ? r.dim : -1;
+        if (h->split) h->split[v] = r.dim >= 0 ? r.split : 0.0f;
+        if (h->left) h->left[v] = r.dim >= 0 ? r.a : -1;
+        if (h->parent) h->parent[v] = r.parent;
+        if (h->start) h->start[v] = start[v];
+        if (h->count) h->count[v] = count[v];
+        for (int j = 0; j < d; ++j) {
+            if (h->lo) h->lo[v * d + j] = bbox[(size_t)v * 2 * d + j];
+            if (h->hi) h->hi[v * d + j] = bbox[(size_t)v * 2 * d + d + j];
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const float* row = &pts[(size_t)i * (d + 1)];
+        if (h->perm) {
+            int32_t id;
+            std::memcpy(&id, row + d, sizeof(id));
+            h->perm[i] = id;
+        }
+        if (h->packed)
+            for (int j = 0; j < d; ++j) h->packed[i * d + j] = row[j];
+    }
+    return KNN_OK;
+}
+
+int knn_set_profiling(int32_t enable)
+{
+    g_prof.on = enable != 0;
+    for (int i = 0; i < KNN_PHASES + 4; ++i) g_prof.have[i] = false;
+    return KNN_OK;
+}
+
+int knn_get_profile(float* ms_out)
+{
+    if (!ms_out) return fail(KNN_EINVAL, "NULL argument");
+    // (phase, first event, last event)
+    static const int spans[KNN_PHASES][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {0, 4},
+                                             {5, 6}, {6, 7}, {7, 8}, {5, 8}};
+    for (int p = 0; p < KNN_PHASES; ++p) {
+        const int a = spans[p][0], b = spans[p][1];
+        float ms = -1.0f;
+        if (g_prof.have[a] && g_prof.have[b]) {
+            KNN_HIP(hipEventSynchronize(g_prof.ev[b]));
+            KNN_HIP(hipEventElapsedTime(&ms, g_prof.ev[a], g_prof.ev[b]));
+        }
+        ms_out[p] = ms;
+    }
+    return KNN_OK;
+}
+
+}  // extern "C"

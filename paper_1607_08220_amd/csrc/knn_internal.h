@@ -1,0 +1,108 @@
+// Internal declarations shared by the build, query and API translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "knn.h"
+
+namespace knn {
+
+// Tree node, 16 bytes.  Inner node: a = left child id (the right child is
+// a + 1), dim = split dimension (>= 0), split = split value.  Leaf: a = first
+// packed position, dim = -(point count) (< 0), split unused.  parent = -1 at
+// the root.
+struct NodeRec {
+    int32_t a;
+    int32_t parent;
+    float split;
+    int32_t dim;
+};
+static_assert(sizeof(NodeRec) == 16, "NodeRec must stay 16 bytes");
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kSampleMax = 1024;   // sample points per node (Section III-A1)
+constexpr int kDefaultLeaf = 32;   // bucket size the paper found best
+constexpr int kDefaultMaxDepth = 64;
+
+}  // namespace knn
+
+// The tree owns every device buffer below.
+struct knn_tree {
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t leaf = 0;
+    int32_t depth = 0;
+    int32_t sub_pts = 0;
+    int64_t n_nodes = 0;
+    int64_t n_leaves = 0;
+    int32_t device = 0;
+    float* pts = nullptr;            // [n][d+1]: packed coordinates, last word = index bits
+    knn::NodeRec* nodes = nullptr;   // [n_nodes]
+    float* bbox = nullptr;           // [n_nodes][2d]: lo[0..d), hi[0..d)
+    int64_t bytes = 0;
+};
+
+namespace knn {
+
+// Thread-local error reporting.
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define KNN_HIP(expr)                                              \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return ::knn::hip_fail(e_, #expr);   \
+    } while (0)
+
+// Device buffer owned by a scope.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { reset(); }
+    hipError_t alloc(size_t b) {
+        reset();
+        bytes = b;
+        return b ? hipMalloc(&p, b) : hipSuccess;
+    }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void* release() {
+        void* q = p;
+        p = nullptr;
+        bytes = 0;
+        return q;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Profiling: events recorded at phase boundaries on the call's stream.
+struct Profiler {
+    bool on = false;
+    hipEvent_t ev[KNN_PHASES + 4] = {};
+    bool have[KNN_PHASES + 4] = {};
+    float ms[KNN_PHASES] = {};
+};
+Profiler& profiler();
+void prof_mark(hipStream_t s, int slot);
+
+// Largest subtree (points) one wavefront finishes in LDS for dimension d.
+int32_t default_subtree_points(int32_t d);
+size_t finish_lds_bytes_per_wave(int32_t d, int32_t w);
+
+int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
+               int32_t sub_pts, hipStream_t stream, knn_tree** out);
+int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+               const int32_t* self_ids, float r2, int32_t order, int32_t* out_idx,
+               float* out_d2, unsigned long long* stats, hipStream_t stream);
+
+}  // namespace knn
