@@ -41,7 +41,45 @@ constexpr int kItems = 16;                           // elements per lane per bl
 constexpr int kWaveChunk = kWave * kItems;           // 1024 elements per wavefront
 constexpr int kChunk = kBlock * kItems;              // 4096 elements per block
 constexpr int kBins = kSampleMax + 1;                // histogram bins per node
+// The histogram pass gives each block 8 times more points: every block adds
+// its LDS histogram into the node's global one, so fewer blocks mean fewer
+// global atomics on the same counters.
+constexpr int kHistChunk = 8 * kChunk;
 constexpr int kStack = 32;                           // subtree DFS stack (entries)
+
+// A subtree handed to the finish kernel: points [start, start + count) of
+// ping-pong buffer `buf`, node id, parent id, depth of its root; leaf_only
+// marks a bucket that is not split further (at most `leaf` points, or all
+// points identical).
+struct SubEntry {
+    int32_t start, count, node_id, parent;
+    int32_t buf, leaf_only, depth0, pad;
+};
+
+// One level of the level passes, all in device memory: the node list
+// (start, count, id, parent, depth), each node's blocks of kChunk points
+// (blk0, nblk) and the block tables (bnode, bbeg for kChunk blocks; hnode,
+// hbeg for kHistChunk blocks).  cnt = {nodes, blocks, histogram blocks}.
+// Kernels are launched with grids sized for the largest possible level and
+// return at once past these counts, so no level needs a host round trip.
+struct Level {
+    int32_t* start;
+    int32_t* count;
+    int32_t* id;
+    int32_t* parent;
+    int32_t* depth;
+    int32_t* blk0;
+    int32_t* nblk;
+    int32_t* bnode;
+    int32_t* bbeg;
+    int32_t* hnode;
+    int32_t* hbeg;
+    int32_t* cnt;
+};
+
+// Build-wide device counters.
+enum { G_NEXT_ID = 0, G_NSUB = 1, G_ERR = 2, G_COUNT = 4 };
+constexpr int kErrOverflow = -100;
 
 __device__ inline void wave_sync()
 {
@@ -92,20 +130,6 @@ __device__ double block_psum(const double a[4], double* red)
     return r;
 }
 
-// The same tree inside one wavefront: lane l holds a[l + 64 r], r = 0..15.
-__device__ double wave_psum(double a[16])
-{
-#pragma unroll
-    for (int r = 0; r < 8; ++r) a[r] = a[r] + a[r + 8];  // w = 512
-#pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = a[r] + a[r + 4];  // w = 256
-#pragma unroll
-    for (int r = 0; r < 2; ++r) a[r] = a[r] + a[r + 2];  // w = 128
-    double v = a[0] + a[1];                              // w = 64
-    for (int w = 32; w >= 1; w >>= 1) v = v + __shfl_down(v, w);
-    return __shfl(v, 0);
-}
-
 // ---------------------------------------------------------------------------
 // B0: ingest
 // ---------------------------------------------------------------------------
@@ -122,16 +146,17 @@ __global__ void k_ingest(const float* __restrict__ aos, int64_t n, int d,
 // ---------------------------------------------------------------------------
 // B1-B3: sample, split dimension, sorted sample (one block per node)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_sample(const int32_t* __restrict__ lv_start,
-                                                   const int32_t* __restrict__ lv_count,
-                                                   const float* __restrict__ cols, int64_t n,
-                                                   int d, float* __restrict__ samples,
-                                                   int32_t* __restrict__ out_dim)
+__global__ __launch_bounds__(kBlock) void k_sample(Level L, const float* __restrict__ cols,
+                                                   int64_t n, int d, float* __restrict__ samples,
+                                                   int32_t* __restrict__ out_dim,
+                                                   uint32_t* __restrict__ hist)
 {
     __shared__ double red[kBlock];
     __shared__ float sv[kSampleMax];
     const int node = blockIdx.x, t = threadIdx.x;
-    const int64_t start = lv_start[node], c = lv_count[node];
+    if (node >= L.cnt[0]) return;
+    const int64_t start = L.start[node], c = L.count[node];
+    for (int i = t; i < kBins; i += kBlock) hist[(int64_t)node * kBins + i] = 0u;
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
     double bestV = -1.0;
     int best = 0;
@@ -187,11 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(const int32_t* __restrict__ l
 // ---------------------------------------------------------------------------
 // B4: histogram over the sorted sample (blocks over node chunks)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_hist(const int32_t* __restrict__ blk_node,
-                                                 const int32_t* __restrict__ blk_begin,
-                                                 const int32_t* __restrict__ lv_start,
-                                                 const int32_t* __restrict__ lv_count,
-                                                 const int32_t* __restrict__ dimv,
+__global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restrict__ dimv,
                                                  const float* __restrict__ samples,
                                                  const float* __restrict__ cols, int64_t n,
                                                  uint32_t* __restrict__ hist)
@@ -199,25 +220,39 @@ __global__ __launch_bounds__(kBlock) void k_hist(const int32_t* __restrict__ blk
     __shared__ float sv[kSampleMax];
     __shared__ uint32_t h[kBins];
     const int b = blockIdx.x, t = threadIdx.x;
-    const int node = blk_node[b];
+    if (b >= L.cnt[2]) return;
+    const int node = L.hnode[b];
     const int dim = dimv[node];
     if (dim < 0) return;
-    const int64_t start = lv_start[node], c = lv_count[node];
+    const int64_t start = L.start[node], c = L.count[node];
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
-    const int64_t beg = blk_begin[b];
-    const int64_t end = beg + kChunk < c ? beg + kChunk : c;
+    const int64_t beg = L.hbeg[b];
+    const int64_t end = beg + kHistChunk < c ? beg + kHistChunk : c;
     for (int i = t; i < s; i += kBlock) sv[i] = samples[(int64_t)node * kSampleMax + i];
     for (int i = t; i <= s; i += kBlock) h[i] = 0u;
     __syncthreads();
     const float* col = cols + (int64_t)dim * n + start;
-    for (int64_t e = beg + t; e < end; e += kBlock) {
-        const float x = col[e];
-        int pos = 0;  // number of sample values <= x
-        for (int step = kSampleMax; step > 0; step >>= 1) {
-            int np = pos + step;
-            if (np <= s && sv[np - 1] <= x) pos = np;
+    // kHistIlp independent binary searches per thread overlap their LDS latency
+    constexpr int kHistIlp = 8;
+    for (int64_t e0 = beg + t; e0 < end; e0 += (int64_t)kBlock * kHistIlp) {
+        float x[kHistIlp];
+        int pos[kHistIlp];  // number of sample values <= x
+#pragma unroll
+        for (int u = 0; u < kHistIlp; ++u) {
+            const int64_t e = e0 + (int64_t)u * kBlock;
+            x[u] = e < end ? col[e] : 0.0f;
+            pos[u] = 0;
         }
-        atomicAdd(&h[pos], 1u);
+        for (int step = kSampleMax; step > 0; step >>= 1) {
+#pragma unroll
+            for (int u = 0; u < kHistIlp; ++u) {
+                const int np = pos[u] + step;
+                if (np <= s && sv[np - 1] <= x[u]) pos[u] = np;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kHistIlp; ++u)
+            if (e0 + (int64_t)u * kBlock < end) atomicAdd(&h[pos[u]], 1u);
     }
     __syncthreads();
     for (int i = t; i <= s; i += kBlock)
@@ -247,9 +282,7 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* total, uint32_t* wsum)
     return base + x - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_choose(const int32_t* __restrict__ lv_start,
-                                                   const int32_t* __restrict__ lv_count,
-                                                   int32_t* __restrict__ dimv,
+__global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict__ dimv,
                                                    const float* __restrict__ samples,
                                                    const uint32_t* __restrict__ hist,
                                                    const float* __restrict__ cols, int64_t n,
@@ -259,7 +292,8 @@ __global__ __launch_bounds__(kBlock) void k_choose(const int32_t* __restrict__ l
     __shared__ long long gbest[kBlock];
     __shared__ float fl[kBlock], fh[kBlock];
     const int node = blockIdx.x, t = threadIdx.x;
-    const int64_t start = lv_start[node], c = lv_count[node];
+    if (node >= L.cnt[0]) return;
+    const int64_t start = L.start[node], c = L.count[node];
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
     const int dim = dimv[node];
     if (dim >= 0) {
@@ -339,19 +373,16 @@ __global__ __launch_bounds__(kBlock) void k_choose(const int32_t* __restrict__ l
 // ---------------------------------------------------------------------------
 // B6: stable partition -- count, per-node scan, scatter
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_count(const int32_t* __restrict__ blk_node,
-                                                  const int32_t* __restrict__ blk_begin,
-                                                  const int32_t* __restrict__ lv_start,
-                                                  const int32_t* __restrict__ lv_count,
-                                                  const int32_t* __restrict__ dimv,
+__global__ __launch_bounds__(kBlock) void k_count(Level L, const int32_t* __restrict__ dimv,
                                                   const float* __restrict__ splitv,
                                                   const float* __restrict__ cols, int64_t n,
                                                   uint32_t* __restrict__ wave_left)
 {
     const int b = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int node = blk_node[b];
-    const int64_t start = lv_start[node], c = lv_count[node];
-    const int64_t beg = blk_begin[b];
+    if (b >= L.cnt[1]) return;
+    const int node = L.bnode[b];
+    const int64_t start = L.start[node], c = L.count[node];
+    const int64_t beg = L.bbeg[b];
     const int64_t end = beg + kChunk < c ? beg + kChunk : c;
     const int64_t wb = beg + (int64_t)w * kWaveChunk;
     const int64_t we = wb + kWaveChunk < end ? wb + kWaveChunk : end;
@@ -371,15 +402,14 @@ __global__ __launch_bounds__(kBlock) void k_count(const int32_t* __restrict__ bl
     if (lane == 0) wave_left[(int64_t)b * kWavesPerBlock + w] = cnt;
 }
 
-__global__ __launch_bounds__(kBlock) void k_blkscan(const int32_t* __restrict__ node_blk0,
-                                                    const int32_t* __restrict__ node_nblk,
-                                                    const uint32_t* __restrict__ wave_left,
+__global__ __launch_bounds__(kBlock) void k_blkscan(Level L, const uint32_t* __restrict__ wave_left,
                                                     uint32_t* __restrict__ blk_off,
                                                     int32_t* __restrict__ n_left)
 {
     __shared__ uint32_t wsum[kWavesPerBlock];
     const int node = blockIdx.x, t = threadIdx.x;
-    const int b0 = node_blk0[node], nb = node_nblk[node];
+    if (node >= L.cnt[0]) return;
+    const int b0 = L.blk0[node], nb = L.nblk[node];
     uint32_t carry = 0;
     for (int base = 0; base < nb; base += kBlock) {
         const int i = base + t;
@@ -396,18 +426,17 @@ __global__ __launch_bounds__(kBlock) void k_blkscan(const int32_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(
-    const int32_t* __restrict__ blk_node, const int32_t* __restrict__ blk_begin,
-    const int32_t* __restrict__ lv_start, const int32_t* __restrict__ lv_count,
-    const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
+    Level L, const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
     const uint32_t* __restrict__ blk_off, const uint32_t* __restrict__ wave_left,
     const int32_t* __restrict__ n_left, const float* __restrict__ src_cols,
     const int32_t* __restrict__ src_idx, float* __restrict__ dst_cols,
     int32_t* __restrict__ dst_idx, int64_t n, int d)
 {
     const int b = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int node = blk_node[b];
-    const int64_t start = lv_start[node], c = lv_count[node];
-    const int64_t beg = blk_begin[b];
+    if (b >= L.cnt[1]) return;
+    const int node = L.bnode[b];
+    const int64_t start = L.start[node], c = L.count[node];
+    const int64_t beg = L.bbeg[b];
     const int64_t end = beg + kChunk < c ? beg + kChunk : c;
     const int64_t wb = beg + (int64_t)w * kWaveChunk;
     const int64_t we = wb + kWaveChunk < end ? wb + kWaveChunk : end;
@@ -440,39 +469,137 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
 // ---------------------------------------------------------------------------
 // B8-B9: subtree finish, one wavefront per node of at most W points
 // ---------------------------------------------------------------------------
-struct SubEntry {
-    int32_t start, count, node_id, parent;
-    int32_t buf, leaf_only, depth0, pad;
-};
 
-__device__ inline void wave_bitonic(float* buf, int P, int lane)
+// Ordered 32-bit key of a float: equal floats (including -0 and +0) get the
+// same key, and key order is float order.
+__device__ inline uint32_t float_key(float v)
 {
-    for (int k = 2; k <= P; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < P; i += kWave) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    float x = buf[i], y = buf[ixj];
-                    bool asc = (i & k) == 0;
-                    if ((x > y) == asc) {
-                        buf[i] = y;
-                        buf[ixj] = x;
-                    }
-                }
-            }
-            wave_sync();
-        }
+    const uint32_t b = __float_as_uint(v + 0.0f);  // -0 becomes +0
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float key_float(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+__device__ inline uint32_t wave_min_u32(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
 }
 
+// DPP lane moves inside a row of 16 lanes.  row_ror:w gives lane l the value
+// of lane (l + w) mod 16 of its row; row_shl:w gives lane l the value of lane
+// l + w (meaningful for l + w < 16).
+template <int CTRL>
+__device__ inline float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kRowRor = 0x120, kRowShl = 0x100;
+
+// Minimum and maximum over the wavefront of N values at once (order does not
+// matter for min/max, so rotations inside rows, then two cross-row swaps).
+template <int N>
+__device__ inline void wave_minmax(float (&lo)[N], float (&hi)[N])
+{
+#define KNN_MM_STEP(CTRL)                                         \
+    _Pragma("unroll") for (int i = 0; i < N; ++i)                 \
+    {                                                             \
+        lo[i] = fminf(lo[i], dpp_f<CTRL>(lo[i]));                 \
+        hi[i] = fmaxf(hi[i], dpp_f<CTRL>(hi[i]));                 \
+    }
+    KNN_MM_STEP(kRowRor + 8)
+    KNN_MM_STEP(kRowRor + 4)
+    KNN_MM_STEP(kRowRor + 2)
+    KNN_MM_STEP(kRowRor + 1)
+#undef KNN_MM_STEP
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            lo[i] = fminf(lo[i], __shfl_xor(lo[i], o));
+            hi[i] = fmaxf(hi[i], __shfl_xor(hi[i], o));
+        }
+    }
+}
+
+// Cross-lane part of the pairwise tree for N sums at once: a[l] += a[l + w]
+// for w = 32, 16, 8, 4, 2, 1 (the last four through DPP); lane 0's value is
+// the sum, returned to every lane.
+template <int N>
+__device__ inline void wave_tree_n(double (&v)[N], double (&out)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + __shfl_down(v[i], 32);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + __shfl_down(v[i], 16);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<kRowShl + 8>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<kRowShl + 4>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<kRowShl + 2>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_d<kRowShl + 1>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v[i]));
+        const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v[i]));
+        out[i] = __hiloint2double(hi, lo);
+    }
+}
+
+// Lane-local part of the pairwise tree (block_psum's order) for N sums:
+// element l + 64 r of sum i is val(i, r); registers r >= R are zeros, whose
+// additions are skipped (they would not change the sum).  The first level is
+// formed straight from the values so that only 8 partial sums are live.
+template <int N, class Val>
+__device__ inline void lane_tree_n(int R, Val val, double (&out)[N])
+{
+    double a[N][8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            a[i][r] = (r + 8 < R) ? val(i, r) + val(i, r + 8) : val(i, r);
+#pragma unroll
+    for (int h = 4; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int r = 0; r < h; ++r)
+            if (r + h < R) {
+#pragma unroll
+                for (int i = 0; i < N; ++i) a[i][r] = a[i][r] + a[i][r + h];
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = a[i][0];
+}
+
+// One wavefront builds the whole subtree of one node of at most W points in
+// LDS.  Every point is a sample here (W <= 1024), so the histogram rule picks
+// the value of rank floor(cnt/2) or the next larger value, whichever has its
+// count below closer to cnt/2 (ties to the smaller value); the rank is found
+// by a bitwise search over the ordered keys with wavefront ballots.  The
+// index permutation ping-pongs between two LDS arrays, and each bucket's
+// packed rows are written as soon as the bucket is final.
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_finish(
     const SubEntry* __restrict__ subs, int32_t n_sub, const float* __restrict__ colsA,
     const int32_t* __restrict__ idxA, const float* __restrict__ colsB,
-    const int32_t* __restrict__ idxB, int64_t n, int d, int leaf, int W, int max_depth,
+    const int32_t* __restrict__ idxB, int64_t n, int leaf, int W, int max_depth,
     size_t per_wave, float* __restrict__ pts, NodeRec* __restrict__ tnodes,
     float* __restrict__ tbox, int32_t* __restrict__ sub_nodes, int32_t* __restrict__ err,
     int32_t* __restrict__ depth_seen)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int D2 = 2 * D;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sub = blockIdx.x * kWavesPerBlock + w;
     if (sub >= n_sub) return;  // only wavefront-level synchronization below
@@ -481,12 +608,12 @@ __global__ __launch_bounds__(kBlock) void k_finish(
     const int32_t* gidx = e.buf ? idxB : idxA;
     const int64_t gs = e.start;
     const int c = e.count;
-    const int D2 = 2 * d;
     NodeRec* trec = tnodes + 2 * gs;
     float* tb = tbox + 2 * gs * D2;
 
     if (e.leaf_only || c <= leaf) {  // a bucket: box and packed rows straight from HBM
-        for (int dd = 0; dd < d; ++dd) {
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
             float lo = INFINITY, hi = -INFINITY;
             for (int j = lane; j < c; j += kWave) {
                 float x = cols[(int64_t)dd * n + gs + j];
@@ -497,13 +624,14 @@ __global__ __launch_bounds__(kBlock) void k_finish(
             hi = wave_max(hi);
             if (lane == 0) {
                 tb[dd] = lo;
-                tb[d + dd] = hi;
+                tb[D + dd] = hi;
             }
         }
         for (int j = lane; j < c; j += kWave) {
-            const int64_t row = (gs + j) * (d + 1);
-            for (int dd = 0; dd < d; ++dd) pts[row + dd] = cols[(int64_t)dd * n + gs + j];
-            pts[row + d] = __int_as_float(gidx[gs + j]);
+            const int64_t row = (gs + j) * (D + 1);
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) pts[row + dd] = cols[(int64_t)dd * n + gs + j];
+            pts[row + D] = __int_as_float(gidx[gs + j]);
         }
         if (lane == 0) {
             NodeRec r;
@@ -519,15 +647,15 @@ __global__ __launch_bounds__(kBlock) void k_finish(
     }
 
     unsigned char* region = smem + (size_t)w * per_wave;
-    float* X = reinterpret_cast<float*>(region);                   // [d][W]
-    uint16_t* perm = reinterpret_cast<uint16_t*>(X + (size_t)d * W);  // [W]
-    float* sortbuf = reinterpret_cast<float*>(perm + W);            // [W] (also partition scratch)
-    uint16_t* tmp = reinterpret_cast<uint16_t*>(sortbuf);
-    int4* stack = reinterpret_cast<int4*>(sortbuf + W);             // [kStack]
+    float* X = reinterpret_cast<float*>(region);                    // [D][W]
+    uint16_t* pa = reinterpret_cast<uint16_t*>(X + (size_t)D * W);  // [W]
+    uint16_t* pb = pa + W;                                           // [W]
+    int4* stack = reinterpret_cast<int4*>(pb + W);                   // [kStack]
 
-    for (int dd = 0; dd < d; ++dd)
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd)
         for (int j = lane; j < c; j += kWave) X[dd * W + j] = cols[(int64_t)dd * n + gs + j];
-    for (int j = lane; j < c; j += kWave) perm[j] = (uint16_t)j;
+    for (int j = lane; j < c; j += kWave) pa[j] = (uint16_t)j;
     if (lane == 0) {
         stack[0] = make_int4(0, 0, c, 0);
         trec[0].parent = -1;
@@ -537,108 +665,168 @@ __global__ __launch_bounds__(kBlock) void k_finish(
     bool bad = false;
     while (sp > 0) {
         const int4 top = stack[--sp];
-        const int id = top.x, ls = top.y, lc = top.z, dep = top.w;
+        const int id = top.x, ls = top.y, lc = top.z;
+        const int dep = top.w & 0xffff, buf = top.w >> 16;
+        const uint16_t* pin = buf ? pb : pa;
+        uint16_t* pout = buf ? pa : pb;
         if (dep > maxdep) maxdep = dep;
-        // tight box of the node
-        for (int dd = 0; dd < d; ++dd) {
-            float lo = INFINITY, hi = -INFINITY;
-            for (int j = lane; j < lc; j += kWave) {
-                float x = X[dd * W + perm[ls + j]];
-                lo = fminf(lo, x);
-                hi = fmaxf(hi, x);
-            }
-            lo = wave_min(lo);
-            hi = wave_max(hi);
-            if (lane == 0) {
-                tb[(int64_t)id * D2 + dd] = lo;
-                tb[(int64_t)id * D2 + d + dd] = hi;
-            }
+        const int R = (lc + kWave - 1) / kWave;
+        int p[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int j = lane + kWave * r;
+            p[r] = (r < R && j < lc) ? pin[ls + j] : 0;
         }
-        bool make_leaf = lc <= leaf;
+        const bool small = lc <= leaf;
+        // box, and the FP64 variance of every dimension (all node points),
+        // DC dimensions at a time so their reductions overlap
+        constexpr int DC = D <= 3 ? D : 2;
+        float lo_d[D], hi_d[D];
+        double bestV = -1.0;
         int best = 0;
-        float split = 0.0f;
-        int nl = 0;
-        if (!make_leaf) {
-            // split dimension: FP64 variance of all node points (the sample)
-            double bestV = -1.0;
-            for (int dd = 0; dd < d; ++dd) {
-                double a[16], q[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    int j = lane + kWave * r;
-                    a[r] = j < lc ? (double)X[dd * W + perm[ls + j]] : 0.0;
-                }
-                double av[16];
+        for (int d0 = 0; d0 < D; d0 += DC) {
+            float v[DC][16];
+            float lo[DC], hi[DC];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) av[r] = a[r];
-                const double S = wave_psum(av);
+            for (int i = 0; i < DC; ++i) {
+                lo[i] = INFINITY;
+                hi[i] = -INFINITY;
+                if (d0 + i < D) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    int j = lane + kWave * r;
-                    double wv = (double)lc * a[r] - S;
-                    q[r] = j < lc ? wv * wv : 0.0;
-                }
-                const double V = wave_psum(q);
-                if (V > bestV) {
-                    bestV = V;
-                    best = dd;
+                    for (int r = 0; r < 16; ++r) {
+                        const int j = lane + kWave * r;
+                        const bool ok = r < R && j < lc;
+                        v[i][r] = ok ? X[(d0 + i) * W + p[r]] : 0.0f;
+                        if (ok) {
+                            lo[i] = fminf(lo[i], v[i][r]);
+                            hi[i] = fmaxf(hi[i], v[i][r]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) v[i][r] = 0.0f;
                 }
             }
-            if (!(bestV > 0.0)) make_leaf = true;  // all points coincide
+            wave_minmax<DC>(lo, hi);
+#pragma unroll
+            for (int i = 0; i < DC; ++i)
+                if (d0 + i < D) {
+                    lo_d[d0 + i] = lo[i];
+                    hi_d[d0 + i] = hi[i];
+                }
+            if (!small) {
+                double part[DC], S[DC], V[DC];
+                // v is zero where there is no point
+                lane_tree_n<DC>(R, [&](int i, int r) { return (double)v[i][r]; }, part);
+                wave_tree_n<DC>(part, S);
+                const double dlc = (double)lc;
+                lane_tree_n<DC>(
+                    R,
+                    [&](int i, int r) {
+                        const double wv = dlc * (double)v[i][r] - S[i];
+                        return (lane + kWave * r < lc) ? wv * wv : 0.0;
+                    },
+                    part);
+                wave_tree_n<DC>(part, V);
+#pragma unroll
+                for (int i = 0; i < DC; ++i)
+                    if (d0 + i < D && V[i] > bestV) {
+                        bestV = V[i];
+                        best = d0 + i;
+                    }
+            }
         }
-        if (make_leaf) {
+        if (lane == 0) {
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) {
+                tb[(int64_t)id * D2 + dd] = lo_d[dd];
+                tb[(int64_t)id * D2 + D + dd] = hi_d[dd];
+            }
+        }
+        if (small || !(bestV > 0.0)) {  // bucket (or identical points): final rows
             if (lane == 0) {
                 trec[id].a = (int32_t)(gs + ls);
                 trec[id].split = 0.0f;
                 trec[id].dim = -lc;
             }
-            wave_sync();
+            for (int j = lane; j < lc; j += kWave) {
+                const int q = pin[ls + j];
+                const int64_t row = (gs + ls + j) * (D + 1);
+#pragma unroll
+                for (int dd = 0; dd < D; ++dd) pts[row + dd] = X[dd * W + q];
+                pts[row + D] = __int_as_float(gidx[gs + q]);
+            }
             continue;
         }
-        // exact split: value of rank lc/2 or the next larger value, whichever
-        // count below is closer to half (ties to the smaller value)
-        int P = 1;
-        while (P < lc) P <<= 1;
-        for (int j = lane; j < P; j += kWave)
-            sortbuf[j] = j < lc ? X[best * W + perm[ls + j]] : INFINITY;
-        wave_sync();
-        wave_bitonic(sortbuf, P, lane);
-        const float vstar = sortbuf[lc / 2];
-        int r_lo = 0, r_hi = 0;
-        for (int j0 = 0; j0 < lc; j0 += kWave) {
-            int j = j0 + lane;
-            float x = j < lc ? sortbuf[j] : INFINITY;
-            r_lo += __popcll(__ballot(j < lc && x < vstar));
-            r_hi += __popcll(__ballot(j < lc && x <= vstar));
+        // rank floor(lc/2) of the best dimension by a bitwise search on keys
+        float v[16];
+        uint32_t key[16];
+        float blo = lo_d[0], bhi = hi_d[0];
+#pragma unroll
+        for (int dd = 1; dd < D; ++dd) {
+            blo = best == dd ? lo_d[dd] : blo;
+            bhi = best == dd ? hi_d[dd] : bhi;
         }
-        const float vnext = r_hi < lc ? sortbuf[r_hi] : vstar;
-        wave_sync();  // sortbuf is reused as partition scratch below
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int j = lane + kWave * r;
+            const bool ok = r < R && j < lc;
+            v[r] = ok ? X[best * W + p[r]] : 0.0f;
+            key[r] = ok ? float_key(v[r]) : 0xffffffffu;
+        }
+        const uint32_t kmin = float_key(blo), kmax = float_key(bhi);
+        const int m = lc >> 1;
+        const int hb = 31 - __clz(kmin ^ kmax);  // kmin != kmax because the variance is > 0
+        uint32_t ans = hb >= 31 ? 0u : (kmin & ~((2u << hb) - 1u));
+        for (int b = hb; b >= 0; --b) {
+            const uint32_t t = ans | ((1u << b) - 1u);
+            int cnt = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (r < R) cnt += __popcll(__ballot(lane + kWave * r < lc && key[r] <= t));
+            if (cnt <= m) ans |= 1u << b;
+        }
+        int r_lo = 0, r_hi = 0;
+        uint32_t kn = 0xffffffffu;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r < R) {
+                const bool ok = lane + kWave * r < lc;
+                r_lo += __popcll(__ballot(ok && key[r] < ans));
+                r_hi += __popcll(__ballot(ok && key[r] <= ans));
+                if (ok && key[r] > ans) kn = min(kn, key[r]);
+            }
+        }
+        kn = wave_min_u32(kn);
         const bool ok_star = r_lo > 0, ok_next = r_hi < lc;
+        float split;
+        int nl;
         if (ok_star && (!ok_next || (lc - 2 * r_lo) <= (2 * r_hi - lc))) {
-            split = vstar;
+            split = key_float(ans);
             nl = r_lo;
         } else {
-            split = vnext;
+            split = key_float(kn);
             nl = r_hi;
         }
-        // stable partition of perm[ls .. ls+lc)
-        int bl_run = 0, br_run = 0;
-        for (int j0 = 0; j0 < lc; j0 += kWave) {
-            const int j = j0 + lane;
-            const bool valid = j < lc;
-            const uint16_t p = valid ? perm[ls + j] : 0;
-            const bool f = valid && X[best * W + p] < split;
-            const uint64_t bl = __ballot(f), bv = __ballot(valid);
-            if (valid) {
-                int dst = f ? bl_run + (int)lanes_below(bl) : nl + br_run + (int)lanes_below(bv & ~bl);
-                tmp[dst] = p;
+        // stable partition into the other permutation array
+        int run_l = 0, run_r = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r < R) {
+                const bool ok = lane + kWave * r < lc;
+                const bool f = ok && v[r] < split;
+                const uint64_t bl = __ballot(f), bv = __ballot(ok);
+                if (ok) {
+                    const int dst = f ? ls + run_l + (int)lanes_below(bl)
+                                      : ls + nl + run_r + (int)lanes_below(bv & ~bl);
+                    pout[dst] = (uint16_t)p[r];
+                }
+                run_l += __popcll(bl);
+                run_r += __popcll(bv & ~bl);
             }
-            bl_run += __popcll(bl);
-            br_run += __popcll(bv & ~bl);
         }
-        wave_sync();
-        for (int j = lane; j < lc; j += kWave) perm[ls + j] = tmp[j];
-        const int L = nloc, R = nloc + 1;
+        const int L = nloc, Rc = nloc + 1;
         nloc += 2;
         if (e.depth0 + dep + 1 > max_depth || sp + 2 > kStack) bad = true;
         if (lane == 0) {
@@ -646,10 +834,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(
             trec[id].split = split;
             trec[id].dim = best;
             trec[L].parent = id;
-            trec[R].parent = id;
+            trec[Rc].parent = id;
             if (!bad) {
-                const int4 lft = make_int4(L, ls, nl, dep + 1);
-                const int4 rgt = make_int4(R, ls + nl, lc - nl, dep + 1);
+                const int wd = (dep + 1) | ((buf ^ 1) << 16);
+                const int4 lft = make_int4(L, ls, nl, wd);
+                const int4 rgt = make_int4(Rc, ls + nl, lc - nl, wd);
                 if (nl <= lc - nl) {  // smaller child next keeps the stack shallow
                     stack[sp] = rgt;
                     stack[sp + 1] = lft;
@@ -666,12 +855,6 @@ __global__ __launch_bounds__(kBlock) void k_finish(
     if (bad) {
         if (lane == 0) atomicExch(err, KNN_EDEPTH);
         return;
-    }
-    for (int j = lane; j < c; j += kWave) {
-        const int p = perm[j];
-        const int64_t row = (gs + j) * (d + 1);
-        for (int dd = 0; dd < d; ++dd) pts[row + dd] = X[dd * W + p];
-        pts[row + d] = __int_as_float(gidx[gs + p]);
     }
     if (lane == 0) {
         sub_nodes[sub] = nloc;
@@ -712,12 +895,16 @@ __global__ __launch_bounds__(kBlock) void k_compact(const SubEntry* __restrict__
     }
 }
 
-__global__ void k_bbox_up(const int32_t* __restrict__ ids, int32_t cnt,
-                          const NodeRec* __restrict__ nodes, float* __restrict__ bbox, int d)
+// Boxes of the level-pass nodes of one depth, whose ids form the range
+// rng[0] .. rng[1]: union of the two children's boxes.  Run from the deepest
+// level up; subtree roots in the range already hold their box (recomputing
+// it from their children gives the same tight box).
+__global__ void k_bbox_up(const int32_t* __restrict__ rng, const NodeRec* __restrict__ nodes,
+                          float* __restrict__ bbox, int d)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int v = ids[i];
+    const int v = rng[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= rng[1]) return;
+    if (nodes[v].dim < 0) return;
     const int L = nodes[v].a;
     const int D2 = 2 * d;
     for (int t = 0; t < d; ++t) {
@@ -727,16 +914,216 @@ __global__ void k_bbox_up(const int32_t* __restrict__ ids, int32_t cnt,
     }
 }
 
-struct LevelNode {
-    int32_t start, count, id, parent, depth;
+// ---------------------------------------------------------------------------
+// B7: level bookkeeping on the device (one block)
+// ---------------------------------------------------------------------------
+constexpr int kPlanBlock = 1024;
+constexpr int kPlanVals = 5;  // split nodes, level children, subtrees, blocks, histogram blocks
+
+// Exclusive scan of kPlanVals counters over the block; totals in tot.
+__device__ void plan_scan(const int (&v)[kPlanVals], int (&ex)[kPlanVals], int (&tot)[kPlanVals],
+                          int (*wsum)[kPlanVals])
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int x[kPlanVals];
+#pragma unroll
+    for (int k = 0; k < kPlanVals; ++k) x[k] = v[k];
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < kPlanVals; ++k) {
+            const int y = __shfl_up(x[k], o);
+            if (lane >= o) x[k] += y;
+        }
+    }
+    if (lane == 63)
+#pragma unroll
+        for (int k = 0; k < kPlanVals; ++k) wsum[w][k] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPlanVals; ++k) {
+        int base = 0, all = 0;
+        for (int i = 0; i < kPlanBlock / 64; ++i) {
+            if (i < w) base += wsum[i][k];
+            all += wsum[i][k];
+        }
+        ex[k] = base + x[k] - v[k];
+        tot[k] = all;
+    }
+    __syncthreads();
+}
+
+// From this level's split decisions: node records of the split nodes (their
+// children get consecutive ids, left then right, in level order), the next
+// level's node list and block tables (children above W points and above the
+// bucket size), and the subtree list entries (all other children, plus nodes
+// whose points all coincide).  Every position comes from a prefix sum, so
+// the result does not depend on thread timing.
+__global__ __launch_bounds__(kPlanBlock) void k_plan(
+    Level cur, Level nxt, const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
+    const int32_t* __restrict__ nleft, int leaf, int W, int max_depth, int nbuf,
+    NodeRec* __restrict__ big, SubEntry* __restrict__ subs, int32_t* __restrict__ g,
+    int32_t* __restrict__ rng, int level, int64_t big_cap, int64_t sub_cap, int64_t nn_cap,
+    int64_t nb_cap, int64_t nbh_cap)
+{
+    __shared__ int wsum[kPlanBlock / 64][kPlanVals];
+    const int t = threadIdx.x;
+    const int nn = cur.cnt[0];
+    const int base_id = g[G_NEXT_ID], base_sub = g[G_NSUB];
+    __syncthreads();  // every thread has read the counters before thread 0 updates them
+    int carry[kPlanVals] = {0, 0, 0, 0, 0};
+    bool overflow = false, too_deep = false;
+    for (int c0 = 0; c0 < nn; c0 += kPlanBlock) {
+        const int i = c0 + t;
+        const bool valid = i < nn;
+        int st = 0, cnt = 0, id = 0, par = -1, dep = 0, dm = -1, nl = 0;
+        float sp = 0.0f;
+        if (valid) {
+            st = cur.start[i];
+            cnt = cur.count[i];
+            id = cur.id[i];
+            par = cur.parent[i];
+            dep = cur.depth[i];
+            dm = dimv[i];
+            sp = splitv[i];
+            nl = nleft[i];
+        }
+        const bool is_split = valid && dm >= 0;
+        const int cs[2] = {st, st + nl}, cc[2] = {nl, cnt - nl};
+        bool lv[2] = {false, false};
+        int v[kPlanVals] = {0, 0, 0, 0, 0};
+        if (is_split) {
+            v[0] = 1;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                lv[k] = cc[k] > W && cc[k] > leaf;
+                if (lv[k]) {
+                    v[1] += 1;
+                    v[3] += (cc[k] + kChunk - 1) / kChunk;
+                    v[4] += (cc[k] + kHistChunk - 1) / kHistChunk;
+                } else {
+                    v[2] += 1;
+                }
+            }
+        } else if (valid) {
+            v[2] = 1;
+        }
+        int ex[kPlanVals], tot[kPlanVals];
+        plan_scan(v, ex, tot, wsum);
+        if (is_split) {
+            const int L = base_id + 2 * (carry[0] + ex[0]);
+            if (L + 1 >= big_cap) overflow = true;
+            else big[id] = NodeRec{L, par, sp, dm};
+            if (dep + 1 > max_depth) too_deep = true;
+            int pos = carry[1] + ex[1], b0 = carry[3] + ex[3], h0 = carry[4] + ex[4];
+            int sidx = base_sub + carry[2] + ex[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (lv[k]) {
+                    const int nb = (cc[k] + kChunk - 1) / kChunk;
+                    const int nbh = (cc[k] + kHistChunk - 1) / kHistChunk;
+                    if (pos >= nn_cap || b0 + nb > nb_cap || h0 + nbh > nbh_cap) {
+                        overflow = true;
+                    } else {
+                        nxt.start[pos] = cs[k];
+                        nxt.count[pos] = cc[k];
+                        nxt.id[pos] = L + k;
+                        nxt.parent[pos] = id;
+                        nxt.depth[pos] = dep + 1;
+                        nxt.blk0[pos] = b0;
+                        nxt.nblk[pos] = nb;
+                        for (int j = 0; j < nb; ++j) {
+                            nxt.bnode[b0 + j] = pos;
+                            nxt.bbeg[b0 + j] = j * kChunk;
+                        }
+                        for (int j = 0; j < nbh; ++j) {
+                            nxt.hnode[h0 + j] = pos;
+                            nxt.hbeg[h0 + j] = j * kHistChunk;
+                        }
+                    }
+                    ++pos;
+                    b0 += nb;
+                    h0 += nbh;
+                } else {
+                    if (sidx >= sub_cap) overflow = true;
+                    else subs[sidx] = SubEntry{cs[k], cc[k], L + k, id, nbuf, 0, dep + 1, 0};
+                    ++sidx;
+                }
+            }
+        } else if (valid) {  // all points identical: an oversized bucket
+            const int sidx = base_sub + carry[2] + ex[2];
+            if (sidx >= sub_cap) overflow = true;
+            else subs[sidx] = SubEntry{st, cnt, id, par, nbuf, 1, dep, 0};
+        }
+#pragma unroll
+        for (int k = 0; k < kPlanVals; ++k) carry[k] += tot[k];
+    }
+    if (overflow) atomicExch(&g[G_ERR], kErrOverflow);
+    if (too_deep) atomicCAS(&g[G_ERR], 0, KNN_EDEPTH);
+    if (t == 0) {
+        nxt.cnt[0] = carry[1];
+        nxt.cnt[1] = carry[3];
+        nxt.cnt[2] = carry[4];
+        g[G_NEXT_ID] = base_id + 2 * carry[0];
+        g[G_NSUB] = base_sub + carry[2];
+        rng[2 * (level + 1)] = base_id;
+        rng[2 * (level + 1) + 1] = base_id + 2 * carry[0];
+    }
+}
+
+// Device buffers of one Level with the given capacities.
+struct LevelMem {
+    DevBuf mem;
+    Level L{};
+    hipError_t alloc(int64_t nn_cap, int64_t nb_cap, int64_t nbh_cap)
+    {
+        const size_t ints = 7 * (size_t)nn_cap + 2 * (size_t)nb_cap + 2 * (size_t)nbh_cap + 4;
+        hipError_t e = mem.alloc(sizeof(int32_t) * ints);
+        if (e != hipSuccess) return e;
+        int32_t* p = mem.as<int32_t>();
+        L.start = p; p += nn_cap;
+        L.count = p; p += nn_cap;
+        L.id = p; p += nn_cap;
+        L.parent = p; p += nn_cap;
+        L.depth = p; p += nn_cap;
+        L.blk0 = p; p += nn_cap;
+        L.nblk = p; p += nn_cap;
+        L.bnode = p; p += nb_cap;
+        L.bbeg = p; p += nb_cap;
+        L.hnode = p; p += nbh_cap;
+        L.hbeg = p; p += nbh_cap;
+        L.cnt = p;
+        return hipSuccess;
+    }
 };
+
+using FinishFn = void (*)(const SubEntry*, int32_t, const float*, const int32_t*, const float*,
+                          const int32_t*, int64_t, int, int, int, size_t, float*, NodeRec*,
+                          float*, int32_t*, int32_t*, int32_t*);
+
+FinishFn finish_for(int d)
+{
+    switch (d) {
+#define KNN_DIM_CASE(DD) \
+    case DD:             \
+        return k_finish<DD>;
+        KNN_DIM_CASE(1) KNN_DIM_CASE(2) KNN_DIM_CASE(3) KNN_DIM_CASE(4)
+        KNN_DIM_CASE(5) KNN_DIM_CASE(6) KNN_DIM_CASE(7) KNN_DIM_CASE(8)
+        KNN_DIM_CASE(9) KNN_DIM_CASE(10) KNN_DIM_CASE(11) KNN_DIM_CASE(12)
+        KNN_DIM_CASE(13) KNN_DIM_CASE(14) KNN_DIM_CASE(15) KNN_DIM_CASE(16)
+#undef KNN_DIM_CASE
+    default:
+        return nullptr;
+    }
+}
+
+inline unsigned blocks_for(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
 
 }  // namespace
 
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w)
 {
-    // X [d][W] floats, perm [W] u16, sort/partition scratch [W] floats, stack
-    size_t b = (size_t)4 * d * w + (size_t)2 * w + (size_t)4 * w + sizeof(int4) * kStack;
+    // X [d][W] floats, two permutation arrays [W] u16, stack
+    size_t b = (size_t)4 * d * w + (size_t)4 * w + sizeof(int4) * kStack;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -753,168 +1140,162 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
 {
     prof_mark(st, 0);
     const int64_t nd = n * d;
-    DevBuf colsA, colsB, idxA, idxB, pts;
+    DevBuf colsA, colsB, idxA, idxB, pts, gbuf;
     KNN_HIP(colsA.alloc(sizeof(float) * nd));
     KNN_HIP(colsB.alloc(sizeof(float) * nd));
     KNN_HIP(idxA.alloc(sizeof(int32_t) * n));
     KNN_HIP(idxB.alloc(sizeof(int32_t) * n));
     KNN_HIP(pts.alloc(sizeof(float) * n * (d + 1)));
+    KNN_HIP(gbuf.alloc(sizeof(int32_t) * G_COUNT));
+    int32_t* g = gbuf.as<int32_t>();
     {
-        int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
+        const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
         k_ingest<<<(unsigned)blocks, kBlock, 0, st>>>(points, n, d, colsA.as<float>(),
                                                       idxA.as<int32_t>());
         KNN_HIP(hipGetLastError());
     }
     prof_mark(st, 1);
 
-    // ---- level passes -------------------------------------------------------
-    const int64_t nn_max = n / W + 1;
-    const int64_t nb_max = n / kChunk + nn_max + 1;
-    DevBuf lvbuf, dimv, splitv, nleft, samples, hist, wave_left, blk_off;
-    KNN_HIP(lvbuf.alloc(sizeof(int32_t) * (4 * nn_max + 2 * nb_max)));
-    KNN_HIP(dimv.alloc(sizeof(int32_t) * nn_max));
-    KNN_HIP(splitv.alloc(sizeof(float) * nn_max));
-    KNN_HIP(nleft.alloc(sizeof(int32_t) * nn_max));
-    KNN_HIP(samples.alloc(sizeof(float) * kSampleMax * nn_max));
-    KNN_HIP(hist.alloc(sizeof(uint32_t) * kBins * nn_max));
-    KNN_HIP(wave_left.alloc(sizeof(uint32_t) * kWavesPerBlock * nb_max));
-    KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_max));
-
-    std::vector<LevelNode> level, next;
-    std::vector<SubEntry> subs;
-    std::vector<NodeRec> big;          // records of level-pass nodes (by id)
-    std::vector<std::vector<int32_t>> inner_by_depth;
-    big.push_back(NodeRec{0, -1, 0.0f, 0});
-    int32_t next_id = 1;
-    // a node goes through the level passes only if it is both above the bucket
-    // size and too large for one wavefront's LDS
+    // ---- level passes: nodes above W points (and above the bucket size) -------
     auto needs_level = [&](int64_t c) { return c > W && c > leaf; };
+    // a level's nodes hold more than W points each and are disjoint
+    const int64_t nn_cap = n / (W + 1) + 1;
+    const int64_t nb_cap = n / kChunk + nn_cap + 1;
+    const int64_t nbh_cap = n / kHistChunk + nn_cap + 1;
+    const int64_t lv_cap = (int64_t)max_depth + 2;
+    // every level-pass node and subtree entry descends from a level node
+    const int64_t big_cap = 2 * nn_cap * lv_cap + 2;
+    const int64_t sub_cap = std::min<int64_t>(n, big_cap);
+    LevelMem lvA, lvB;
+    DevBuf dimv, splitv, nleft, samples, hist, wave_left, blk_off, d_big, d_subs, d_rng;
+    int32_t n_sub = 0, n_big = 1, n_levels = 0;
+    std::vector<int32_t> h_g(G_COUNT, 0);
     if (!needs_level(n)) {
-        subs.push_back(SubEntry{0, (int32_t)n, 0, -1, 0, 0, 0, 0});
+        const SubEntry root{0, (int32_t)n, 0, -1, 0, 0, 0, 0};
+        KNN_HIP(d_subs.alloc(sizeof(SubEntry)));
+        KNN_HIP(hipMemcpyAsync(d_subs.p, &root, sizeof(root), hipMemcpyHostToDevice, st));
+        KNN_HIP(d_big.alloc(sizeof(NodeRec)));
+        KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2));
+        n_sub = 1;
     } else {
-        level.push_back(LevelNode{0, (int32_t)n, 0, -1, 0});
-    }
-    int buf = 0;  // buffer holding the current level's points
-    std::vector<int32_t> hbuf;
-    std::vector<int32_t> h_dim;
-    std::vector<float> h_split;
-    std::vector<int32_t> h_nl;
-    while (!level.empty()) {
-        const int32_t nn = (int32_t)level.size();
-        if (level[0].depth + 1 > max_depth)
-            return fail(KNN_EDEPTH, "tree deeper than max_depth");
-        // block table: each node's points in chunks of kChunk
-        std::vector<int32_t> blk_node, blk_begin, node_blk0(nn), node_nblk(nn);
-        for (int32_t i = 0; i < nn; ++i) {
-            const int32_t nb = (int32_t)((level[i].count + kChunk - 1) / kChunk);
-            node_blk0[i] = (int32_t)blk_node.size();
-            node_nblk[i] = nb;
+        KNN_HIP(lvA.alloc(nn_cap, nb_cap, nbh_cap));
+        KNN_HIP(lvB.alloc(nn_cap, nb_cap, nbh_cap));
+        KNN_HIP(dimv.alloc(sizeof(int32_t) * nn_cap));
+        KNN_HIP(splitv.alloc(sizeof(float) * nn_cap));
+        KNN_HIP(nleft.alloc(sizeof(int32_t) * nn_cap));
+        KNN_HIP(samples.alloc(sizeof(float) * kSampleMax * nn_cap));
+        KNN_HIP(hist.alloc(sizeof(uint32_t) * kBins * nn_cap));
+        KNN_HIP(wave_left.alloc(sizeof(uint32_t) * kWavesPerBlock * nb_cap));
+        KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
+        KNN_HIP(d_big.alloc(sizeof(NodeRec) * big_cap));
+        KNN_HIP(d_subs.alloc(sizeof(SubEntry) * sub_cap));
+        KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2 * (lv_cap + 1)));
+        {   // level 0: the root and its block tables
+            const int32_t nb = (int32_t)((n + kChunk - 1) / kChunk);
+            const int32_t nbh = (int32_t)((n + kHistChunk - 1) / kHistChunk);
+            std::vector<int32_t> h(2 * (size_t)nb + 2 * (size_t)nbh);
             for (int32_t j = 0; j < nb; ++j) {
-                blk_node.push_back(i);
-                blk_begin.push_back(j * kChunk);
+                h[j] = 0;
+                h[nb + j] = j * kChunk;
+            }
+            for (int32_t j = 0; j < nbh; ++j) {
+                h[2 * nb + j] = 0;
+                h[2 * nb + nbh + j] = j * kHistChunk;
+            }
+            const int32_t node[7] = {0, (int32_t)n, 0, -1, 0, 0, nb};
+            const Level& L0 = lvA.L;
+            int32_t* dst[7] = {L0.start, L0.count, L0.id, L0.parent, L0.depth, L0.blk0, L0.nblk};
+            for (int f = 0; f < 7; ++f)
+                KNN_HIP(hipMemcpyAsync(dst[f], &node[f], sizeof(int32_t), hipMemcpyHostToDevice, st));
+            KNN_HIP(hipMemcpyAsync(L0.bnode, h.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+            KNN_HIP(hipMemcpyAsync(L0.bbeg, h.data() + nb, sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+            KNN_HIP(hipMemcpyAsync(L0.hnode, h.data() + 2 * nb, sizeof(int32_t) * nbh,
+                                   hipMemcpyHostToDevice, st));
+            KNN_HIP(hipMemcpyAsync(L0.hbeg, h.data() + 2 * nb + nbh, sizeof(int32_t) * nbh,
+                                   hipMemcpyHostToDevice, st));
+            const int32_t cnt[3] = {1, nb, nbh};
+            KNN_HIP(hipMemcpyAsync(L0.cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice, st));
+            const int32_t g0[G_COUNT] = {1, 0, 0, 0};
+            KNN_HIP(hipMemcpyAsync(g, g0, sizeof(g0), hipMemcpyHostToDevice, st));
+            const int32_t r0[2] = {0, 1};
+            KNN_HIP(hipMemcpyAsync(d_rng.p, r0, sizeof(r0), hipMemcpyHostToDevice, st));
+            KNN_HIP(hipStreamSynchronize(st));  // the host staging vectors die here
+        }
+        // levels expected for balanced splits; the host checks for more after that
+        int expected = 1;
+        for (int64_t c = n; needs_level(c); c = (c + 1) / 2) ++expected;
+        Level cur = lvA.L, nxt = lvB.L;
+        int buf = 0;
+        for (int level = 0;; ++level) {
+            if (level >= lv_cap) return fail(KNN_EDEPTH, "tree deeper than max_depth");
+            const int64_t nn_l = std::min<int64_t>(level < 40 ? (int64_t(1) << level) : nn_cap, nn_cap);
+            const unsigned g_nn = (unsigned)nn_l;
+            const unsigned g_nb = (unsigned)std::min<int64_t>(n / kChunk + nn_l + 1, nb_cap);
+            const unsigned g_nbh = (unsigned)std::min<int64_t>(n / kHistChunk + nn_l + 1, nbh_cap);
+            const float* src = (buf ? colsB : colsA).as<float>();
+            const int32_t* srci = (buf ? idxB : idxA).as<int32_t>();
+            float* dst = (buf ? colsA : colsB).as<float>();
+            int32_t* dsti = (buf ? idxA : idxB).as<int32_t>();
+            k_sample<<<g_nn, kBlock, 0, st>>>(cur, src, n, d, samples.as<float>(),
+                                              dimv.as<int32_t>(), hist.as<uint32_t>());
+            k_hist<<<g_nbh, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), samples.as<float>(), src, n,
+                                             hist.as<uint32_t>());
+            k_choose<<<g_nn, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), samples.as<float>(),
+                                              hist.as<uint32_t>(), src, n, d, splitv.as<float>());
+            k_count<<<g_nb, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), splitv.as<float>(), src, n,
+                                             wave_left.as<uint32_t>());
+            k_blkscan<<<g_nn, kBlock, 0, st>>>(cur, wave_left.as<uint32_t>(), blk_off.as<uint32_t>(),
+                                               nleft.as<int32_t>());
+            k_scatter<<<g_nb, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), splitv.as<float>(),
+                                               blk_off.as<uint32_t>(), wave_left.as<uint32_t>(),
+                                               nleft.as<int32_t>(), src, srci, dst, dsti, n, d);
+            k_plan<<<1, kPlanBlock, 0, st>>>(cur, nxt, dimv.as<int32_t>(), splitv.as<float>(),
+                                             nleft.as<int32_t>(), leaf, W, max_depth, buf ^ 1,
+                                             d_big.as<NodeRec>(), d_subs.as<SubEntry>(), g,
+                                             d_rng.as<int32_t>(), level, big_cap, sub_cap, nn_cap,
+                                             nb_cap, nbh_cap);
+            KNN_HIP(hipGetLastError());
+            n_levels = level + 2;  // depth ranges 0 .. level + 1 are recorded
+            std::swap(cur, nxt);
+            buf ^= 1;
+            if (level + 1 >= expected) {
+                int32_t h_nn = 0;
+                KNN_HIP(hipMemcpyAsync(&h_nn, cur.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                KNN_HIP(hipMemcpyAsync(h_g.data(), g, sizeof(int32_t) * G_COUNT,
+                                       hipMemcpyDeviceToHost, st));
+                KNN_HIP(hipStreamSynchronize(st));
+                if (h_g[G_ERR] == KNN_EDEPTH) return fail(KNN_EDEPTH, "tree deeper than max_depth");
+                if (h_g[G_ERR]) return fail(KNN_EDEVICE, "level bookkeeping overflowed its buffers");
+                if (h_nn == 0) break;
             }
         }
-        const int32_t nb = (int32_t)blk_node.size();
-        hbuf.assign(4 * (size_t)nn + 2 * (size_t)nb, 0);
-        for (int32_t i = 0; i < nn; ++i) {
-            hbuf[i] = level[i].start;
-            hbuf[nn + i] = level[i].count;
-            hbuf[2 * nn + i] = node_blk0[i];
-            hbuf[3 * nn + i] = node_nblk[i];
-        }
-        std::copy(blk_node.begin(), blk_node.end(), hbuf.begin() + 4 * nn);
-        std::copy(blk_begin.begin(), blk_begin.end(), hbuf.begin() + 4 * nn + nb);
-        KNN_HIP(hipMemcpyAsync(lvbuf.p, hbuf.data(), sizeof(int32_t) * hbuf.size(),
-                               hipMemcpyHostToDevice, st));
-        const int32_t* d_start = lvbuf.as<int32_t>();
-        const int32_t* d_count = d_start + nn;
-        const int32_t* d_blk0 = d_start + 2 * nn;
-        const int32_t* d_nblk = d_start + 3 * nn;
-        const int32_t* d_bnode = d_start + 4 * nn;
-        const int32_t* d_bbeg = d_bnode + nb;
-        const float* src = (buf ? colsB : colsA).as<float>();
-        const int32_t* srci = (buf ? idxB : idxA).as<int32_t>();
-        float* dst = (buf ? colsA : colsB).as<float>();
-        int32_t* dsti = (buf ? idxA : idxB).as<int32_t>();
-
-        k_sample<<<nn, kBlock, 0, st>>>(d_start, d_count, src, n, d, samples.as<float>(),
-                                        dimv.as<int32_t>());
-        KNN_HIP(hipMemsetAsync(hist.p, 0, sizeof(uint32_t) * kBins * (size_t)nn, st));
-        k_hist<<<nb, kBlock, 0, st>>>(d_bnode, d_bbeg, d_start, d_count, dimv.as<int32_t>(),
-                                      samples.as<float>(), src, n, hist.as<uint32_t>());
-        k_choose<<<nn, kBlock, 0, st>>>(d_start, d_count, dimv.as<int32_t>(),
-                                        samples.as<float>(), hist.as<uint32_t>(), src, n, d,
-                                        splitv.as<float>());
-        k_count<<<nb, kBlock, 0, st>>>(d_bnode, d_bbeg, d_start, d_count, dimv.as<int32_t>(),
-                                       splitv.as<float>(), src, n, wave_left.as<uint32_t>());
-        k_blkscan<<<nn, kBlock, 0, st>>>(d_blk0, d_nblk, wave_left.as<uint32_t>(),
-                                         blk_off.as<uint32_t>(), nleft.as<int32_t>());
-        k_scatter<<<nb, kBlock, 0, st>>>(d_bnode, d_bbeg, d_start, d_count, dimv.as<int32_t>(),
-                                         splitv.as<float>(), blk_off.as<uint32_t>(),
-                                         wave_left.as<uint32_t>(), nleft.as<int32_t>(), src,
-                                         srci, dst, dsti, n, d);
-        KNN_HIP(hipGetLastError());
-        h_dim.resize(nn);
-        h_split.resize(nn);
-        h_nl.resize(nn);
-        KNN_HIP(hipMemcpyAsync(h_dim.data(), dimv.p, sizeof(int32_t) * nn, hipMemcpyDeviceToHost, st));
-        KNN_HIP(hipMemcpyAsync(h_split.data(), splitv.p, sizeof(float) * nn, hipMemcpyDeviceToHost, st));
-        KNN_HIP(hipMemcpyAsync(h_nl.data(), nleft.p, sizeof(int32_t) * nn, hipMemcpyDeviceToHost, st));
-        KNN_HIP(hipStreamSynchronize(st));
-
-        next.clear();
-        const int nbuf = buf ^ 1;
-        for (int32_t i = 0; i < nn; ++i) {
-            const LevelNode& v = level[i];
-            if (h_dim[i] < 0) {  // identical points: an oversized bucket
-                subs.push_back(SubEntry{v.start, v.count, v.id, v.parent, nbuf, 1, v.depth, 0});
-                continue;
-            }
-            const int32_t nl = h_nl[i];
-            if (nl <= 0 || nl >= v.count)
-                return fail(KNN_EDEVICE, "level pass produced an empty child");
-            const int32_t L = next_id, R = next_id + 1;
-            next_id += 2;
-            if ((int64_t)next_id > 2 * n) return fail(KNN_EDEVICE, "node id overflow");
-            big.resize(next_id, NodeRec{0, -1, 0.0f, 0});
-            big[v.id] = NodeRec{L, v.parent, h_split[i], h_dim[i]};
-            if ((int)inner_by_depth.size() <= v.depth) inner_by_depth.resize(v.depth + 1);
-            inner_by_depth[v.depth].push_back(v.id);
-            const LevelNode kids[2] = {{v.start, nl, L, v.id, v.depth + 1},
-                                       {v.start + nl, v.count - nl, R, v.id, v.depth + 1}};
-            for (const LevelNode& ch : kids) {
-                if (needs_level(ch.count)) next.push_back(ch);
-                else subs.push_back(SubEntry{ch.start, ch.count, ch.id, ch.parent, nbuf, 0, ch.depth, 0});
-            }
-        }
-        level.swap(next);
-        buf = nbuf;
+        n_sub = h_g[G_NSUB];
+        n_big = h_g[G_NEXT_ID];
+        lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); wave_left.reset();
+        blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset();
     }
-    lvbuf.reset(); samples.reset(); hist.reset(); wave_left.reset(); blk_off.reset();
     prof_mark(st, 2);
 
     // ---- subtree finish -----------------------------------------------------
-    const int32_t n_sub = (int32_t)subs.size();
-    const int32_t n_big = next_id;
-    DevBuf d_subs, tnodes, tbox, subn, flags;
-    KNN_HIP(d_subs.alloc(sizeof(SubEntry) * n_sub));
+    DevBuf tnodes, tbox, subn, flags;
     KNN_HIP(tnodes.alloc(sizeof(NodeRec) * 2 * n));
     KNN_HIP(tbox.alloc(sizeof(float) * 2 * n * 2 * d));
     KNN_HIP(subn.alloc(sizeof(int32_t) * n_sub));
     KNN_HIP(flags.alloc(sizeof(int32_t) * 2));
-    KNN_HIP(hipMemcpyAsync(d_subs.p, subs.data(), sizeof(SubEntry) * n_sub, hipMemcpyHostToDevice, st));
     KNN_HIP(hipMemsetAsync(flags.p, 0, sizeof(int32_t) * 2, st));
     const size_t per_wave = finish_lds_bytes_per_wave(d, W);
     const size_t lds = per_wave * kWavesPerBlock;
     const int32_t fblocks = (n_sub + kWavesPerBlock - 1) / kWavesPerBlock;
+    FinishFn ff = finish_for(d);
+    if (!ff) return fail(KNN_EINVAL, "unsupported dimension");
     if (lds > 64 * 1024)
-        KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_finish),
+        KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ff),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    k_finish<<<fblocks, kBlock, lds, st>>>(
-        d_subs.as<SubEntry>(), n_sub, colsA.as<float>(), idxA.as<int32_t>(), colsB.as<float>(),
-        idxB.as<int32_t>(), n, d, leaf, W, max_depth, per_wave, pts.as<float>(),
-        tnodes.as<NodeRec>(), tbox.as<float>(), subn.as<int32_t>(), flags.as<int32_t>(),
-        flags.as<int32_t>() + 1);
+    hipLaunchKernelGGL(ff, dim3(fblocks), dim3(kBlock), lds, st, d_subs.as<SubEntry>(), n_sub,
+                       colsA.as<float>(), idxA.as<int32_t>(), colsB.as<float>(),
+                       idxB.as<int32_t>(), n, leaf, W, max_depth, per_wave, pts.as<float>(),
+                       tnodes.as<NodeRec>(), tbox.as<float>(), subn.as<int32_t>(),
+                       flags.as<int32_t>(), flags.as<int32_t>() + 1);
     KNN_HIP(hipGetLastError());
     std::vector<int32_t> h_subn(n_sub);
     int32_t h_flags[2] = {0, 0};
@@ -928,7 +1309,6 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     // ---- ids, records, boxes --------------------------------------------------
     std::vector<int32_t> h_base(n_sub);
     int64_t total = n_big;
-    int64_t leaves = 0;
     for (int32_t i = 0; i < n_sub; ++i) {
         h_base[i] = (int32_t)total;
         total += h_subn[i] - 1;
@@ -937,24 +1317,18 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     KNN_HIP(nodes.alloc(sizeof(NodeRec) * total));
     KNN_HIP(bbox.alloc(sizeof(float) * total * 2 * d));
     KNN_HIP(d_base.alloc(sizeof(int32_t) * n_sub));
-    KNN_HIP(hipMemcpyAsync(nodes.p, big.data(), sizeof(NodeRec) * n_big, hipMemcpyHostToDevice, st));
+    if (n_big > 1)
+        KNN_HIP(hipMemcpyAsync(nodes.p, d_big.p, sizeof(NodeRec) * n_big, hipMemcpyDeviceToDevice, st));
     KNN_HIP(hipMemcpyAsync(d_base.p, h_base.data(), sizeof(int32_t) * n_sub, hipMemcpyHostToDevice, st));
     k_compact<<<fblocks, kBlock, 0, st>>>(d_subs.as<SubEntry>(), n_sub, subn.as<int32_t>(),
                                           d_base.as<int32_t>(), tnodes.as<NodeRec>(),
                                           tbox.as<float>(), d, nodes.as<NodeRec>(),
                                           bbox.as<float>());
     KNN_HIP(hipGetLastError());
-    DevBuf d_ids;
-    size_t max_ids = 1;
-    for (auto& v : inner_by_depth) max_ids = std::max(max_ids, v.size());
-    KNN_HIP(d_ids.alloc(sizeof(int32_t) * max_ids));
-    for (int dep = (int)inner_by_depth.size() - 1; dep >= 0; --dep) {
-        const auto& ids = inner_by_depth[dep];
-        if (ids.empty()) continue;
-        KNN_HIP(hipMemcpyAsync(d_ids.p, ids.data(), sizeof(int32_t) * ids.size(),
-                               hipMemcpyHostToDevice, st));
-        k_bbox_up<<<(unsigned)((ids.size() + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-            d_ids.as<int32_t>(), (int32_t)ids.size(), nodes.as<NodeRec>(), bbox.as<float>(), d);
+    for (int dep = n_levels - 1; dep >= 0; --dep) {
+        const int64_t cap = std::min<int64_t>(dep < 40 ? (int64_t(1) << dep) : total, total);
+        k_bbox_up<<<blocks_for(cap, kBlock), kBlock, 0, st>>>(d_rng.as<int32_t>() + 2 * dep,
+                                                             nodes.as<NodeRec>(), bbox.as<float>(), d);
         KNN_HIP(hipGetLastError());
     }
     KNN_HIP(hipStreamSynchronize(st));
@@ -967,7 +1341,6 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     t->depth = h_flags[1];
     t->sub_pts = W;
     t->n_nodes = total;
-    (void)leaves;
     (void)hipGetDevice(&t->device);
     t->bytes = (int64_t)(pts.bytes + nodes.bytes + bbox.bytes);
     t->pts = pts.as<float>();

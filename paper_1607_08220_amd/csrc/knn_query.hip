@@ -182,21 +182,30 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             n_leaf += lcnt > 0;
             n_pts += lcnt;
         }
-        for (int j = 0; j < lcnt; ++j) {
-            float x[D + 1];
-            load_row<D>(pts + (int64_t)(lstart + j) * (D + 1), x);
-            float t0 = q[0] - x[0];
-            float acc = t0 * t0;
+        // bucket rows are loaded B at a time so that their latencies overlap
+        constexpr int B = D <= 4 ? 8 : 4;
+        for (int j0 = 0; j0 < lcnt; j0 += B) {
+            float x[B][D + 1];
 #pragma unroll
-            for (int t = 1; t < D; ++t) {
-                const float u = q[t] - x[t];
-                const float sq = u * u;
-                acc = acc + sq;
-            }
-            if (acc <= hd[KC - 1]) {
-                const int id = __float_as_int(x[D]);
-                if (id != self && key_less(acc, id, hd[KC - 1], hi[KC - 1]))
-                    heap_insert<KC>(hd, hi, acc, id);
+            for (int b = 0; b < B; ++b)
+                if (j0 + b < lcnt) load_row<D>(pts + (int64_t)(lstart + j0 + b) * (D + 1), x[b]);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (j0 + b < lcnt) {
+                    const float t0 = q[0] - x[b][0];
+                    float acc = t0 * t0;
+#pragma unroll
+                    for (int t = 1; t < D; ++t) {
+                        const float u = q[t] - x[b][t];
+                        const float sq = u * u;
+                        acc = acc + sq;
+                    }
+                    if (acc <= hd[KC - 1]) {
+                        const int id = __float_as_int(x[b][D]);
+                        if (id != self && key_less(acc, id, hd[KC - 1], hi[KC - 1]))
+                            heap_insert<KC>(hd, hi, acc, id);
+                    }
+                }
             }
         }
     }
