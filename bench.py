@@ -80,6 +80,8 @@ def main() -> int:
                     help="shrink n and m (debugging only; the reported workload is scale 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -106,6 +108,15 @@ def main() -> int:
     idx = torch.empty((m, k), dtype=torch.int32, device=dev)
     d2 = torch.empty((m, k), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
+
+    if args.calib_copy:  # a plain copy kernel of known size for HBM counter scaling
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 1 GiB read + 1 GiB written")
 
     knn.knn_set_profiling(True)
     trees = []

@@ -74,11 +74,15 @@ struct Level {
     int32_t* bbeg;
     int32_t* hnode;
     int32_t* hbeg;
+    int32_t* hblk0;
     int32_t* cnt;
 };
 
-// Build-wide device counters.
-enum { G_NEXT_ID = 0, G_NSUB = 1, G_ERR = 2, G_COUNT = 4 };
+// Build-wide device counters (the id and subtree counters before the
+// current level are kept in G_BASE_ID / G_BASE_SUB for the plan writes).
+enum { G_NEXT_ID = 0, G_NSUB = 1, G_ERR = 2, G_BASE_ID = 3, G_BASE_SUB = 4, G_COUNT = 8 };
+constexpr int kPlanVals = 5;  // split nodes, level children, subtrees, blocks, histogram blocks
+constexpr int kPlanStride = 8;
 constexpr int kErrOverflow = -100;
 
 __device__ inline void wave_sync()
@@ -238,9 +242,9 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
         float x[kHistIlp];
         int pos[kHistIlp];  // number of sample values <= x
 #pragma unroll
-        for (int u = 0; u < kHistIlp; ++u) {
+        for (int u = 0; u < kHistIlp; ++u) {  // unconditional loads, clamped in range
             const int64_t e = e0 + (int64_t)u * kBlock;
-            x[u] = e < end ? col[e] : 0.0f;
+            x[u] = col[e < end ? e : end - 1];
             pos[u] = 0;
         }
         for (int step = kSampleMax; step > 0; step >>= 1) {
@@ -402,9 +406,19 @@ __global__ __launch_bounds__(kBlock) void k_count(Level L, const int32_t* __rest
     if (lane == 0) wave_left[(int64_t)b * kWavesPerBlock + w] = cnt;
 }
 
+// Children of a split node that need another level pass: more than W
+// points and more than the bucket size.
+__device__ inline bool needs_level_pass(int c, int W, int leaf) { return c > W && c > leaf; }
+
+// Per-node exclusive scan of the block counts (the left count before each
+// block), the node's left count, and the node's plan counters: split (0/1),
+// children needing a level pass, subtree entries, and their blocks of kChunk
+// and kHistChunk points.
 __global__ __launch_bounds__(kBlock) void k_blkscan(Level L, const uint32_t* __restrict__ wave_left,
-                                                    uint32_t* __restrict__ blk_off,
-                                                    int32_t* __restrict__ n_left)
+                                                    const int32_t* __restrict__ dimv, int W,
+                                                    int leaf, uint32_t* __restrict__ blk_off,
+                                                    int32_t* __restrict__ n_left,
+                                                    int32_t* __restrict__ planv)
 {
     __shared__ uint32_t wsum[kWavesPerBlock];
     const int node = blockIdx.x, t = threadIdx.x;
@@ -422,47 +436,114 @@ __global__ __launch_bounds__(kBlock) void k_blkscan(Level L, const uint32_t* __r
         if (i < nb) blk_off[b0 + i] = carry + ex;
         carry += tot;
     }
-    if (t == 0) n_left[node] = (int32_t)carry;
+    if (t == 0) {
+        n_left[node] = (int32_t)carry;
+        int v[kPlanVals] = {0, 0, 0, 0, 0};
+        const int cnt = L.count[node];
+        if (dimv[node] >= 0) {
+            const int cc[2] = {(int)carry, cnt - (int)carry};
+            v[0] = 1;
+            for (int k = 0; k < 2; ++k) {
+                if (needs_level_pass(cc[k], W, leaf)) {
+                    v[1] += 1;
+                    v[3] += (cc[k] + kChunk - 1) / kChunk;
+                    v[4] += (cc[k] + kHistChunk - 1) / kHistChunk;
+                } else {
+                    v[2] += 1;
+                }
+            }
+        } else {
+            v[2] = 1;
+        }
+        for (int k = 0; k < kPlanVals; ++k) planv[(int64_t)node * kPlanStride + k] = v[k];
+    }
 }
 
+// The block's chunk of kChunk points is reordered in LDS so that every
+// column leaves as two contiguous runs (its left part, then its right part):
+// element e = 256 r + thread goes to slot rank(e) of the chunk's output.
 __global__ __launch_bounds__(kBlock) void k_scatter(
     Level L, const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
-    const uint32_t* __restrict__ blk_off, const uint32_t* __restrict__ wave_left,
-    const int32_t* __restrict__ n_left, const float* __restrict__ src_cols,
-    const int32_t* __restrict__ src_idx, float* __restrict__ dst_cols,
-    int32_t* __restrict__ dst_idx, int64_t n, int d)
+    const uint32_t* __restrict__ blk_off, const int32_t* __restrict__ n_left,
+    const float* __restrict__ src_cols, const int32_t* __restrict__ src_idx,
+    float* __restrict__ dst_cols, int32_t* __restrict__ dst_idx, int64_t n, int d)
 {
-    const int b = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int kR = kChunk / kBlock;  // 16 elements per thread
+    __shared__ uint16_t perm[kChunk];
+    __shared__ uint32_t stage[kChunk];
+    __shared__ uint32_t cnt[kR][kWavesPerBlock];
+    __shared__ uint32_t pre[kR * kWavesPerBlock + 1];
+    const int b = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
     if (b >= L.cnt[1]) return;
     const int node = L.bnode[b];
     const int64_t start = L.start[node], c = L.count[node];
     const int64_t beg = L.bbeg[b];
-    const int64_t end = beg + kChunk < c ? beg + kChunk : c;
-    const int64_t wb = beg + (int64_t)w * kWaveChunk;
-    const int64_t we = wb + kWaveChunk < end ? wb + kWaveChunk : end;
-    if (wb >= we) return;
-    int64_t lefts_before = blk_off[b];
-    for (int i = 0; i < w; ++i) lefts_before += wave_left[(int64_t)b * kWavesPerBlock + i];
+    const int len = (int)(beg + kChunk < c ? kChunk : c - beg);
     const int dim = dimv[node];
     const float split = splitv[node];
     const int64_t nl = n_left[node];
-    int64_t base_l = start + lefts_before;
-    int64_t base_r = start + nl + (wb - lefts_before);
-    const float* key = dim >= 0 ? src_cols + (int64_t)dim * n + start : nullptr;
-    for (int64_t e0 = wb; e0 < we; e0 += kWave) {
-        const int64_t e = e0 + lane;
-        const bool valid = e < we;
-        const bool f = valid && (dim < 0 || key[e] < split);
-        const uint64_t bl = __ballot(f), bv = __ballot(valid);
-        if (valid) {
-            const int64_t dst = f ? base_l + lanes_below(bl) : base_r + lanes_below(bv & ~bl);
-            const int64_t src = start + e;
-            for (int t = 0; t < d; ++t)
-                dst_cols[(int64_t)t * n + dst] = src_cols[(int64_t)t * n + src];
-            dst_idx[dst] = src_idx[src];
+    const int64_t lefts_before = blk_off[b];
+    const int64_t base_l = start + lefts_before;
+    const int64_t base_r = start + nl + (beg - lefts_before);
+    const int64_t src0 = start + beg;
+    // flags in element order e = 256 r + t; per (r, wave) ballot counts
+    uint64_t lmask[kR];
+    const float* key = src_cols + (int64_t)(dim >= 0 ? dim : 0) * n + src0;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int e = kBlock * r + t;
+        const bool ok = e < len;
+        const bool f = ok && (dim < 0 || key[e] < split);
+        lmask[r] = __ballot(f);
+        if (lane == 0) cnt[r][w] = (uint32_t)__popcll(lmask[r]);
+    }
+    __syncthreads();
+    // exclusive prefix of the 64 (r, wave) counts, in element order
+    if (w == 0) {
+        const uint32_t v = cnt[lane >> 2][lane & 3];
+        uint32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
         }
-        base_l += __popcll(bl);
-        base_r += __popcll(bv & ~bl);
+        pre[lane] = x - v;
+        if (lane == 63) pre[64] = x;
+    }
+    __syncthreads();
+    const uint32_t nl_chunk = pre[64];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const uint32_t before = pre[r * kWavesPerBlock + w];
+        const int e = kBlock * r + t;
+        if (e < len) {
+            const bool f = (lmask[r] >> lane) & 1;
+            const uint32_t lb = before + lanes_below(lmask[r]);  // lefts before e
+            const uint32_t slot = f ? lb : nl_chunk + (uint32_t)e - lb;
+            perm[slot] = (uint16_t)e;
+        }
+    }
+    __syncthreads();
+    // columns d .. 0 (d is the index column): stage, then write contiguous runs
+    for (int col = 0; col <= d; ++col) {
+        const uint32_t* srcw = col < d ? reinterpret_cast<const uint32_t*>(src_cols + (int64_t)col * n)
+                                       : reinterpret_cast<const uint32_t*>(src_idx);
+        uint32_t* dstw = col < d ? reinterpret_cast<uint32_t*>(dst_cols + (int64_t)col * n)
+                                 : reinterpret_cast<uint32_t*>(dst_idx);
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int e = kBlock * r + t;
+            if (e < len) stage[e] = srcw[src0 + e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int i = kBlock * r + t;
+            if (i < len) {
+                const int64_t dst = i < (int)nl_chunk ? base_l + i : base_r + (i - (int)nl_chunk);
+                dstw[dst] = stage[perm[i]];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -557,29 +638,263 @@ __device__ inline void wave_tree_n(double (&v)[N], double (&out)[N])
 }
 
 // Lane-local part of the pairwise tree (block_psum's order) for N sums:
-// element l + 64 r of sum i is val(i, r); registers r >= R are zeros, whose
-// additions are skipped (they would not change the sum).  The first level is
-// formed straight from the values so that only 8 partial sums are live.
-template <int N, class Val>
+// element l + 64 r of sum i is val(i, r), for r < RM; registers r >= R are
+// zeros, whose additions are skipped (they would not change the sum), and so
+// are the steps of the 1024-wide tree that pair registers at or above RM.
+// The first level is formed straight from the values.
+template <int N, int RM, class Val>
 __device__ inline void lane_tree_n(int R, Val val, double (&out)[N])
 {
-    double a[N][8];
+    if constexpr (RM == 1) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+        for (int i = 0; i < N; ++i) out[i] = val(i, 0);
+    } else {
+        constexpr int H = RM / 2;
+        double a[N][H];
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            a[i][r] = (r + 8 < R) ? val(i, r) + val(i, r + 8) : val(i, r);
+        for (int r = 0; r < H; ++r)
 #pragma unroll
-    for (int h = 4; h >= 1; h >>= 1) {
+            for (int i = 0; i < N; ++i)
+                a[i][r] = (r + H < R) ? val(i, r) + val(i, r + H) : val(i, r);
 #pragma unroll
-        for (int r = 0; r < h; ++r)
-            if (r + h < R) {
+        for (int h = H / 2; h >= 1; h >>= 1) {
 #pragma unroll
-                for (int i = 0; i < N; ++i) a[i][r] = a[i][r] + a[i][r + h];
+            for (int r = 0; r < h; ++r)
+                if (r + h < R) {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) a[i][r] = a[i][r] + a[i][r + h];
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = a[i][0];
+    }
+}
+
+// Registers per lane of the largest node a finish wavefront handles: the
+// subtree limit is 64 * kFinishMaxR<D> points (1024 up to 3 dimensions, 512
+// up to 8, else 256), which keeps the larger dimensions within the register
+// file.
+template <int D>
+constexpr int kFinishMaxR = D <= 3 ? 16 : (D <= 8 ? 8 : 4);
+
+// Context of one wavefront's subtree build.
+struct FinishCtx {
+    float* X;
+    uint16_t* pa;
+    uint16_t* pb;
+    int4* stack;
+    int W, leaf, max_depth, depth0;
+    int64_t gs;
+    NodeRec* trec;
+    float* tb;
+    float* pts;
+    const int32_t* gidx;
+    int lane;
+};
+
+// Process one node of RM or fewer registers per lane (lc <= 64 RM points):
+// its box, its split (or bucket rows), the stable partition, and the pushes
+// of its children.  Returns the number of stack entries written.
+template <int D, int RM>
+__device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep, int buf,
+                           int sp, int& nloc, bool& bad)
+{
+    constexpr int D2 = 2 * D;
+    float* X = cx.X;
+    uint16_t* pa = cx.pa;
+    uint16_t* pb = cx.pb;
+    int4* stack = cx.stack;
+    const int W = cx.W, leaf = cx.leaf, max_depth = cx.max_depth, lane = cx.lane;
+    const int64_t gs = cx.gs;
+    NodeRec* trec = cx.trec;
+    float* tb = cx.tb;
+    float* pts = cx.pts;
+    const int32_t* gidx = cx.gidx;
+    const int R = (lc + kWave - 1) / kWave;
+    const uint16_t* pin = buf ? pb : pa;
+    uint16_t* pout = buf ? pa : pb;
+    int p[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {  // unconditional LDS loads, clamped in range
+        const int j = lane + kWave * r;
+        const int q = pin[ls + (j < lc ? j : lc - 1)];
+        p[r] = (r < R && j < lc) ? q : 0;
+    }
+    const bool small = lc <= leaf;
+    // box, and the FP64 variance of every dimension (all node points),
+    // DC dimensions at a time so their reductions overlap
+    constexpr int DC = D <= 3 ? D : (D <= 8 ? 2 : 1);
+    float lo_d[D], hi_d[D];
+    double bestV = -1.0;
+    int best = 0;
+#pragma unroll
+    for (int d0 = 0; d0 < D; d0 += DC) {
+        float v[DC][RM];
+        float lo[DC], hi[DC];
+#pragma unroll
+        for (int i = 0; i < DC; ++i) {
+            lo[i] = INFINITY;
+            hi[i] = -INFINITY;
+            if (d0 + i < D) {
+#pragma unroll
+                for (int r = 0; r < RM; ++r) {
+                    const int j = lane + kWave * r;
+                    const bool ok = r < R && j < lc;
+                    const float xv = X[(d0 + i) * W + p[r]];  // p[r] = 0 past the end
+                    v[i][r] = ok ? xv : 0.0f;
+                    if (ok) {
+                        lo[i] = fminf(lo[i], v[i][r]);
+                        hi[i] = fmaxf(hi[i], v[i][r]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RM; ++r) v[i][r] = 0.0f;
             }
+        }
+        wave_minmax<DC>(lo, hi);
+#pragma unroll
+        for (int i = 0; i < DC; ++i)
+            if (d0 + i < D) {
+                lo_d[d0 + i] = lo[i];
+                hi_d[d0 + i] = hi[i];
+            }
+        if (!small) {
+            double part[DC], S[DC], V[DC];
+            // v is zero where there is no point
+            lane_tree_n<DC, RM>(R, [&](int i, int r) { return (double)v[i][r]; }, part);
+            wave_tree_n<DC>(part, S);
+            const double dlc = (double)lc;
+            lane_tree_n<DC, RM>(
+                R,
+                [&](int i, int r) {
+                    const double wv = dlc * (double)v[i][r] - S[i];
+                    return (lane + kWave * r < lc) ? wv * wv : 0.0;
+                },
+                part);
+            wave_tree_n<DC>(part, V);
+#pragma unroll
+            for (int i = 0; i < DC; ++i)
+                if (d0 + i < D && V[i] > bestV) {
+                    bestV = V[i];
+                    best = d0 + i;
+                }
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+            tb[(int64_t)id * D2 + dd] = lo_d[dd];
+            tb[(int64_t)id * D2 + D + dd] = hi_d[dd];
+        }
+    }
+    if (small || !(bestV > 0.0)) {  // bucket (or identical points): final rows
+        if (lane == 0) {
+            trec[id].a = (int32_t)(gs + ls);
+            trec[id].split = 0.0f;
+            trec[id].dim = -lc;
+        }
+        for (int j = lane; j < lc; j += kWave) {
+            const int q = pin[ls + j];
+            const int64_t row = (gs + ls + j) * (D + 1);
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) pts[row + dd] = X[dd * W + q];
+            pts[row + D] = __int_as_float(gidx[gs + q]);
+        }
+        return 0;
+    }
+    // rank floor(lc/2) of the best dimension by a bitwise search on keys
+    float v[RM];
+    uint32_t key[RM];
+    float blo = lo_d[0], bhi = hi_d[0];
+#pragma unroll
+    for (int dd = 1; dd < D; ++dd) {
+        blo = best == dd ? lo_d[dd] : blo;
+        bhi = best == dd ? hi_d[dd] : bhi;
     }
 #pragma unroll
-    for (int i = 0; i < N; ++i) out[i] = a[i][0];
+    for (int r = 0; r < RM; ++r) {
+        const int j = lane + kWave * r;
+        const bool ok = r < R && j < lc;
+        const float xv = X[best * W + p[r]];
+        v[r] = ok ? xv : 0.0f;
+        key[r] = ok ? float_key(v[r]) : 0xffffffffu;
+    }
+    const uint32_t kmin = float_key(blo), kmax = float_key(bhi);
+    const int m = lc >> 1;
+    const int hb = 31 - __clz(kmin ^ kmax);  // kmin != kmax because the variance is > 0
+    uint32_t ans = hb >= 31 ? 0u : (kmin & ~((2u << hb) - 1u));
+    for (int b = hb; b >= 0; --b) {
+        const uint32_t t = ans | ((1u << b) - 1u);
+        int cnt = 0;
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+            if (r < R) cnt += __popcll(__ballot(lane + kWave * r < lc && key[r] <= t));
+        if (cnt <= m) ans |= 1u << b;
+    }
+    int r_lo = 0, r_hi = 0;
+    uint32_t kn = 0xffffffffu;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        if (r < R) {
+            const bool ok = lane + kWave * r < lc;
+            r_lo += __popcll(__ballot(ok && key[r] < ans));
+            r_hi += __popcll(__ballot(ok && key[r] <= ans));
+            if (ok && key[r] > ans) kn = min(kn, key[r]);
+        }
+    }
+    kn = wave_min_u32(kn);
+    const bool ok_star = r_lo > 0, ok_next = r_hi < lc;
+    float split;
+    int nl;
+    if (ok_star && (!ok_next || (lc - 2 * r_lo) <= (2 * r_hi - lc))) {
+        split = key_float(ans);
+        nl = r_lo;
+    } else {
+        split = key_float(kn);
+        nl = r_hi;
+    }
+    // stable partition into the other permutation array
+    int run_l = 0, run_r = 0;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        if (r < R) {
+            const bool ok = lane + kWave * r < lc;
+            const bool f = ok && v[r] < split;
+            const uint64_t bl = __ballot(f), bv = __ballot(ok);
+            if (ok) {
+                const int dst = f ? ls + run_l + (int)lanes_below(bl)
+                                  : ls + nl + run_r + (int)lanes_below(bv & ~bl);
+                pout[dst] = (uint16_t)p[r];
+            }
+            run_l += __popcll(bl);
+            run_r += __popcll(bv & ~bl);
+        }
+    }
+    const int L = nloc, Rc = nloc + 1;
+    nloc += 2;
+    if (cx.depth0 + dep + 1 > max_depth || sp + 2 > kStack) bad = true;
+    if (lane == 0) {
+        trec[id].a = L;
+        trec[id].split = split;
+        trec[id].dim = best;
+        trec[L].parent = id;
+        trec[Rc].parent = id;
+        if (!bad) {
+            const int wd = (dep + 1) | ((buf ^ 1) << 16);
+            const int4 lft = make_int4(L, ls, nl, wd);
+            const int4 rgt = make_int4(Rc, ls + nl, lc - nl, wd);
+            if (nl <= lc - nl) {  // smaller child next keeps the stack shallow
+                stack[sp] = rgt;
+                stack[sp + 1] = lft;
+            } else {
+                stack[sp] = lft;
+                stack[sp + 1] = rgt;
+            }
+        }
+    }
+    wave_sync();
+    return bad ? 0 : 2;
 }
 
 // One wavefront builds the whole subtree of one node of at most W points in
@@ -667,190 +982,19 @@ __global__ __launch_bounds__(kBlock) void k_finish(
         const int4 top = stack[--sp];
         const int id = top.x, ls = top.y, lc = top.z;
         const int dep = top.w & 0xffff, buf = top.w >> 16;
-        const uint16_t* pin = buf ? pb : pa;
-        uint16_t* pout = buf ? pa : pb;
         if (dep > maxdep) maxdep = dep;
         const int R = (lc + kWave - 1) / kWave;
-        int p[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int j = lane + kWave * r;
-            p[r] = (r < R && j < lc) ? pin[ls + j] : 0;
-        }
-        const bool small = lc <= leaf;
-        // box, and the FP64 variance of every dimension (all node points),
-        // DC dimensions at a time so their reductions overlap
-        constexpr int DC = D <= 3 ? D : 2;
-        float lo_d[D], hi_d[D];
-        double bestV = -1.0;
-        int best = 0;
-#pragma unroll
-        for (int d0 = 0; d0 < D; d0 += DC) {
-            float v[DC][16];
-            float lo[DC], hi[DC];
-#pragma unroll
-            for (int i = 0; i < DC; ++i) {
-                lo[i] = INFINITY;
-                hi[i] = -INFINITY;
-                if (d0 + i < D) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int j = lane + kWave * r;
-                        const bool ok = r < R && j < lc;
-                        v[i][r] = ok ? X[(d0 + i) * W + p[r]] : 0.0f;
-                        if (ok) {
-                            lo[i] = fminf(lo[i], v[i][r]);
-                            hi[i] = fmaxf(hi[i], v[i][r]);
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) v[i][r] = 0.0f;
-                }
-            }
-            wave_minmax<DC>(lo, hi);
-#pragma unroll
-            for (int i = 0; i < DC; ++i)
-                if (d0 + i < D) {
-                    lo_d[d0 + i] = lo[i];
-                    hi_d[d0 + i] = hi[i];
-                }
-            if (!small) {
-                double part[DC], S[DC], V[DC];
-                // v is zero where there is no point
-                lane_tree_n<DC>(R, [&](int i, int r) { return (double)v[i][r]; }, part);
-                wave_tree_n<DC>(part, S);
-                const double dlc = (double)lc;
-                lane_tree_n<DC>(
-                    R,
-                    [&](int i, int r) {
-                        const double wv = dlc * (double)v[i][r] - S[i];
-                        return (lane + kWave * r < lc) ? wv * wv : 0.0;
-                    },
-                    part);
-                wave_tree_n<DC>(part, V);
-#pragma unroll
-                for (int i = 0; i < DC; ++i)
-                    if (d0 + i < D && V[i] > bestV) {
-                        bestV = V[i];
-                        best = d0 + i;
-                    }
-            }
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int dd = 0; dd < D; ++dd) {
-                tb[(int64_t)id * D2 + dd] = lo_d[dd];
-                tb[(int64_t)id * D2 + D + dd] = hi_d[dd];
-            }
-        }
-        if (small || !(bestV > 0.0)) {  // bucket (or identical points): final rows
-            if (lane == 0) {
-                trec[id].a = (int32_t)(gs + ls);
-                trec[id].split = 0.0f;
-                trec[id].dim = -lc;
-            }
-            for (int j = lane; j < lc; j += kWave) {
-                const int q = pin[ls + j];
-                const int64_t row = (gs + ls + j) * (D + 1);
-#pragma unroll
-                for (int dd = 0; dd < D; ++dd) pts[row + dd] = X[dd * W + q];
-                pts[row + D] = __int_as_float(gidx[gs + q]);
-            }
-            continue;
-        }
-        // rank floor(lc/2) of the best dimension by a bitwise search on keys
-        float v[16];
-        uint32_t key[16];
-        float blo = lo_d[0], bhi = hi_d[0];
-#pragma unroll
-        for (int dd = 1; dd < D; ++dd) {
-            blo = best == dd ? lo_d[dd] : blo;
-            bhi = best == dd ? hi_d[dd] : bhi;
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int j = lane + kWave * r;
-            const bool ok = r < R && j < lc;
-            v[r] = ok ? X[best * W + p[r]] : 0.0f;
-            key[r] = ok ? float_key(v[r]) : 0xffffffffu;
-        }
-        const uint32_t kmin = float_key(blo), kmax = float_key(bhi);
-        const int m = lc >> 1;
-        const int hb = 31 - __clz(kmin ^ kmax);  // kmin != kmax because the variance is > 0
-        uint32_t ans = hb >= 31 ? 0u : (kmin & ~((2u << hb) - 1u));
-        for (int b = hb; b >= 0; --b) {
-            const uint32_t t = ans | ((1u << b) - 1u);
-            int cnt = 0;
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (r < R) cnt += __popcll(__ballot(lane + kWave * r < lc && key[r] <= t));
-            if (cnt <= m) ans |= 1u << b;
-        }
-        int r_lo = 0, r_hi = 0;
-        uint32_t kn = 0xffffffffu;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if (r < R) {
-                const bool ok = lane + kWave * r < lc;
-                r_lo += __popcll(__ballot(ok && key[r] < ans));
-                r_hi += __popcll(__ballot(ok && key[r] <= ans));
-                if (ok && key[r] > ans) kn = min(kn, key[r]);
-            }
-        }
-        kn = wave_min_u32(kn);
-        const bool ok_star = r_lo > 0, ok_next = r_hi < lc;
-        float split;
-        int nl;
-        if (ok_star && (!ok_next || (lc - 2 * r_lo) <= (2 * r_hi - lc))) {
-            split = key_float(ans);
-            nl = r_lo;
-        } else {
-            split = key_float(kn);
-            nl = r_hi;
-        }
-        // stable partition into the other permutation array
-        int run_l = 0, run_r = 0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if (r < R) {
-                const bool ok = lane + kWave * r < lc;
-                const bool f = ok && v[r] < split;
-                const uint64_t bl = __ballot(f), bv = __ballot(ok);
-                if (ok) {
-                    const int dst = f ? ls + run_l + (int)lanes_below(bl)
-                                      : ls + nl + run_r + (int)lanes_below(bv & ~bl);
-                    pout[dst] = (uint16_t)p[r];
-                }
-                run_l += __popcll(bl);
-                run_r += __popcll(bv & ~bl);
-            }
-        }
-        const int L = nloc, Rc = nloc + 1;
-        nloc += 2;
-        if (e.depth0 + dep + 1 > max_depth || sp + 2 > kStack) bad = true;
-        if (lane == 0) {
-            trec[id].a = L;
-            trec[id].split = split;
-            trec[id].dim = best;
-            trec[L].parent = id;
-            trec[Rc].parent = id;
-            if (!bad) {
-                const int wd = (dep + 1) | ((buf ^ 1) << 16);
-                const int4 lft = make_int4(L, ls, nl, wd);
-                const int4 rgt = make_int4(Rc, ls + nl, lc - nl, wd);
-                if (nl <= lc - nl) {  // smaller child next keeps the stack shallow
-                    stack[sp] = rgt;
-                    stack[sp + 1] = lft;
-                } else {
-                    stack[sp] = lft;
-                    stack[sp + 1] = rgt;
-                }
-            }
-        }
-        wave_sync();
+        FinishCtx ctx{X, pa, pb, stack, W, leaf, max_depth, e.depth0, gs, trec, tb, pts, gidx, lane};
+        int pushed;
+        if (R <= 1) pushed = finish_node<D, 1>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
+        else if (R <= 2) pushed = finish_node<D, 2>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
+        else if (R <= 4 || kFinishMaxR<D> == 4)
+            pushed = finish_node<D, 4>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
+        else if (R <= 8 || kFinishMaxR<D> == 8)
+            pushed = finish_node<D, 8>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
+        else pushed = finish_node<D, kFinishMaxR<D>>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
         if (bad) break;
-        sp += 2;
+        sp += pushed;
     }
     if (bad) {
         if (lane == 0) atomicExch(err, KNN_EDEPTH);
@@ -915,19 +1059,31 @@ __global__ void k_bbox_up(const int32_t* __restrict__ rng, const NodeRec* __rest
 }
 
 // ---------------------------------------------------------------------------
-// B7: level bookkeeping on the device (one block)
+// B7: level bookkeeping on the device
 // ---------------------------------------------------------------------------
 constexpr int kPlanBlock = 1024;
-constexpr int kPlanVals = 5;  // split nodes, level children, subtrees, blocks, histogram blocks
 
-// Exclusive scan of kPlanVals counters over the block; totals in tot.
-__device__ void plan_scan(const int (&v)[kPlanVals], int (&ex)[kPlanVals], int (&tot)[kPlanVals],
-                          int (*wsum)[kPlanVals])
+// Exclusive scan over the level's nodes of the plan counters (planv ->
+// planx), by one block; the totals give the next level's sizes and advance
+// the id and subtree counters.  Every position comes from a prefix sum, so
+// ids and list order do not depend on thread timing.
+__global__ __launch_bounds__(kPlanBlock) void k_plan_scan(
+    Level cur, Level nxt, const int32_t* __restrict__ planv, int32_t* __restrict__ planx,
+    int32_t* __restrict__ g, int32_t* __restrict__ rng, int level, int64_t big_cap,
+    int64_t sub_cap, int64_t nn_cap, int64_t nb_cap, int64_t nbh_cap)
 {
+    __shared__ int wsum[kPlanBlock / 64][kPlanVals];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int nn = cur.cnt[0];
+    const int per = (nn + kPlanBlock - 1) / kPlanBlock;
+    const int i0 = t * per, i1 = min(nn, i0 + per);
+    int sum[kPlanVals] = {0, 0, 0, 0, 0};
+    for (int i = i0; i < i1; ++i)
+#pragma unroll
+        for (int k = 0; k < kPlanVals; ++k) sum[k] += planv[(int64_t)i * kPlanStride + k];
     int x[kPlanVals];
 #pragma unroll
-    for (int k = 0; k < kPlanVals; ++k) x[k] = v[k];
+    for (int k = 0; k < kPlanVals; ++k) x[k] = sum[k];
     for (int o = 1; o < 64; o <<= 1) {
 #pragma unroll
         for (int k = 0; k < kPlanVals; ++k) {
@@ -939,134 +1095,110 @@ __device__ void plan_scan(const int (&v)[kPlanVals], int (&ex)[kPlanVals], int (
 #pragma unroll
         for (int k = 0; k < kPlanVals; ++k) wsum[w][k] = x[k];
     __syncthreads();
+    int run[kPlanVals], tot[kPlanVals];
 #pragma unroll
     for (int k = 0; k < kPlanVals; ++k) {
         int base = 0, all = 0;
-        for (int i = 0; i < kPlanBlock / 64; ++i) {
-            if (i < w) base += wsum[i][k];
-            all += wsum[i][k];
+        for (int j = 0; j < kPlanBlock / 64; ++j) {
+            if (j < w) base += wsum[j][k];
+            all += wsum[j][k];
         }
-        ex[k] = base + x[k] - v[k];
+        run[k] = base + x[k] - sum[k];
         tot[k] = all;
     }
-    __syncthreads();
+    for (int i = i0; i < i1; ++i)
+#pragma unroll
+        for (int k = 0; k < kPlanVals; ++k) {
+            planx[(int64_t)i * kPlanStride + k] = run[k];
+            run[k] += planv[(int64_t)i * kPlanStride + k];
+        }
+    if (t == 0) {
+        const int base_id = g[G_NEXT_ID], base_sub = g[G_NSUB];
+        g[G_BASE_ID] = base_id;
+        g[G_BASE_SUB] = base_sub;
+        g[G_NEXT_ID] = base_id + 2 * tot[0];
+        g[G_NSUB] = base_sub + tot[2];
+        nxt.cnt[0] = tot[1];
+        nxt.cnt[1] = tot[3];
+        nxt.cnt[2] = tot[4];
+        rng[2 * (level + 1)] = base_id;
+        rng[2 * (level + 1) + 1] = base_id + 2 * tot[0];
+        if (base_id + 2 * (int64_t)tot[0] > big_cap || base_sub + (int64_t)tot[2] > sub_cap ||
+            tot[1] > nn_cap || tot[3] > nb_cap || tot[4] > nbh_cap) {
+            atomicExch(&g[G_ERR], kErrOverflow);
+            nxt.cnt[0] = nxt.cnt[1] = nxt.cnt[2] = 0;  // nothing more is written
+        }
+    }
 }
 
-// From this level's split decisions: node records of the split nodes (their
-// children get consecutive ids, left then right, in level order), the next
-// level's node list and block tables (children above W points and above the
-// bucket size), and the subtree list entries (all other children, plus nodes
-// whose points all coincide).  Every position comes from a prefix sum, so
-// the result does not depend on thread timing.
-__global__ __launch_bounds__(kPlanBlock) void k_plan(
+// One thread per node of the level: the split node's record (children get
+// ids L and L+1, L = base + 2 * (split nodes before it)), its children in
+// the next level's node list or in the subtree list, and nodes whose points
+// all coincide as oversized buckets.
+__global__ __launch_bounds__(kBlock) void k_plan_write(
     Level cur, Level nxt, const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
-    const int32_t* __restrict__ nleft, int leaf, int W, int max_depth, int nbuf,
-    NodeRec* __restrict__ big, SubEntry* __restrict__ subs, int32_t* __restrict__ g,
-    int32_t* __restrict__ rng, int level, int64_t big_cap, int64_t sub_cap, int64_t nn_cap,
-    int64_t nb_cap, int64_t nbh_cap)
+    const int32_t* __restrict__ nleft, const int32_t* __restrict__ planx, int leaf, int W,
+    int max_depth, int nbuf, NodeRec* __restrict__ big, SubEntry* __restrict__ subs,
+    int32_t* __restrict__ g)
 {
-    __shared__ int wsum[kPlanBlock / 64][kPlanVals];
-    const int t = threadIdx.x;
-    const int nn = cur.cnt[0];
-    const int base_id = g[G_NEXT_ID], base_sub = g[G_NSUB];
-    __syncthreads();  // every thread has read the counters before thread 0 updates them
-    int carry[kPlanVals] = {0, 0, 0, 0, 0};
-    bool overflow = false, too_deep = false;
-    for (int c0 = 0; c0 < nn; c0 += kPlanBlock) {
-        const int i = c0 + t;
-        const bool valid = i < nn;
-        int st = 0, cnt = 0, id = 0, par = -1, dep = 0, dm = -1, nl = 0;
-        float sp = 0.0f;
-        if (valid) {
-            st = cur.start[i];
-            cnt = cur.count[i];
-            id = cur.id[i];
-            par = cur.parent[i];
-            dep = cur.depth[i];
-            dm = dimv[i];
-            sp = splitv[i];
-            nl = nleft[i];
-        }
-        const bool is_split = valid && dm >= 0;
-        const int cs[2] = {st, st + nl}, cc[2] = {nl, cnt - nl};
-        bool lv[2] = {false, false};
-        int v[kPlanVals] = {0, 0, 0, 0, 0};
-        if (is_split) {
-            v[0] = 1;
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                lv[k] = cc[k] > W && cc[k] > leaf;
-                if (lv[k]) {
-                    v[1] += 1;
-                    v[3] += (cc[k] + kChunk - 1) / kChunk;
-                    v[4] += (cc[k] + kHistChunk - 1) / kHistChunk;
-                } else {
-                    v[2] += 1;
-                }
-            }
-        } else if (valid) {
-            v[2] = 1;
-        }
-        int ex[kPlanVals], tot[kPlanVals];
-        plan_scan(v, ex, tot, wsum);
-        if (is_split) {
-            const int L = base_id + 2 * (carry[0] + ex[0]);
-            if (L + 1 >= big_cap) overflow = true;
-            else big[id] = NodeRec{L, par, sp, dm};
-            if (dep + 1 > max_depth) too_deep = true;
-            int pos = carry[1] + ex[1], b0 = carry[3] + ex[3], h0 = carry[4] + ex[4];
-            int sidx = base_sub + carry[2] + ex[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                if (lv[k]) {
-                    const int nb = (cc[k] + kChunk - 1) / kChunk;
-                    const int nbh = (cc[k] + kHistChunk - 1) / kHistChunk;
-                    if (pos >= nn_cap || b0 + nb > nb_cap || h0 + nbh > nbh_cap) {
-                        overflow = true;
-                    } else {
-                        nxt.start[pos] = cs[k];
-                        nxt.count[pos] = cc[k];
-                        nxt.id[pos] = L + k;
-                        nxt.parent[pos] = id;
-                        nxt.depth[pos] = dep + 1;
-                        nxt.blk0[pos] = b0;
-                        nxt.nblk[pos] = nb;
-                        for (int j = 0; j < nb; ++j) {
-                            nxt.bnode[b0 + j] = pos;
-                            nxt.bbeg[b0 + j] = j * kChunk;
-                        }
-                        for (int j = 0; j < nbh; ++j) {
-                            nxt.hnode[h0 + j] = pos;
-                            nxt.hbeg[h0 + j] = j * kHistChunk;
-                        }
-                    }
-                    ++pos;
-                    b0 += nb;
-                    h0 += nbh;
-                } else {
-                    if (sidx >= sub_cap) overflow = true;
-                    else subs[sidx] = SubEntry{cs[k], cc[k], L + k, id, nbuf, 0, dep + 1, 0};
-                    ++sidx;
-                }
-            }
-        } else if (valid) {  // all points identical: an oversized bucket
-            const int sidx = base_sub + carry[2] + ex[2];
-            if (sidx >= sub_cap) overflow = true;
-            else subs[sidx] = SubEntry{st, cnt, id, par, nbuf, 1, dep, 0};
-        }
-#pragma unroll
-        for (int k = 0; k < kPlanVals; ++k) carry[k] += tot[k];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cur.cnt[0] || g[G_ERR] == kErrOverflow) return;
+    const int st = cur.start[i], cnt = cur.count[i], id = cur.id[i];
+    const int par = cur.parent[i], dep = cur.depth[i], dm = dimv[i];
+    const int* x = planx + (int64_t)i * kPlanStride;
+    const int base_id = g[G_BASE_ID], base_sub = g[G_BASE_SUB];
+    if (dm < 0) {  // all points identical: an oversized bucket
+        subs[base_sub + x[2]] = SubEntry{st, cnt, id, par, nbuf, 1, dep, 0};
+        return;
     }
-    if (overflow) atomicExch(&g[G_ERR], kErrOverflow);
-    if (too_deep) atomicCAS(&g[G_ERR], 0, KNN_EDEPTH);
-    if (t == 0) {
-        nxt.cnt[0] = carry[1];
-        nxt.cnt[1] = carry[3];
-        nxt.cnt[2] = carry[4];
-        g[G_NEXT_ID] = base_id + 2 * carry[0];
-        g[G_NSUB] = base_sub + carry[2];
-        rng[2 * (level + 1)] = base_id;
-        rng[2 * (level + 1) + 1] = base_id + 2 * carry[0];
+    const int nl = nleft[i];
+    const int L = base_id + 2 * x[0];
+    big[id] = NodeRec{L, par, splitv[i], dm};
+    if (dep + 1 > max_depth) atomicCAS(&g[G_ERR], 0, KNN_EDEPTH);
+    const int cs[2] = {st, st + nl}, cc[2] = {nl, cnt - nl};
+    int pos = x[1], b0 = x[3], h0 = x[4], sidx = base_sub + x[2];
+    for (int k = 0; k < 2; ++k) {
+        if (needs_level_pass(cc[k], W, leaf)) {
+            nxt.start[pos] = cs[k];
+            nxt.count[pos] = cc[k];
+            nxt.id[pos] = L + k;
+            nxt.parent[pos] = id;
+            nxt.depth[pos] = dep + 1;
+            nxt.blk0[pos] = b0;
+            nxt.nblk[pos] = (cc[k] + kChunk - 1) / kChunk;
+            nxt.hblk0[pos] = h0;
+            b0 += (cc[k] + kChunk - 1) / kChunk;
+            h0 += (cc[k] + kHistChunk - 1) / kHistChunk;
+            ++pos;
+        } else {
+            subs[sidx++] = SubEntry{cs[k], cc[k], L + k, id, nbuf, 0, dep + 1, 0};
+        }
+    }
+}
+
+// Block tables of the next level: block b belongs to the node whose first
+// block is the largest blk0 <= b (every node has at least one block).
+__global__ __launch_bounds__(kBlock) void k_plan_fill(Level nxt)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nn = nxt.cnt[0], nb = nxt.cnt[1], nbh = nxt.cnt[2];
+    for (int tab = 0; tab < 2; ++tab) {
+        const int lim = tab ? nbh : nb;
+        if (b >= lim) continue;
+        const int32_t* first = tab ? nxt.hblk0 : nxt.blk0;
+        int lo = 0, hi = nn - 1;  // largest pos with first[pos] <= b
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        if (tab) {
+            nxt.hnode[b] = lo;
+            nxt.hbeg[b] = (b - first[lo]) * kHistChunk;
+        } else {
+            nxt.bnode[b] = lo;
+            nxt.bbeg[b] = (b - first[lo]) * kChunk;
+        }
     }
 }
 
@@ -1074,9 +1206,10 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(
 struct LevelMem {
     DevBuf mem;
     Level L{};
+    explicit LevelMem(hipStream_t s) : mem(s) {}
     hipError_t alloc(int64_t nn_cap, int64_t nb_cap, int64_t nbh_cap)
     {
-        const size_t ints = 7 * (size_t)nn_cap + 2 * (size_t)nb_cap + 2 * (size_t)nbh_cap + 4;
+        const size_t ints = 8 * (size_t)nn_cap + 2 * (size_t)nb_cap + 2 * (size_t)nbh_cap + 4;
         hipError_t e = mem.alloc(sizeof(int32_t) * ints);
         if (e != hipSuccess) return e;
         int32_t* p = mem.as<int32_t>();
@@ -1091,6 +1224,7 @@ struct LevelMem {
         L.bbeg = p; p += nb_cap;
         L.hnode = p; p += nbh_cap;
         L.hbeg = p; p += nbh_cap;
+        L.hblk0 = p; p += nn_cap;
         L.cnt = p;
         return hipSuccess;
     }
@@ -1120,6 +1254,8 @@ inline unsigned blocks_for(int64_t items, int per) { return (unsigned)((items + 
 
 }  // namespace
 
+int32_t finish_max_points(int32_t d) { return d <= 3 ? 1024 : (d <= 8 ? 512 : 256); }
+
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w)
 {
     // X [d][W] floats, two permutation arrays [W] u16, stack
@@ -1139,8 +1275,16 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                int32_t W, hipStream_t st, knn_tree** out)
 {
     prof_mark(st, 0);
+    {   // let the pool keep build scratch between builds (up to 64 GiB)
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t keep = uint64_t(64) << 30;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
     const int64_t nd = n * d;
-    DevBuf colsA, colsB, idxA, idxB, pts, gbuf;
+    DevBuf colsA(st), colsB(st), idxA(st), idxB(st), pts, gbuf(st);
     KNN_HIP(colsA.alloc(sizeof(float) * nd));
     KNN_HIP(colsB.alloc(sizeof(float) * nd));
     KNN_HIP(idxA.alloc(sizeof(int32_t) * n));
@@ -1166,8 +1310,9 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     // every level-pass node and subtree entry descends from a level node
     const int64_t big_cap = 2 * nn_cap * lv_cap + 2;
     const int64_t sub_cap = std::min<int64_t>(n, big_cap);
-    LevelMem lvA, lvB;
-    DevBuf dimv, splitv, nleft, samples, hist, wave_left, blk_off, d_big, d_subs, d_rng;
+    LevelMem lvA(st), lvB(st);
+    DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), wave_left(st), blk_off(st),
+        d_big(st), d_subs(st), d_rng(st), planv(st), planx(st);
     int32_t n_sub = 0, n_big = 1, n_levels = 0;
     std::vector<int32_t> h_g(G_COUNT, 0);
     if (!needs_level(n)) {
@@ -1187,6 +1332,8 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(hist.alloc(sizeof(uint32_t) * kBins * nn_cap));
         KNN_HIP(wave_left.alloc(sizeof(uint32_t) * kWavesPerBlock * nb_cap));
         KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
+        KNN_HIP(planv.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
+        KNN_HIP(planx.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
         KNN_HIP(d_big.alloc(sizeof(NodeRec) * big_cap));
         KNN_HIP(d_subs.alloc(sizeof(SubEntry) * sub_cap));
         KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2 * (lv_cap + 1)));
@@ -1202,10 +1349,11 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                 h[2 * nb + j] = 0;
                 h[2 * nb + nbh + j] = j * kHistChunk;
             }
-            const int32_t node[7] = {0, (int32_t)n, 0, -1, 0, 0, nb};
+            const int32_t node[8] = {0, (int32_t)n, 0, -1, 0, 0, nb, 0};
             const Level& L0 = lvA.L;
-            int32_t* dst[7] = {L0.start, L0.count, L0.id, L0.parent, L0.depth, L0.blk0, L0.nblk};
-            for (int f = 0; f < 7; ++f)
+            int32_t* dst[8] = {L0.start, L0.count, L0.id, L0.parent, L0.depth, L0.blk0, L0.nblk,
+                               L0.hblk0};
+            for (int f = 0; f < 8; ++f)
                 KNN_HIP(hipMemcpyAsync(dst[f], &node[f], sizeof(int32_t), hipMemcpyHostToDevice, st));
             KNN_HIP(hipMemcpyAsync(L0.bnode, h.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
             KNN_HIP(hipMemcpyAsync(L0.bbeg, h.data() + nb, sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
@@ -1215,7 +1363,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                                    hipMemcpyHostToDevice, st));
             const int32_t cnt[3] = {1, nb, nbh};
             KNN_HIP(hipMemcpyAsync(L0.cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice, st));
-            const int32_t g0[G_COUNT] = {1, 0, 0, 0};
+            const int32_t g0[G_COUNT] = {1, 0, 0, 0, 0, 0, 0, 0};
             KNN_HIP(hipMemcpyAsync(g, g0, sizeof(g0), hipMemcpyHostToDevice, st));
             const int32_t r0[2] = {0, 1};
             KNN_HIP(hipMemcpyAsync(d_rng.p, r0, sizeof(r0), hipMemcpyHostToDevice, st));
@@ -1244,16 +1392,24 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                                               hist.as<uint32_t>(), src, n, d, splitv.as<float>());
             k_count<<<g_nb, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), splitv.as<float>(), src, n,
                                              wave_left.as<uint32_t>());
-            k_blkscan<<<g_nn, kBlock, 0, st>>>(cur, wave_left.as<uint32_t>(), blk_off.as<uint32_t>(),
-                                               nleft.as<int32_t>());
+            k_blkscan<<<g_nn, kBlock, 0, st>>>(cur, wave_left.as<uint32_t>(), dimv.as<int32_t>(), W,
+                                               leaf, blk_off.as<uint32_t>(), nleft.as<int32_t>(),
+                                               planv.as<int32_t>());
             k_scatter<<<g_nb, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), splitv.as<float>(),
-                                               blk_off.as<uint32_t>(), wave_left.as<uint32_t>(),
-                                               nleft.as<int32_t>(), src, srci, dst, dsti, n, d);
-            k_plan<<<1, kPlanBlock, 0, st>>>(cur, nxt, dimv.as<int32_t>(), splitv.as<float>(),
-                                             nleft.as<int32_t>(), leaf, W, max_depth, buf ^ 1,
-                                             d_big.as<NodeRec>(), d_subs.as<SubEntry>(), g,
-                                             d_rng.as<int32_t>(), level, big_cap, sub_cap, nn_cap,
-                                             nb_cap, nbh_cap);
+                                               blk_off.as<uint32_t>(), nleft.as<int32_t>(), src,
+                                               srci, dst, dsti, n, d);
+            k_plan_scan<<<1, kPlanBlock, 0, st>>>(cur, nxt, planv.as<int32_t>(), planx.as<int32_t>(),
+                                                  g, d_rng.as<int32_t>(), level, big_cap, sub_cap,
+                                                  nn_cap, nb_cap, nbh_cap);
+            k_plan_write<<<blocks_for(nn_l, kBlock), kBlock, 0, st>>>(
+                cur, nxt, dimv.as<int32_t>(), splitv.as<float>(), nleft.as<int32_t>(),
+                planx.as<int32_t>(), leaf, W, max_depth, buf ^ 1, d_big.as<NodeRec>(),
+                d_subs.as<SubEntry>(), g);
+            {
+                const int64_t nn_next = std::min<int64_t>(2 * nn_l, nn_cap);
+                const int64_t fill = std::min<int64_t>(n / kChunk + nn_next + 1, nb_cap);
+                k_plan_fill<<<blocks_for(fill, kBlock), kBlock, 0, st>>>(nxt);
+            }
             KNN_HIP(hipGetLastError());
             n_levels = level + 2;  // depth ranges 0 .. level + 1 are recorded
             std::swap(cur, nxt);
@@ -1272,12 +1428,12 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         n_sub = h_g[G_NSUB];
         n_big = h_g[G_NEXT_ID];
         lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); wave_left.reset();
-        blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset();
+        blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset(); planv.reset(); planx.reset();
     }
     prof_mark(st, 2);
 
     // ---- subtree finish -----------------------------------------------------
-    DevBuf tnodes, tbox, subn, flags;
+    DevBuf tnodes(st), tbox(st), subn(st), flags(st);
     KNN_HIP(tnodes.alloc(sizeof(NodeRec) * 2 * n));
     KNN_HIP(tbox.alloc(sizeof(float) * 2 * n * 2 * d));
     KNN_HIP(subn.alloc(sizeof(int32_t) * n_sub));
@@ -1313,7 +1469,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         h_base[i] = (int32_t)total;
         total += h_subn[i] - 1;
     }
-    DevBuf nodes, bbox, d_base;
+    DevBuf nodes, bbox, d_base(st);
     KNN_HIP(nodes.alloc(sizeof(NodeRec) * total));
     KNN_HIP(bbox.alloc(sizeof(float) * total * 2 * d));
     KNN_HIP(d_base.alloc(sizeof(int32_t) * n_sub));

@@ -58,21 +58,27 @@ int hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::knn::hip_fail(e_, #expr);   \
     } while (0)
 
-// Device buffer owned by a scope.
+// Device buffer owned by a scope.  With a stream it is scratch taken from
+// the device's stream-ordered pool (freed in stream order, kept by the pool
+// for the next build); without one it is a plain allocation.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    bool pooled = false;
     DevBuf() = default;
+    explicit DevBuf(hipStream_t s) : stream(s), pooled(true) {}
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { reset(); }
     hipError_t alloc(size_t b) {
         reset();
         bytes = b;
-        return b ? hipMalloc(&p, b) : hipSuccess;
+        if (!b) return hipSuccess;
+        return pooled ? hipMallocAsync(&p, b, stream) : hipMalloc(&p, b);
     }
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) (void)(pooled ? hipFreeAsync(p, stream) : hipFree(p));
         p = nullptr;
         bytes = 0;
     }
@@ -97,6 +103,7 @@ void prof_mark(hipStream_t s, int slot);
 
 // Largest subtree (points) one wavefront finishes in LDS for dimension d.
 int32_t default_subtree_points(int32_t d);
+int32_t finish_max_points(int32_t d);
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w);
 
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,

@@ -33,25 +33,43 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// q[dim] as a chain of selects.  The empty asm keeps the compiler from
+// turning the chain back into a dynamically indexed array (which it would
+// place in LDS).
 template <int D>
 __device__ inline float select_dim(const float (&q)[D], int dim)
 {
     float v = q[0];
 #pragma unroll
-    for (int t = 1; t < D; ++t) v = dim == t ? q[t] : v;
+    for (int t = 1; t < D; ++t) {
+        asm volatile("" : "+v"(v));
+        v = dim == t ? q[t] : v;
+    }
     return v;
 }
 
-// Sum over dimensions, left to right, of the squared offset of q from the
-// box [lo, hi]; <= the FP32 distance from q to every point in the box.
+// The node's box [lo, hi] (2D floats, 8-byte aligned), loaded without branches.
 template <int D>
-__device__ inline float box_bound(const float (&q)[D], const float* __restrict__ bb)
+__device__ inline void load_box(const float* __restrict__ bb, float (&b)[2 * D])
+{
+#pragma unroll
+    for (int t = 0; t < 2 * D; t += 2) {
+        const float2 v = *reinterpret_cast<const float2*>(bb + t);
+        b[t] = v.x;
+        b[t + 1] = v.y;
+    }
+}
+
+// Sum over dimensions, left to right, of the squared offset of q from the
+// box [lo, hi]: max(lo - q, q - hi, 0) per dimension.  Rounding is monotone,
+// so this is <= the FP32 distance from q to every point in the box.
+template <int D>
+__device__ inline float box_bound(const float (&q)[D], const float (&b)[2 * D])
 {
     float acc = 0.0f;
 #pragma unroll
     for (int t = 0; t < D; ++t) {
-        const float lo = bb[t], hi = bb[D + t];
-        const float o = q[t] < lo ? lo - q[t] : (q[t] > hi ? q[t] - hi : 0.0f);
+        const float o = fmaxf(fmaxf(b[t] - q[t], q[t] - b[D + t]), 0.0f);
         const float sq = o * o;
         acc = t == 0 ? sq : acc + sq;
     }
@@ -141,42 +159,53 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     }
     int cur = home ? home[slot] : 0;
     int from = -1;  // -1: arrived from the parent; otherwise the child we came from
+    // The record and box of `cur` are loaded at the end of the step that moves
+    // there, together, so one memory latency is exposed per step.
+    NodeRec r = nodes[cur];
+    float bb[2 * D];
+    load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
     while (cur >= 0) {
         int lstart = 0, lcnt = 0;
         while (cur >= 0) {
-            const NodeRec r = nodes[cur];
+            int next, nfrom;
+            bool scan = false;
             if (from < 0) {
                 if constexpr (STATS) ++n_enter;
-                const float b = box_bound<D>(q, bbox + (int64_t)cur * (2 * D));
+                const float b = box_bound<D>(q, bb);
                 if (b > hd[KC - 1]) {  // no point of this node can enter H
-                    from = cur;
-                    cur = r.parent;
-                    continue;
-                }
-                if (r.dim < 0) {  // leaf: scan it below, then return to the parent
+                    next = r.parent;
+                    nfrom = cur;
+                } else if (r.dim < 0) {  // leaf: scan it below, then return to the parent
                     lstart = r.a;
                     lcnt = -r.dim;
-                    from = cur;
-                    cur = r.parent;
-                    break;
+                    next = r.parent;
+                    nfrom = cur;
+                    scan = true;
+                } else {
+                    const float qd = select_dim<D>(q, r.dim);
+                    next = qd < r.split ? r.a : r.a + 1;  // near child first
+                    nfrom = -1;
                 }
-                const float qd = select_dim<D>(q, r.dim);
-                cur = qd < r.split ? r.a : r.a + 1;  // near child first
             } else {
                 const float qd = select_dim<D>(q, r.dim);
                 const bool left_near = qd < r.split;
                 const int near = left_near ? r.a : r.a + 1;
-                if (from == near) {
-                    const float o = left_near ? r.split - qd : qd - r.split;
-                    if (o * o <= hd[KC - 1]) {  // split-plane bound of the far child
-                        cur = left_near ? r.a + 1 : r.a;
-                        from = -1;
-                        continue;
-                    }
+                const float o = left_near ? r.split - qd : qd - r.split;
+                if (from == near && o * o <= hd[KC - 1]) {  // split-plane bound of the far child
+                    next = left_near ? r.a + 1 : r.a;
+                    nfrom = -1;
+                } else {
+                    next = r.parent;
+                    nfrom = cur;
                 }
-                from = cur;
-                cur = r.parent;
             }
+            cur = next;
+            from = nfrom;
+            if (cur >= 0) {
+                r = nodes[cur];
+                load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+            }
+            if (scan) break;
         }
         if constexpr (STATS) {
             n_leaf += lcnt > 0;
@@ -186,9 +215,13 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
         constexpr int B = D <= 4 ? 8 : 4;
         for (int j0 = 0; j0 < lcnt; j0 += B) {
             float x[B][D + 1];
+            // unconditional loads (the last row repeats past the end) so all B
+            // are in flight at once; only the arithmetic below is masked
 #pragma unroll
-            for (int b = 0; b < B; ++b)
-                if (j0 + b < lcnt) load_row<D>(pts + (int64_t)(lstart + j0 + b) * (D + 1), x[b]);
+            for (int b = 0; b < B; ++b) {
+                const int j = j0 + b < lcnt ? j0 + b : lcnt - 1;
+                load_row<D>(pts + (int64_t)(lstart + j) * (D + 1), x[b]);
+            }
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 if (j0 + b < lcnt) {
