@@ -49,6 +49,26 @@ def build_bytes_per_point(d: int, levels: int) -> float:
     return (4 * d + 4 * d + 4) + levels * (4 + 4 + 8 * (d + 1)) + (4 * (d + 1) + 4 * (d + 1))
 
 
+def partition_bytes_per_point(d: int) -> float:
+    """Algorithmic bytes the partition kernel moves per point: the split
+    coordinate read for the flags, then d coordinates + index read and written."""
+    return 4 + 8 * (d + 1)
+
+
+def measured_traffic(kernel_file: str, profile: str):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1607_08220_amd", "csrc", kernel_file), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(X: np.ndarray, k: int, log2n: int, m: int, threads: int) -> dict:
     import oracle
     rng = np.random.default_rng(7)
@@ -149,6 +169,9 @@ def main() -> int:
 
     mean = {kk: float(np.mean([p[kk] for p in phases])) for kk in phases[0]}
     build_ms, query_ms, trav_ms = mean["build_total"], mean["query_total"], mean["query_traverse"]
+    part_launches = mean["build_partition_launches"]
+    part_avg_ms = mean["build_partition_ms"] / part_launches
+    part_bytes = partition_bytes_per_point(d) * mean["build_partition_mpts"] * 1e6 / part_launches
 
     # visit counts of this traversal on this tree (untimed, instrumented run)
     stats = torch.zeros(3, dtype=torch.int64, device=dev)
@@ -195,18 +218,25 @@ def main() -> int:
                    "k": k, "leaf_size": w.leaf, "queries": "data points, self excluded",
                    "scale": args.scale},
         "build_mpts_per_s": n / (build_ms * 1e-3) / 1e6,
-        "phases_ms": mean,
+        "phases_ms": {kk: v for kk, v in mean.items() if not kk.startswith("build_partition")},
         "tree": {kk: info[kk] for kk in ("depth", "nodes", "leaves", "subtree_points",
                                          "device_bytes")},
         "visits_per_query": {"nodes_entered": enter, "leaves_scanned": leaves,
                              "points_scanned": pts},
         "roofline": {"kernel": "k_traverse", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_query": bpq},
-        "build_roofline": {"bound": "hbm", "bytes_per_point": bpp, "level_passes": levels,
-                           "achieved": bpp * n / (build_ms * 1e-3) / 1e9,
+                     "traffic": measured_traffic("knn_query.hip", "traffic_k_traverse_cosmo_clustered.json"),
+                     "bytes_per_launch": bpq * m, "bytes_per_query": bpq,
+                     "avg_launch_ms": trav_ms},
+        "build_roofline": {"kernel": "k_scatter", "bound": "hbm",
+                           "achieved": part_bytes / (part_avg_ms * 1e-3) / 1e9,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": bpp * n / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                           "frac": part_bytes / (part_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "traffic": measured_traffic("knn_build.hip", "traffic_k_scatter_cosmo_clustered.json"),
+                           "bytes_per_launch": part_bytes, "avg_launch_ms": part_avg_ms,
+                           "launches": part_launches,
+                           "whole_build_bytes_per_point": bpp, "level_passes": levels,
+                           "whole_build_frac": bpp * n / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "verified_sample": verified,
         "paper_context": "PANDA: 189e9 points built in 48 s and 19e9 queries in 12 s on "
                          "~50,000 Xeon cores (2048 nodes); single node (24 cores): "
@@ -217,8 +247,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
         log(f"timing the oracle on the host ({threads} threads)")
-        out["cpu_baseline"] = cpu_baseline(w.points, k, 22 if args.scale >= 1 else 16,
-                                           1 << 16 if args.scale >= 1 else 4096, threads)
+        out["cpu_baseline"] = cpu_baseline(w.points, k, 23 if args.scale >= 1 else 16,
+                                           1 << 21 if args.scale >= 1 else 4096, threads)
     print(json.dumps(out), flush=True)
     return 0
 

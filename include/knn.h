@@ -154,11 +154,13 @@ const char* knn_last_error(void);
 
 /* Per-phase device times of the most recent build and query on this thread,
  * in milliseconds, taken with HIP events on the call's stream while profiling
- * is enabled (knn_set_profiling(1)).  Phases:
+ * is enabled (knn_set_profiling(1)).  Slots:
  *   build: 0 ingest, 1 level passes (sample, histogram, split, partition),
  *          2 subtree finish in LDS, 3 node compaction and boxes, 4 total
- *   query: 5 locate home leaves, 6 group queries by leaf, 7 traversal, 8 total */
-#define KNN_PHASES 9
+ *   query: 5 locate home leaves, 6 group queries by leaf, 7 traversal, 8 total
+ *   build partition kernel: 9 summed duration of its launches (ms),
+ *          10 number of launches, 11 points it moved (millions) */
+#define KNN_PHASES 12
 int knn_set_profiling(int32_t enable);
 int knn_get_profile(float* ms_out /* [KNN_PHASES] */);
 

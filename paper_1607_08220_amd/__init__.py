@@ -21,9 +21,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libknn.so")
 
 KNN_OK, KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH = 0, -1, -2, -3, -4
-KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES = 16, 64, 9
+KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES = 16, 64, 12
 PHASES = ("build_ingest", "build_levels", "build_finish", "build_compact", "build_total",
-          "query_locate", "query_group", "query_traverse", "query_total")
+          "query_locate", "query_group", "query_traverse", "query_total",
+          "build_partition_ms", "build_partition_launches", "build_partition_mpts")
 
 
 class KnnError(RuntimeError):

@@ -55,6 +55,25 @@ void prof_mark(hipStream_t s, int slot)
     if (hipEventRecord(g_prof.ev[slot], s) == hipSuccess) g_prof.have[slot] = true;
 }
 
+void prof_part_begin()
+{
+    g_prof.part_used = 0;
+    g_prof.part_points = 0.0;
+}
+
+void prof_part_mark(hipStream_t s)
+{
+    if (!g_prof.on) return;
+    if (g_prof.part_used == (int)g_prof.part_ev.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        g_prof.part_ev.push_back(e);
+    }
+    if (hipEventRecord(g_prof.part_ev[g_prof.part_used], s) == hipSuccess) ++g_prof.part_used;
+}
+
+void prof_part_points(double points) { g_prof.part_points = points; }
+
 static int32_t pow2_floor(int32_t v)
 {
     int32_t p = 1;
@@ -227,9 +246,20 @@ int knn_get_profile(float* ms_out)
 {
     if (!ms_out) return fail(KNN_EINVAL, "NULL argument");
     // (phase, first event, last event)
-    static const int spans[KNN_PHASES][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {0, 4},
-                                             {5, 6}, {6, 7}, {7, 8}, {5, 8}};
-    for (int p = 0; p < KNN_PHASES; ++p) {
+    static const int spans[9][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {0, 4},
+                                    {5, 6}, {6, 7}, {7, 8}, {5, 8}};
+    float part = 0.0f;
+    const int pairs = g_prof.part_used / 2;
+    for (int i = 0; i < pairs; ++i) {
+        float ms = 0.0f;
+        KNN_HIP(hipEventSynchronize(g_prof.part_ev[2 * i + 1]));
+        KNN_HIP(hipEventElapsedTime(&ms, g_prof.part_ev[2 * i], g_prof.part_ev[2 * i + 1]));
+        part += ms;
+    }
+    ms_out[9] = pairs ? part : -1.0f;
+    ms_out[10] = (float)pairs;
+    ms_out[11] = (float)(g_prof.part_points / 1e6);
+    for (int p = 0; p < 9; ++p) {
         const int a = spans[p][0], b = spans[p][1];
         float ms = -1.0f;
         if (g_prof.have[a] && g_prof.have[b]) {

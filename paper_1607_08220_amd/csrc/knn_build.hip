@@ -80,7 +80,8 @@ struct Level {
 
 // Build-wide device counters (the id and subtree counters before the
 // current level are kept in G_BASE_ID / G_BASE_SUB for the plan writes).
-enum { G_NEXT_ID = 0, G_NSUB = 1, G_ERR = 2, G_BASE_ID = 3, G_BASE_SUB = 4, G_COUNT = 8 };
+enum { G_NEXT_ID = 0, G_NSUB = 1, G_ERR = 2, G_BASE_ID = 3, G_BASE_SUB = 4, G_MOVED = 6,
+       G_COUNT = 8 };  // G_MOVED: 64-bit count of points partitioned (slots 6-7)
 constexpr int kPlanVals = 5;  // split nodes, level children, subtrees, blocks, histogram blocks
 constexpr int kPlanStride = 8;
 constexpr int kErrOverflow = -100;
@@ -1078,9 +1079,14 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scan(
     const int per = (nn + kPlanBlock - 1) / kPlanBlock;
     const int i0 = t * per, i1 = min(nn, i0 + per);
     int sum[kPlanVals] = {0, 0, 0, 0, 0};
-    for (int i = i0; i < i1; ++i)
+    unsigned long long pts = 0;  // points this level partitions (profiling counter)
+    for (int i = i0; i < i1; ++i) {
 #pragma unroll
         for (int k = 0; k < kPlanVals; ++k) sum[k] += planv[(int64_t)i * kPlanStride + k];
+        pts += (unsigned long long)cur.count[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) pts += __shfl_xor(pts, o);
+    if (lane == 0 && pts) atomicAdd(reinterpret_cast<unsigned long long*>(g + G_MOVED), pts);
     int x[kPlanVals];
 #pragma unroll
     for (int k = 0; k < kPlanVals; ++k) x[k] = sum[k];
@@ -1275,6 +1281,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                int32_t W, hipStream_t st, knn_tree** out)
 {
     prof_mark(st, 0);
+    prof_part_begin();
     {   // let the pool keep build scratch between builds (up to 64 GiB)
         int dev = 0;
         hipMemPool_t pool;
@@ -1395,9 +1402,11 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
             k_blkscan<<<g_nn, kBlock, 0, st>>>(cur, wave_left.as<uint32_t>(), dimv.as<int32_t>(), W,
                                                leaf, blk_off.as<uint32_t>(), nleft.as<int32_t>(),
                                                planv.as<int32_t>());
+            prof_part_mark(st);
             k_scatter<<<g_nb, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), splitv.as<float>(),
                                                blk_off.as<uint32_t>(), nleft.as<int32_t>(), src,
                                                srci, dst, dsti, n, d);
+            prof_part_mark(st);
             k_plan_scan<<<1, kPlanBlock, 0, st>>>(cur, nxt, planv.as<int32_t>(), planx.as<int32_t>(),
                                                   g, d_rng.as<int32_t>(), level, big_cap, sub_cap,
                                                   nn_cap, nb_cap, nbh_cap);
@@ -1427,6 +1436,11 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         }
         n_sub = h_g[G_NSUB];
         n_big = h_g[G_NEXT_ID];
+        {
+            uint64_t moved = 0;
+            std::memcpy(&moved, &h_g[G_MOVED], sizeof(moved));
+            prof_part_points((double)moved);
+        }
         lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); wave_left.reset();
         blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset(); planv.reset(); planx.reset();
     }

@@ -96,10 +96,16 @@ struct Profiler {
     bool on = false;
     hipEvent_t ev[KNN_PHASES + 4] = {};
     bool have[KNN_PHASES + 4] = {};
-    float ms[KNN_PHASES] = {};
+    // events around each launch of the build's partition kernel
+    std::vector<hipEvent_t> part_ev;
+    int part_used = 0;
+    double part_points = 0.0;
 };
 Profiler& profiler();
 void prof_mark(hipStream_t s, int slot);
+void prof_part_begin();                 // start of a build
+void prof_part_mark(hipStream_t s);     // before / after one partition launch
+void prof_part_points(double points);   // points moved by the build's partition launches
 
 // Largest subtree (points) one wavefront finishes in LDS for dimension d.
 int32_t default_subtree_points(int32_t d);

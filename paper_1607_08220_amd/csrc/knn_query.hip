@@ -32,6 +32,7 @@ namespace knn {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
 // q[dim] as a chain of selects.  The empty asm keeps the compiler from
 // turning the chain back into a dynamically indexed array (which it would
@@ -131,19 +132,15 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     int32_t* __restrict__ out_idx, float* __restrict__ out_d2,
     unsigned long long* __restrict__ stats)
 {
-    const int64_t slot = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    // XCD-aware order: consecutive blocks are dispatched to the 8 XCDs in
+    // turn, so block b takes chunk (b % 8) * per + b / 8 -- each XCD then
+    // walks one contiguous range of the grouped queries and their leaves
+    // stay in its own L2.  The grid is a multiple of 8; extra blocks exit.
+    const int64_t per = gridDim.x / kXcds;
+    const int64_t blk = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int64_t slot = blk * blockDim.x + threadIdx.x;
     unsigned long long n_enter = 0, n_leaf = 0, n_pts = 0;
-    if (slot >= m) {
-        if constexpr (STATS) {
-            // take part in the wavefront sums below with zero counts
-            for (int o = 32; o > 0; o >>= 1) {
-                n_enter += __shfl_xor(n_enter, o);
-                n_leaf += __shfl_xor(n_leaf, o);
-                n_pts += __shfl_xor(n_pts, o);
-            }
-        }
-        return;
-    }
+    if (slot < m) {  // every lane meets the counter sums below
     const int64_t qid = order ? order[slot] : slot;
     float q[D];
 #pragma unroll
@@ -251,6 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             out_d2[o] = id < 0 ? INFINITY : hd[j];
         }
     }
+    }  // slot < m
     if constexpr (STATS) {
         for (int o = 32; o > 0; o >>= 1) {
             n_enter += __shfl_xor(n_enter, o);
@@ -265,11 +263,14 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     }
 }
 
-// Home leaf of every query: descend with the near-child rule (x < split left).
+// Home leaf of every query: descend with the near-child rule (x < split
+// left).  Queries are grouped by key = (first packed position of the home
+// leaf) >> shift: buckets are contiguous in packed order, so key order is the
+// tree's spatial order.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ nodes,
                                                    const float* __restrict__ queries, int64_t m,
-                                                   int32_t* __restrict__ home,
+                                                   int shift, int32_t* __restrict__ home,
                                                    uint32_t* __restrict__ cnt)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -284,18 +285,19 @@ __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ n
         r = nodes[cur];
     }
     home[i] = cur;
-    atomicAdd(&cnt[cur], 1u);
+    atomicAdd(&cnt[r.a >> shift], 1u);
 }
 
-__global__ __launch_bounds__(kBlock) void k_group(const int32_t* __restrict__ home, int64_t m,
-                                                  uint32_t* __restrict__ offs,
+__global__ __launch_bounds__(kBlock) void k_group(const NodeRec* __restrict__ nodes,
+                                                  const int32_t* __restrict__ home, int64_t m,
+                                                  int shift, uint32_t* __restrict__ offs,
                                                   int32_t* __restrict__ order,
                                                   int32_t* __restrict__ shome)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= m) return;
     const int h = home[i];
-    const uint32_t p = atomicAdd(&offs[h], 1u);
+    const uint32_t p = atomicAdd(&offs[nodes[h].a >> shift], 1u);
     order[p] = (int32_t)i;
     shome[p] = h;
 }
@@ -370,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t* __restrict__ a, i
 using TraverseFn = void (*)(const NodeRec*, const float*, const float*, const float*,
                             const int32_t*, const int32_t*, const int32_t*, int64_t, int, float,
                             int32_t*, float*, unsigned long long*);
-using LocateFn = void (*)(const NodeRec*, const float*, int64_t, int32_t*, uint32_t*);
+using LocateFn = void (*)(const NodeRec*, const float*, int64_t, int, int32_t*, uint32_t*);
 
 template <int D, bool STATS>
 TraverseFn pick_traverse(int k)
@@ -435,16 +437,20 @@ int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     if (!tf || !lf) return fail(KNN_EINVAL, "unsupported dimension");
     prof_mark(st, 5);
     const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
+    const unsigned tgrid = (unsigned)((grid + kXcds - 1) / kXcds * kXcds);  // multiple of 8
     if (order == 1) {
         prof_mark(st, 6);
         prof_mark(st, 7);
-        hipLaunchKernelGGL(tf, dim3(grid), dim3(kBlock), 0, st, t->nodes, t->bbox, t->pts,
+        hipLaunchKernelGGL(tf, dim3(tgrid), dim3(kBlock), 0, st, t->nodes, t->bbox, t->pts,
                            queries, nullptr, nullptr, self_ids, m, k, r2, out_idx, out_d2, stats);
         KNN_HIP(hipGetLastError());
         prof_mark(st, 8);
         return KNN_OK;
     }
-    const int64_t N = t->n_nodes;
+    // key range: packed positions >> shift, at most 2^22 buckets
+    int shift = 0;
+    while ((t->n >> shift) > (int64_t(1) << 22)) ++shift;
+    const int64_t N = (t->n >> shift) + 1;
     const int64_t nsb = (N + kScanChunk - 1) / kScanChunk;
     // workspace: home[m], order[m], shome[m], cnt[N], block sums[nsb]
     const size_t bytes = sizeof(int32_t) * 3 * (size_t)m + sizeof(uint32_t) * (size_t)(N + nsb);
@@ -457,16 +463,16 @@ int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     uint32_t* cnt = reinterpret_cast<uint32_t*>(shome + m);
     uint32_t* bsum = cnt + N;
     KNN_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * N, st));
-    hipLaunchKernelGGL(lf, dim3(grid), dim3(kBlock), 0, st, t->nodes, queries, m, home, cnt);
+    hipLaunchKernelGGL(lf, dim3(grid), dim3(kBlock), 0, st, t->nodes, queries, m, shift, home, cnt);
     KNN_HIP(hipGetLastError());
     prof_mark(st, 6);
     k_scan_local<<<(unsigned)nsb, kBlock, 0, st>>>(cnt, N, bsum);
     k_scan_sums<<<1, kBlock, 0, st>>>(bsum, nsb);
     k_scan_add<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N, bsum);
-    k_group<<<grid, kBlock, 0, st>>>(home, m, cnt, ord, shome);
+    k_group<<<grid, kBlock, 0, st>>>(t->nodes, home, m, shift, cnt, ord, shome);
     KNN_HIP(hipGetLastError());
     prof_mark(st, 7);
-    hipLaunchKernelGGL(tf, dim3(grid), dim3(kBlock), 0, st, t->nodes, t->bbox, t->pts, queries,
+    hipLaunchKernelGGL(tf, dim3(tgrid), dim3(kBlock), 0, st, t->nodes, t->bbox, t->pts, queries,
                        ord, shome, self_ids, m, k, r2, out_idx, out_d2, stats);
     KNN_HIP(hipGetLastError());
     prof_mark(st, 8);
