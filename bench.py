@@ -174,10 +174,13 @@ def main() -> int:
     part_bytes = partition_bytes_per_point(d) * mean["build_partition_mpts"] * 1e6 / part_launches
 
     # visit counts of this traversal on this tree (untimed, instrumented run)
-    stats = torch.zeros(3, dtype=torch.int64, device=dev)
+    stats = torch.zeros(knn.KNN_QUERY_STATS, dtype=torch.int64, device=dev)
     knn.knn_query_ex(trees[-1], Q, k, self_ids=S, stats=stats)
     torch.cuda.synchronize()
-    enter, leaves, pts = (stats.cpu().numpy() / m).tolist()
+    st = stats.cpu().numpy().astype(np.float64)
+    enter, leaves, pts, steps, ins = (st[:5] / m).tolist()
+    waves = (m + 63) // 64
+    w_steps, w_rows, w_rounds, w_ins = (st[5:9] / waves).tolist()
     bpq = query_bytes_per_query(d, k, enter, pts)
     achieved = bpq * m / (trav_ms * 1e-3) / 1e9
 
@@ -222,7 +225,10 @@ def main() -> int:
         "tree": {kk: info[kk] for kk in ("depth", "nodes", "leaves", "subtree_points",
                                          "device_bytes")},
         "visits_per_query": {"nodes_entered": enter, "leaves_scanned": leaves,
-                             "points_scanned": pts},
+                             "points_scanned": pts, "steps": steps, "heap_inserts": ins},
+        "per_wavefront": {"loop_iterations": w_steps, "row_batches": w_rows,
+                          "leaf_rounds": w_rounds, "heap_insert_runs": w_ins,
+                          "step_efficiency": steps * 64 / w_steps if w_steps else None},
         "roofline": {"kernel": "k_traverse", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("knn_query.hip", "traffic_k_traverse_cosmo_clustered.json"),

@@ -49,14 +49,22 @@ typedef struct {
                                wavefront in LDS (default: derived from dim, at most 1024) */
 } knn_build_params;
 
+#define KNN_QUERY_STATS 9
+
 /* Query parameters.  Zero selects the default. */
 typedef struct {
     int32_t order;  /* 0 (default): process queries grouped by the leaf that contains them;
                        1: process queries in input order */
-    int32_t pad_;
-    int64_t* stats; /* NULL, or a device pointer to 3 int64 counters the traversal adds to:
-                       nodes entered from above, leaves scanned, points scanned (the
-                       traversal counts of Section V-B2); slower, for measurement only */
+    int32_t leaf_batch; /* 1..64, 0 = default: a wavefront scans buckets once at least
+                           leaf_batch of every 64 of its unfinished lanes (one per query)
+                           hold one; a scheduling knob, the result does not depend on it */
+    int64_t* stats; /* NULL, or a device pointer to KNN_QUERY_STATS int64 counters the
+                       traversal adds to; slower, for measurement only.  Summed over
+                       queries: 0 nodes entered from above, 1 leaves scanned, 2 points
+                       scanned (the traversal counts of Section V-B2), 3 traversal
+                       steps, 4 heap inserts; summed over wavefronts (64 queries):
+                       5 traversal-loop iterations, 6 bucket-row batches, 7 leaf
+                       rounds, 8 heap-insert executions */
 } knn_query_params;
 
 typedef struct {

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libknn.so")
 
 KNN_OK, KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH = 0, -1, -2, -3, -4
-KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES = 16, 64, 12
+KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES, KNN_QUERY_STATS = 16, 64, 12, 9
 PHASES = ("build_ingest", "build_levels", "build_finish", "build_compact", "build_total",
           "query_locate", "query_group", "query_traverse", "query_total",
           "build_partition_ms", "build_partition_launches", "build_partition_mpts")
@@ -39,7 +39,7 @@ class _BuildParams(ctypes.Structure):
 
 
 class _QueryParams(ctypes.Structure):
-    _fields_ = [("order", ctypes.c_int32), ("pad_", ctypes.c_int32),
+    _fields_ = [("order", ctypes.c_int32), ("leaf_batch", ctypes.c_int32),
                 ("stats", ctypes.c_void_p)]
 
 
@@ -194,10 +194,10 @@ def knn_query(tree: Tree, queries, k: int, out=None):
 
 
 def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = math.inf,
-                 order: int = 0, out=None, stats=None):
+                 order: int = 0, out=None, stats=None, leaf_batch: int = 0):
     """knn_query with self exclusion (int32 [m], -1 = none), radius and order.
-    ``stats``: optional CUDA int64 [3] tensor the traversal adds its visit
-    counts to (nodes entered, leaves scanned, points scanned)."""
+    ``stats``: optional CUDA int64 [KNN_QUERY_STATS] tensor the traversal adds
+    its counters to (see knn_query_params in knn.h)."""
     import torch
     lib = load_library()
     _dev_f32(queries, "queries", tree.dim)
@@ -212,10 +212,11 @@ def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = mat
     st = None
     if stats is not None:
         if not (isinstance(stats, torch.Tensor) and stats.is_cuda and stats.dtype == torch.int64
-                and stats.numel() >= 3 and stats.is_contiguous()):
-            raise TypeError("stats must be a contiguous CUDA int64 tensor of 3 counters")
+                and stats.numel() >= KNN_QUERY_STATS and stats.is_contiguous()):
+            raise TypeError(f"stats must be a contiguous CUDA int64 tensor of "
+                            f"{KNN_QUERY_STATS} counters")
         st = stats.data_ptr()
-    p = _QueryParams(order, 0, st)
+    p = _QueryParams(order, leaf_batch, st)
     _check(lib.knn_query_ex(tree.handle, ctypes.c_void_p(queries.data_ptr()), queries.shape[0],
                             k, sp, ctypes.c_float(r2_max), ctypes.byref(p),
                             ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),

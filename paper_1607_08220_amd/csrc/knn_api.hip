@@ -143,10 +143,12 @@ int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     if (!queries || !out_idx || !out_dist2) return fail(KNN_EINVAL, "NULL query or output pointer");
     const int32_t order = p ? p->order : 0;
     if (order != 0 && order != 1) return fail(KNN_EINVAL, "order must be 0 or 1");
+    const int32_t batch = p && p->leaf_batch ? p->leaf_batch : kDefaultLeafBatch;
+    if (batch < 1 || batch > 64) return fail(KNN_EINVAL, "leaf_batch must be in [0, 64]");
     DeviceGuard g(t->device);
     unsigned long long* stats = p ? reinterpret_cast<unsigned long long*>(p->stats) : nullptr;
-    return query_tree(t, queries, m, k, self_ids, r2_max, order, out_idx, out_dist2, stats,
-                      static_cast<hipStream_t>(stream));
+    return query_tree(t, queries, m, k, self_ids, r2_max, order, batch, out_idx, out_dist2,
+                      stats, static_cast<hipStream_t>(stream));
 }
 
 int knn_query(const knn_tree* t, const float* queries, int64_t m, int32_t k, int32_t* out_idx,

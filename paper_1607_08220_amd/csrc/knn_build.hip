@@ -1296,7 +1296,8 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     KNN_HIP(colsB.alloc(sizeof(float) * nd));
     KNN_HIP(idxA.alloc(sizeof(int32_t) * n));
     KNN_HIP(idxB.alloc(sizeof(int32_t) * n));
-    KNN_HIP(pts.alloc(sizeof(float) * n * (d + 1)));
+    KNN_HIP(pts.alloc(sizeof(float) * (n + kRowPad) * (d + 1)));
+    KNN_HIP(hipMemsetAsync(pts.as<float>() + n * (d + 1), 0, sizeof(float) * kRowPad * (d + 1), st));
     KNN_HIP(gbuf.alloc(sizeof(int32_t) * G_COUNT));
     int32_t* g = gbuf.as<int32_t>();
     {

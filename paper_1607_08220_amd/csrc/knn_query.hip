@@ -17,12 +17,14 @@
 // scanned first, which tightens r' immediately (the near-first order of the
 // paper), and adjacent lanes walk nearly the same nodes, so loads coalesce.
 //
-// The heap H is a sorted register array of KC >= k entries; the lowest KC-k
-// slots hold (-inf) sentinels so the top k slots behave as a k-entry bounded
-// max-heap with its maximum in slot KC-1.  Empty slots hold (r2, -1): a point
-// enters iff (D, i) < (top D, top i), which for an empty slot means D < r2.
+// The heap H is a sorted register array of KC >= k keys (D, i); the lowest
+// KC-k slots hold the key 0, below every point, so the top k slots behave as
+// a k-entry bounded max-heap with its maximum in slot KC-1.  Empty slots hold
+// (r2, 0): a point enters iff (D, i) < the top key, which for an empty slot
+// means D < r2 (and for r2 <= 0, never).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -98,37 +100,92 @@ __device__ inline void load_row(const float* __restrict__ row, float (&x)[D + 1]
     }
 }
 
-__device__ inline bool key_less(float d, int i, float td, int ti)
+// 1 in the lowest-numbered active lane of the wavefront, else 0.
+__device__ inline unsigned first_active_lane()
 {
-    return d < td || (d == td && i < ti);
+    const unsigned long long ex = __builtin_amdgcn_read_exec();
+    return __lane_id() == (unsigned)__builtin_ctzll(ex);
 }
 
-template <int KC>
-__device__ inline void heap_insert(float (&hd)[KC], int (&hi)[KC], float D, int I)
+// FP32 squared distance: separate multiply and add, summed left to right.
+template <int D>
+__device__ inline float distance(const float (&q)[D], const float (&x)[D + 1])
 {
+    const float t0 = q[0] - x[0];
+    float acc = t0 * t0;
+#pragma unroll
+    for (int t = 1; t < D; ++t) {
+        const float u = q[t] - x[t];
+        const float sq = u * u;
+        acc = acc + sq;
+    }
+    return acc;
+}
+
+// Heap entries are 64-bit keys: the FP32 distance bits in the high word (a
+// non-negative float orders like its bit pattern) and the point index in the
+// low word, so unsigned key order is the (D, i) order.
+__device__ inline uint64_t make_key(float d, int i)
+{
+    return ((uint64_t)__float_as_uint(d) << 32) | (uint32_t)i;
+}
+
+__device__ inline float key_dist(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32)); }
+
+// Insert key into the ascending array h, dropping h[KC-1]; the caller has
+// checked key < h[KC-1].  Branch-free: one compare and two selects per slot.
+template <int KC>
+__device__ inline void heap_insert(uint64_t (&h)[KC], uint64_t key)
+{
+    bool below = true;  // key < h[p]
 #pragma unroll
     for (int p = KC - 1; p >= 1; --p) {
-        const bool below_prev = key_less(D, I, hd[p - 1], hi[p - 1]);
-        const bool below_cur = key_less(D, I, hd[p], hi[p]);
-        const float nd = below_prev ? hd[p - 1] : (below_cur ? D : hd[p]);
-        const int ni = below_prev ? hi[p - 1] : (below_cur ? I : hi[p]);
-        hd[p] = nd;
-        hi[p] = ni;
+        const bool below_prev = key < h[p - 1];
+        h[p] = below_prev ? h[p - 1] : (below ? key : h[p]);
+        below = below_prev;
     }
-    if (key_less(D, I, hd[0], hi[0])) {
-        hd[0] = D;
-        hi[0] = I;
-    }
+    h[0] = below ? key : h[0];
 }
 
-// STATS adds visit counters (nodes entered from above, leaves scanned, points
-// scanned) summed per wavefront into stats[0..2]; the timed kernel has none.
-template <int D, int KC, bool STATS>
+// True if the ball around q of squared radius thr lies strictly inside the
+// box [lo, hi]: per dimension m = min(q - lo, hi - q) > 0 and m*m > thr.  A
+// point x outside the box differs from q in some dimension by at least m, so
+// (rounding being monotone) its FP32 distance is >= fl(m*m) > thr and it
+// cannot enter H.
+template <int D>
+__device__ inline bool ball_inside(const float (&q)[D], const float (&b)[2 * D], float thr)
+{
+    bool in = true;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const float mt = fminf(q[t] - b[t], b[D + t] - q[t]);
+        in = in && mt > 0.0f && mt * mt > thr;
+    }
+    return in;
+}
+
+// STATS adds visit counters summed per wavefront into stats[0..8]: per lane
+// (nodes entered from above, leaves scanned, points scanned, traversal steps,
+// heap inserts) and per wavefront (traversal-loop iterations, bucket-row
+// batches, leaf rounds, heap-insert executions); the timed kernel has none.
+// The wavefront counts are taken by its first active lane, so their ratio to
+// the lane counts measures divergence.  RB bucket rows are loaded per batch.
+//
+// Lanes walk the tree until they reach a bucket to scan; a lane holding a
+// bucket pauses, and the wavefront scans once at least `batch` of every 64 of
+// its unfinished lanes hold one (or no lane can walk on).  Waiting for every
+// lane (batch = 64) leaves most lanes idle while the slowest one walks;
+// scanning for a single lane wastes the scan loop.  The result does not depend
+// on `batch`.
+//
+// A lane whose search ball lies inside the tight box of the node it is
+// leaving upwards stops: every point outside that box is farther than r'.
+template <int D, int KC, bool STATS, int RB>
 __global__ __launch_bounds__(kBlock) void k_traverse(
     const NodeRec* __restrict__ nodes, const float* __restrict__ bbox,
     const float* __restrict__ pts, const float* __restrict__ queries,
     const int32_t* __restrict__ order, const int32_t* __restrict__ home,
-    const int32_t* __restrict__ self_ids, int64_t m, int k, float r2,
+    const int32_t* __restrict__ self_ids, int64_t m, int k, float r2, int batch,
     int32_t* __restrict__ out_idx, float* __restrict__ out_d2,
     unsigned long long* __restrict__ stats)
 {
@@ -139,21 +196,19 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     const int64_t per = gridDim.x / kXcds;
     const int64_t blk = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
     const int64_t slot = blk * blockDim.x + threadIdx.x;
-    unsigned long long n_enter = 0, n_leaf = 0, n_pts = 0;
+    unsigned long long n_enter = 0, n_leaf = 0, n_pts = 0, n_step = 0, n_ins = 0;
+    unsigned long long w_step = 0, w_rows = 0, w_round = 0, w_ins = 0;
     if (slot < m) {  // every lane meets the counter sums below
     const int64_t qid = order ? order[slot] : slot;
     float q[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) q[t] = queries[qid * D + t];
     const int32_t self = self_ids ? self_ids[qid] : -1;
-    float hd[KC];
-    int hi[KC];
+    uint64_t h[KC];
     const int pad = KC - k;
+    const uint64_t empty = r2 > 0.0f ? make_key(r2, 0) : 0;
 #pragma unroll
-    for (int j = 0; j < KC; ++j) {
-        hd[j] = j < pad ? -INFINITY : r2;
-        hi[j] = j < pad ? INT_MIN : -1;
-    }
+    for (int j = 0; j < KC; ++j) h[j] = j < pad ? 0 : empty;
     int cur = home ? home[slot] : 0;
     int from = -1;  // -1: arrived from the parent; otherwise the child we came from
     // The record and box of `cur` are loaded at the end of the step that moves
@@ -161,104 +216,144 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     NodeRec r = nodes[cur];
     float bb[2 * D];
     load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
-    while (cur >= 0) {
-        int lstart = 0, lcnt = 0;
-        while (cur >= 0) {
-            int next, nfrom;
-            bool scan = false;
-            if (from < 0) {
-                if constexpr (STATS) ++n_enter;
-                const float b = box_bound<D>(q, bb);
-                if (b > hd[KC - 1]) {  // no point of this node can enter H
-                    next = r.parent;
-                    nfrom = cur;
-                } else if (r.dim < 0) {  // leaf: scan it below, then return to the parent
-                    lstart = r.a;
-                    lcnt = -r.dim;
-                    next = r.parent;
-                    nfrom = cur;
-                    scan = true;
+    int lstart = 0, lcnt = 0;  // the bucket waiting to be scanned (lcnt > 0)
+    while (true) {
+        if constexpr (STATS) w_round += first_active_lane();
+        while (true) {
+            const bool walking = cur >= 0 && lcnt == 0;
+            const unsigned long long wb = __ballot(walking);
+            if (wb == 0) break;
+            const int held = __popcll(__ballot(lcnt > 0));
+            if (held * 64 >= batch * (held + __popcll(wb))) break;
+            if (walking) {
+                if constexpr (STATS) {
+                    ++n_step;
+                    w_step += first_active_lane();
+                }
+                const float thr = key_dist(h[KC - 1]);
+                int next, nfrom;
+                if (from < 0) {
+                    if constexpr (STATS) ++n_enter;
+                    const float b = box_bound<D>(q, bb);
+                    if (b > thr) {  // no point of this node can enter H
+                        next = r.parent;
+                        nfrom = cur;
+                    } else if (r.dim < 0) {  // leaf: scan it, then return to the parent
+                        lstart = r.a;
+                        lcnt = -r.dim;
+                        next = ball_inside<D>(q, bb, thr) ? -1 : r.parent;
+                        nfrom = cur;
+                    } else {
+                        const float qd = select_dim<D>(q, r.dim);
+                        next = qd < r.split ? r.a : r.a + 1;  // near child first
+                        nfrom = -1;
+                    }
                 } else {
                     const float qd = select_dim<D>(q, r.dim);
-                    next = qd < r.split ? r.a : r.a + 1;  // near child first
-                    nfrom = -1;
+                    const bool left_near = qd < r.split;
+                    const int near = left_near ? r.a : r.a + 1;
+                    const float o = left_near ? r.split - qd : qd - r.split;
+                    if (from == near && o * o <= thr) {  // split-plane bound of the far child
+                        next = left_near ? r.a + 1 : r.a;
+                        nfrom = -1;
+                    } else {
+                        next = ball_inside<D>(q, bb, thr) ? -1 : r.parent;
+                        nfrom = cur;
+                    }
                 }
-            } else {
-                const float qd = select_dim<D>(q, r.dim);
-                const bool left_near = qd < r.split;
-                const int near = left_near ? r.a : r.a + 1;
-                const float o = left_near ? r.split - qd : qd - r.split;
-                if (from == near && o * o <= hd[KC - 1]) {  // split-plane bound of the far child
-                    next = left_near ? r.a + 1 : r.a;
-                    nfrom = -1;
-                } else {
-                    next = r.parent;
-                    nfrom = cur;
+                cur = next;
+                from = nfrom;
+                if (cur >= 0) {
+                    r = nodes[cur];
+                    load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
                 }
             }
-            cur = next;
-            from = nfrom;
-            if (cur >= 0) {
-                r = nodes[cur];
-                load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
-            }
-            if (scan) break;
         }
+        if (__ballot(lcnt > 0) == 0) break;  // no lane walks and none holds a bucket
         if constexpr (STATS) {
             n_leaf += lcnt > 0;
             n_pts += lcnt;
         }
-        // bucket rows are loaded B at a time so that their latencies overlap
-        constexpr int B = D <= 4 ? 8 : 4;
-        for (int j0 = 0; j0 < lcnt; j0 += B) {
-            float x[B][D + 1];
-            // unconditional loads (the last row repeats past the end) so all B
-            // are in flight at once; only the arithmetic below is masked
+        // Bucket rows are loaded B at a time so that their latencies overlap;
+        // rows past the bucket (the next bucket's, or the zero rows after the
+        // last one) are loaded too, and only the arithmetic is masked.
+        constexpr int B = RB;
+        static_assert(B <= kRowPad, "row batches must fit in the padding rows");
+        const float* row0 = pts + (int64_t)lstart * (D + 1);
+        if (__ballot(lcnt > 0 && h[KC - 1] == empty) != 0) {
+            // Some heap is still filling, so most rows enter: insert each row
+            // as soon as its distance is known.
+            for (int j0 = 0; j0 < lcnt; j0 += B) {
+                if constexpr (STATS) w_rows += first_active_lane();
+                float x[B][D + 1];
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const int j = j0 + b < lcnt ? j0 + b : lcnt - 1;
-                load_row<D>(pts + (int64_t)(lstart + j) * (D + 1), x[b]);
-            }
+                for (int b = 0; b < B; ++b) load_row<D>(row0 + (j0 + b) * (D + 1), x[b]);
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if (j0 + b < lcnt) {
-                    const float t0 = q[0] - x[b][0];
-                    float acc = t0 * t0;
-#pragma unroll
-                    for (int t = 1; t < D; ++t) {
-                        const float u = q[t] - x[b][t];
-                        const float sq = u * u;
-                        acc = acc + sq;
+                for (int b = 0; b < B; ++b) {
+                    const int id = __float_as_int(x[b][D]);
+                    const uint64_t key = make_key(distance<D>(q, x[b]), id);
+                    if (j0 + b < lcnt && key < h[KC - 1] && id != self) {
+                        if constexpr (STATS) {
+                            ++n_ins;
+                            w_ins += first_active_lane();
+                        }
+                        heap_insert<KC>(h, key);
                     }
-                    if (acc <= hd[KC - 1]) {
-                        const int id = __float_as_int(x[b][D]);
-                        if (id != self && key_less(acc, id, hd[KC - 1], hi[KC - 1]))
-                            heap_insert<KC>(hd, hi, acc, id);
+                }
+            }
+        } else {
+            // Every heap is full and few rows enter: mark the rows of a batch
+            // below the top, then insert only those, so a wavefront runs as
+            // many inserts as its busiest lane needs instead of one per row.
+            for (int j0 = 0; j0 < lcnt; j0 += B) {
+                if constexpr (STATS) w_rows += first_active_lane();
+                float x[B][D + 1];
+#pragma unroll
+                for (int b = 0; b < B; ++b) load_row<D>(row0 + (j0 + b) * (D + 1), x[b]);
+                uint64_t keys[B];
+                unsigned cand = 0;
+                const uint64_t top = h[KC - 1];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const int id = __float_as_int(x[b][D]);
+                    keys[b] = make_key(distance<D>(q, x[b]), id);
+                    if (j0 + b < lcnt && keys[b] < top && id != self) cand |= 1u << b;
+                }
+                while (cand) {
+                    const int j = __builtin_ctz(cand);
+                    cand &= cand - 1;
+                    uint64_t key = keys[0];
+#pragma unroll
+                    for (int b = 1; b < B; ++b) key = j == b ? keys[b] : key;
+                    if (key < h[KC - 1]) {
+                        if constexpr (STATS) {
+                            ++n_ins;
+                            w_ins += first_active_lane();
+                        }
+                        heap_insert<KC>(h, key);
                     }
                 }
             }
         }
+        lcnt = 0;
     }
 #pragma unroll
     for (int j = 0; j < KC; ++j) {
         if (j >= pad) {
             const int64_t o = qid * k + (j - pad);
-            const int id = hi[j];
-            out_idx[o] = id;
-            out_d2[o] = id < 0 ? INFINITY : hd[j];
+            const bool none = h[j] == empty;
+            out_idx[o] = none ? -1 : (int)(uint32_t)h[j];
+            out_d2[o] = none ? INFINITY : key_dist(h[j]);
         }
     }
     }  // slot < m
     if constexpr (STATS) {
-        for (int o = 32; o > 0; o >>= 1) {
-            n_enter += __shfl_xor(n_enter, o);
-            n_leaf += __shfl_xor(n_leaf, o);
-            n_pts += __shfl_xor(n_pts, o);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&stats[0], n_enter);
-            atomicAdd(&stats[1], n_leaf);
-            atomicAdd(&stats[2], n_pts);
+        unsigned long long c[9] = {n_enter, n_leaf, n_pts, n_step, n_ins,
+                                   w_step, w_rows, w_round, w_ins};
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            for (int o = 32; o > 0; o >>= 1) c[j] += __shfl_xor(c[j], o);
+            if ((threadIdx.x & 63) == 0) atomicAdd(&stats[j], c[j]);
         }
     }
 }
@@ -266,26 +361,52 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
 // Home leaf of every query: descend with the near-child rule (x < split
 // left).  Queries are grouped by key = (first packed position of the home
 // leaf) >> shift: buckets are contiguous in packed order, so key order is the
-// tree's spatial order.
+// tree's spatial order.  Each lane descends kLocQ queries at once (blocks of
+// kBlock * kLocQ consecutive queries, lane t taking t, t + kBlock, ...), so
+// that kLocQ independent node loads are in flight per step.
+constexpr int kLocQ = 4;
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ nodes,
                                                    const float* __restrict__ queries, int64_t m,
                                                    int shift, int32_t* __restrict__ home,
                                                    uint32_t* __restrict__ cnt)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    float q[D];
+    const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kLocQ) + threadIdx.x;
+    float q[kLocQ][D];
+    int cur[kLocQ];
+    NodeRec r[kLocQ];
 #pragma unroll
-    for (int t = 0; t < D; ++t) q[t] = queries[i * D + t];
-    int cur = 0;
-    NodeRec r = nodes[0];
-    while (r.dim >= 0) {
-        cur = select_dim<D>(q, r.dim) < r.split ? r.a : r.a + 1;
-        r = nodes[cur];
+    for (int u = 0; u < kLocQ; ++u) {
+        const int64_t i = min(i0 + (int64_t)u * kBlock, m - 1);  // clamped: extra lanes repeat
+#pragma unroll
+        for (int t = 0; t < D; ++t) q[u][t] = queries[i * D + t];
+        cur[u] = 0;
     }
-    home[i] = cur;
-    atomicAdd(&cnt[r.a >> shift], 1u);
+    const NodeRec root = nodes[0];
+#pragma unroll
+    for (int u = 0; u < kLocQ; ++u) r[u] = root;
+    bool inner = root.dim >= 0;
+    while (inner) {
+        inner = false;
+#pragma unroll
+        for (int u = 0; u < kLocQ; ++u) {
+            if (r[u].dim >= 0) {
+                cur[u] = select_dim<D>(q[u], r[u].dim) < r[u].split ? r[u].a : r[u].a + 1;
+                r[u] = nodes[cur[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLocQ; ++u) inner = inner || r[u].dim >= 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLocQ; ++u) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        if (i < m) {
+            home[i] = cur[u];
+            atomicAdd(&cnt[r[u].a >> shift], 1u);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_group(const NodeRec* __restrict__ nodes,
@@ -300,6 +421,12 @@ __global__ __launch_bounds__(kBlock) void k_group(const NodeRec* __restrict__ no
     const uint32_t p = atomicAdd(&offs[nodes[h].a >> shift], 1u);
     order[p] = (int32_t)i;
     shome[p] = h;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(uint32_t* __restrict__ a, int64_t len)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < len) a[i] = 0u;
 }
 
 // Exclusive scan of uint32 in place: per-block scan of 4096 values, a scan
@@ -371,17 +498,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t* __restrict__ a, i
 
 using TraverseFn = void (*)(const NodeRec*, const float*, const float*, const float*,
                             const int32_t*, const int32_t*, const int32_t*, int64_t, int, float,
-                            int32_t*, float*, unsigned long long*);
+                            int, int32_t*, float*, unsigned long long*);
 using LocateFn = void (*)(const NodeRec*, const float*, int64_t, int, int32_t*, uint32_t*);
 
 template <int D, bool STATS>
 TraverseFn pick_traverse(int k)
 {
-    if (k <= 4) return k_traverse<D, 4, STATS>;
-    if (k <= 8) return k_traverse<D, 8, STATS>;
-    if (k <= 16) return k_traverse<D, 16, STATS>;
-    if (k <= 32) return k_traverse<D, 32, STATS>;
-    return k_traverse<D, 64, STATS>;
+    constexpr int RB = D <= 4 ? 8 : 4;  // bucket rows per batch
+    if (k <= 4) return k_traverse<D, 4, STATS, RB>;
+    if (k <= 8) return k_traverse<D, 8, STATS, RB>;
+    if (k <= 16) return k_traverse<D, 16, STATS, RB>;
+    if (k <= 32) return k_traverse<D, 32, STATS, RB>;
+    return k_traverse<D, 64, STATS, RB>;
 }
 
 TraverseFn traverse_for(int d, int k, bool stats)
@@ -428,8 +556,8 @@ struct StreamBuf {
 }  // namespace
 
 int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
-               const int32_t* self_ids, float r2, int32_t order, int32_t* out_idx,
-               float* out_d2, unsigned long long* stats, hipStream_t st)
+               const int32_t* self_ids, float r2, int32_t order, int32_t batch,
+               int32_t* out_idx, float* out_d2, unsigned long long* stats, hipStream_t st)
 {
     const int d = t->d;
     TraverseFn tf = traverse_for(d, k, stats != nullptr);
@@ -438,42 +566,43 @@ int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     prof_mark(st, 5);
     const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
     const unsigned tgrid = (unsigned)((grid + kXcds - 1) / kXcds * kXcds);  // multiple of 8
-    if (order == 1) {
-        prof_mark(st, 6);
-        prof_mark(st, 7);
-        hipLaunchKernelGGL(tf, dim3(tgrid), dim3(kBlock), 0, st, t->nodes, t->bbox, t->pts,
-                           queries, nullptr, nullptr, self_ids, m, k, r2, out_idx, out_d2, stats);
-        KNN_HIP(hipGetLastError());
-        prof_mark(st, 8);
-        return KNN_OK;
-    }
     // key range: packed positions >> shift, at most 2^22 buckets
     int shift = 0;
     while ((t->n >> shift) > (int64_t(1) << 22)) ++shift;
-    const int64_t N = (t->n >> shift) + 1;
+    const int64_t N = order == 1 ? 0 : (t->n >> shift) + 1;
     const int64_t nsb = (N + kScanChunk - 1) / kScanChunk;
-    // workspace: home[m], order[m], shome[m], cnt[N], block sums[nsb]
-    const size_t bytes = sizeof(int32_t) * 3 * (size_t)m + sizeof(uint32_t) * (size_t)(N + nsb);
+    const int64_t mg = order == 1 ? 0 : m;
+    // workspace: cnt[N], block sums[nsb], home[m], order[m], shome[m]
+    const size_t bytes = sizeof(uint32_t) * (size_t)(N + nsb) + sizeof(int32_t) * 3 * (size_t)mg;
     StreamBuf ws;
     ws.s = st;
     KNN_HIP(hipMallocAsync(&ws.p, bytes, st));
-    int32_t* home = static_cast<int32_t*>(ws.p);
-    int32_t* ord = home + m;
-    int32_t* shome = ord + m;
-    uint32_t* cnt = reinterpret_cast<uint32_t*>(shome + m);
+    uint32_t* cnt = static_cast<uint32_t*>(ws.p);
     uint32_t* bsum = cnt + N;
-    KNN_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * N, st));
-    hipLaunchKernelGGL(lf, dim3(grid), dim3(kBlock), 0, st, t->nodes, queries, m, shift, home, cnt);
-    KNN_HIP(hipGetLastError());
+    int32_t* home = reinterpret_cast<int32_t*>(bsum + nsb);
+    int32_t* ord = home + mg;
+    int32_t* shome = ord + mg;
+    if (order != 1) {
+        // cleared by a kernel, not a memset node, so the call can be captured in a graph
+        k_zero<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N);
+        const unsigned lgrid = (unsigned)((m + kBlock * kLocQ - 1) / (kBlock * kLocQ));
+        hipLaunchKernelGGL(lf, dim3(lgrid), dim3(kBlock), 0, st, t->nodes, queries, m, shift, home,
+                           cnt);
+        KNN_HIP(hipGetLastError());
+    }
     prof_mark(st, 6);
-    k_scan_local<<<(unsigned)nsb, kBlock, 0, st>>>(cnt, N, bsum);
-    k_scan_sums<<<1, kBlock, 0, st>>>(bsum, nsb);
-    k_scan_add<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N, bsum);
-    k_group<<<grid, kBlock, 0, st>>>(t->nodes, home, m, shift, cnt, ord, shome);
-    KNN_HIP(hipGetLastError());
+    if (order != 1) {
+        k_scan_local<<<(unsigned)nsb, kBlock, 0, st>>>(cnt, N, bsum);
+        k_scan_sums<<<1, kBlock, 0, st>>>(bsum, nsb);
+        k_scan_add<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N, bsum);
+        k_group<<<grid, kBlock, 0, st>>>(t->nodes, home, m, shift, cnt, ord, shome);
+        KNN_HIP(hipGetLastError());
+    }
     prof_mark(st, 7);
+    const int32_t* o = order == 1 ? nullptr : ord;
+    const int32_t* hm = order == 1 ? nullptr : shome;
     hipLaunchKernelGGL(tf, dim3(tgrid), dim3(kBlock), 0, st, t->nodes, t->bbox, t->pts, queries,
-                       ord, shome, self_ids, m, k, r2, out_idx, out_d2, stats);
+                       o, hm, self_ids, m, k, r2, batch, out_idx, out_d2, stats);
     KNN_HIP(hipGetLastError());
     prof_mark(st, 8);
     return KNN_OK;

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import pins
-from gpu_util import assert_same, compare_trees, gpu_knn, log
+from gpu_util import assert_same, compare_trees, dev, gpu_knn, log
 from paper_1607_08220_amd import inputs
 from treecheck import check_knn_lists, check_tree
 
@@ -170,8 +170,35 @@ def test_determinism_and_order_independence(knn):
     half = len(p) // 2
     d_i, d_d, _ = gpu_knn(w.points, w.queries[:half], w.k, self_ids=w.self_ids[:half], tree=t1)
     assert_same(d_i, d_d, a_i[:half], a_d[:half], "batch split")
+    # the leaf-batch knob only reschedules the traversal: identical results
+    import torch
+    Q, S = dev(w.queries), dev(w.self_ids)
+    for lb in (1, 17, 64):
+        idx, d2 = knn.knn_query_ex(t1, Q, w.k, self_ids=S, leaf_batch=lb)
+        torch.cuda.synchronize()
+        assert_same(idx.cpu().numpy(), d2.cpu().numpy(), a_i, a_d, f"leaf_batch={lb}")
+    with pytest.raises(knn.KnnError):
+        knn.knn_query_ex(t1, Q, w.k, leaf_batch=65)
     t1.free()
     t2.free()
+
+
+def test_radius_at_or_below_zero(knn):
+    """r2_max <= 0 admits no point (D < r2_max is never true for D >= 0); a
+    radius equal to a distance excludes that point (strict)."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 2, 0], [3, 0, 0]], np.float32)
+    log("[case] radius <= 0 and strict radius")
+    for r2 in (0.0, -1.0, -np.inf):
+        gi, gd, t = gpu_knn(X, X[:2], 3, r2=r2)
+        assert (gi == -1).all() and np.isinf(gd).all(), r2
+        bi, bd = oracle.bf32(X, X[:2], 3, r2=r2)
+        assert_same(gi, gd, bi, bd, f"r2={r2}")
+        t.free()
+    gi, gd, t = gpu_knn(X, X[:1], 4, r2=4.0)  # D = 0, 1 qualify; D = 4 is not < 4
+    assert gi.tolist() == [[0, 1, -1, -1]] and gd[0, :2].tolist() == [0.0, 1.0]
+    bi, bd = oracle.bf32(X, X[:1], 4, r2=4.0)
+    assert_same(gi, gd, bi, bd, "strict radius")
+    t.free()
 
 
 def test_empty_and_degenerate_calls(knn):
