@@ -40,7 +40,12 @@ constexpr int kWavesPerBlock = kBlock / kWave;       // 4
 constexpr int kItems = 16;                           // elements per lane per block pass
 constexpr int kWaveChunk = kWave * kItems;           // 1024 elements per wavefront
 constexpr int kChunk = kBlock * kItems;              // 4096 elements per block
-constexpr int kBins = kSampleMax + 1;                // histogram bins per node
+constexpr int kBins = kSampleMax + 1;                // histogram bins per node (full)
+// The level histogram only resolves the sample ranks jl..jh around the middle
+// (jl = s/2 - kWinHalf, jh = s/2 + kWinHalf, clamped): a node's row holds
+// [#{x < s_jl}, the bins jl+1..jh, #{x >= s_jh}].
+constexpr int kWinHalf = 128;
+constexpr int kWinRow = 2 * kWinHalf + 2;
 // The histogram pass gives each block 8 times more points: every block adds
 // its LDS histogram into the node's global one, so fewer blocks mean fewer
 // global atomics on the same counters.
@@ -161,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(Level L, const float* __restr
     const int node = blockIdx.x, t = threadIdx.x;
     if (node >= L.cnt[0]) return;
     const int64_t start = L.start[node], c = L.count[node];
-    for (int i = t; i < kBins; i += kBlock) hist[(int64_t)node * kBins + i] = 0u;
+    for (int i = t; i < kWinRow; i += kBlock) hist[(int64_t)node * kWinRow + i] = 0u;
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
     double bestV = -1.0;
     int best = 0;
@@ -217,51 +222,107 @@ __global__ __launch_bounds__(kBlock) void k_sample(Level L, const float* __restr
 // ---------------------------------------------------------------------------
 // B4: histogram over the sorted sample (blocks over node chunks)
 // ---------------------------------------------------------------------------
+__device__ inline void sample_window(int s, int* jl, int* jh)
+{
+    *jl = s / 2 - kWinHalf > 0 ? s / 2 - kWinHalf : 0;
+    *jh = s / 2 + kWinHalf < s - 1 ? s / 2 + kWinHalf : s - 1;
+}
+
+// Counts, over the node's points x, #{x < s_jl}, #{x >= s_jh} and the bins
+// b = #{j : s_j <= x} for the points in between (jl < b <= jh), which give
+// C_j = #{x < s_j} exactly for every j in [jl, jh].  Points outside the
+// window are counted with wavefront ballots; the points inside are first
+// queued per wavefront in LDS so that every lane of a binary search over the
+// window's sample values has a point to place.
 __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restrict__ dimv,
                                                  const float* __restrict__ samples,
                                                  const float* __restrict__ cols, int64_t n,
                                                  uint32_t* __restrict__ hist)
 {
-    __shared__ float sv[kSampleMax];
-    __shared__ uint32_t h[kBins];
-    const int b = blockIdx.x, t = threadIdx.x;
+    __shared__ float sv[2 * kWinHalf + 1];
+    __shared__ uint32_t h[kWinRow];
+    __shared__ float queue[kWavesPerBlock][2 * kWave];
+    const int b = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
     if (b >= L.cnt[2]) return;
     const int node = L.hnode[b];
     const int dim = dimv[node];
     if (dim < 0) return;
     const int64_t start = L.start[node], c = L.count[node];
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
+    int jl, jh;
+    sample_window(s, &jl, &jh);
+    const int nwin = jh - jl;  // window bins jl+1 .. jh
     const int64_t beg = L.hbeg[b];
     const int64_t end = beg + kHistChunk < c ? beg + kHistChunk : c;
-    for (int i = t; i < s; i += kBlock) sv[i] = samples[(int64_t)node * kSampleMax + i];
-    for (int i = t; i <= s; i += kBlock) h[i] = 0u;
+    for (int i = t; i <= nwin; i += kBlock) sv[i] = samples[(int64_t)node * kSampleMax + jl + i];
+    for (int i = t; i < kWinRow; i += kBlock) h[i] = 0u;
     __syncthreads();
+    const float lo_v = sv[0], hi_v = sv[nwin];
     const float* col = cols + (int64_t)dim * n + start;
-    // kHistIlp independent binary searches per thread overlap their LDS latency
-    constexpr int kHistIlp = 8;
-    for (int64_t e0 = beg + t; e0 < end; e0 += (int64_t)kBlock * kHistIlp) {
-        float x[kHistIlp];
-        int pos[kHistIlp];  // number of sample values <= x
+    uint32_t below = 0, above = 0;
+    int qn = 0;  // queued points of this wavefront (uniform)
+    float* qw = queue[w];
+    // place the first 64 queued points: bin = jl + 1 + #{1 <= i < nwin : sv[i] <= x}
+    auto drain = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        const float x = qw[lane];
+        int pos = 0;
+        for (int step = kWinHalf; step > 0; step >>= 1) {
+            const int np = pos + step;
+            if (np < nwin && sv[np] <= x) pos = np;
+        }
+        atomicAdd(&h[1 + pos], 1u);
+        const float tail = qw[kWave + lane];
+        if (lane < qn - kWave) qw[lane] = tail;
+        __builtin_amdgcn_wave_barrier();
+        qn -= kWave;
+    };
+    constexpr int kIlp = 8;
+    const int64_t wbeg = beg + (int64_t)w * kWave * kIlp;
+    for (int64_t e0 = wbeg; e0 < end; e0 += (int64_t)kBlock * kIlp) {
+        float x[kIlp];
 #pragma unroll
-        for (int u = 0; u < kHistIlp; ++u) {  // unconditional loads, clamped in range
-            const int64_t e = e0 + (int64_t)u * kBlock;
+        for (int u = 0; u < kIlp; ++u) {  // unconditional loads, clamped in range
+            const int64_t e = e0 + (int64_t)u * kWave + lane;
             x[u] = col[e < end ? e : end - 1];
-            pos[u] = 0;
         }
-        for (int step = kSampleMax; step > 0; step >>= 1) {
 #pragma unroll
-            for (int u = 0; u < kHistIlp; ++u) {
-                const int np = pos[u] + step;
-                if (np <= s && sv[np - 1] <= x[u]) pos[u] = np;
+        for (int u = 0; u < kIlp; ++u) {
+            const bool ok = e0 + (int64_t)u * kWave + lane < end;
+            below += ok && x[u] < lo_v;
+            above += ok && x[u] >= hi_v;
+            const bool in = ok && x[u] >= lo_v && x[u] < hi_v;
+            const unsigned long long m = __ballot(in);
+            const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+            if (in) qw[qn + off] = x[u];
+            qn += __popcll(m);
+            if (qn >= kWave) drain();
+        }
+    }
+    if (qn > 0) {  // the last partial queue: lanes past qn place nothing
+        __builtin_amdgcn_wave_barrier();
+        const float x = qw[lane];
+        if (lane < qn) {
+            int pos = 0;
+            for (int step = kWinHalf; step > 0; step >>= 1) {
+                const int np = pos + step;
+                if (np < nwin && sv[np] <= x) pos = np;
             }
+            atomicAdd(&h[1 + pos], 1u);
         }
-#pragma unroll
-        for (int u = 0; u < kHistIlp; ++u)
-            if (e0 + (int64_t)u * kBlock < end) atomicAdd(&h[pos[u]], 1u);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        below += __shfl_xor(below, o);
+        above += __shfl_xor(above, o);
+    }
+    if (lane == 0) {
+        atomicAdd(&h[0], below);
+        atomicAdd(&h[nwin + 1], above);
     }
     __syncthreads();
-    for (int i = t; i <= s; i += kBlock)
-        if (h[i]) atomicAdd(&hist[(int64_t)node * kBins + i], h[i]);
+    for (int i = t; i <= nwin + 1; i += kBlock)
+        if (h[i]) atomicAdd(&hist[(int64_t)node * kWinRow + i], h[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,6 +348,49 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* total, uint32_t* wsum)
     return base + x - v;
 }
 
+// Thread t holds R consecutive counts v (of the entries R*t .. R*t+R-1, the
+// entry e standing for sample rank j0 + e) whose inclusive prefix sums are
+// C_j = #{x < s_j}.  Returns, to every thread, the smallest key
+// gap * 2048 + j over the valid j (j < jend, 0 < C_j < c), gap = |2 C_j - c|:
+// the rank closest to half, ties to the smaller rank; LLONG_MAX if none.
+template <int R>
+__device__ long long block_split_key(const uint32_t (&v)[R], int j0, int jend, int64_t c,
+                                     uint32_t* wsum, long long* gbest)
+{
+    const int t = threadIdx.x;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) sum += v[r];
+    uint32_t tot;
+    uint32_t C = block_excl_scan(sum, &tot, wsum);
+    long long key = LLONG_MAX;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = j0 + R * t + r;
+        C += v[r];
+        if (j < jend && C > 0 && (int64_t)C < c) {
+            long long gap = 2 * (long long)C - c;
+            if (gap < 0) gap = -gap;
+            const long long kk = gap * 2048 + j;
+            if (kk < key) key = kk;
+        }
+    }
+    gbest[t] = key;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if (t < w && gbest[t + w] < gbest[t]) gbest[t] = gbest[t + w];
+        __syncthreads();
+    }
+    key = gbest[0];
+    __syncthreads();
+    return key;
+}
+
+// One block per node.  From the window counts, C_j is exact for j in
+// [jl, jh]; since C_j does not decrease with j, the rank closest to half lies
+// in the window whenever 2 C_jl <= c <= 2 C_jh (a rank outside the window with
+// the same gap has the same C_j, hence the same sample value, as jl or jh).
+// Otherwise the block counts the full histogram of the node itself.
 __global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict__ dimv,
                                                    const float* __restrict__ samples,
                                                    const uint32_t* __restrict__ hist,
@@ -296,44 +400,53 @@ __global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict_
     __shared__ uint32_t wsum[kWavesPerBlock];
     __shared__ long long gbest[kBlock];
     __shared__ float fl[kBlock], fh[kBlock];
+    __shared__ float sv[kSampleMax];
+    __shared__ uint32_t hfull[kBins];
     const int node = blockIdx.x, t = threadIdx.x;
     if (node >= L.cnt[0]) return;
     const int64_t start = L.start[node], c = L.count[node];
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
     const int dim = dimv[node];
     if (dim >= 0) {
-        // thread t owns bins 4t .. 4t+3; C_j = sum of bins 0..j
-        uint32_t hb[4], sum = 0;
+        int jl, jh;
+        sample_window(s, &jl, &jh);
+        const int nwin = jh - jl;
+        const uint32_t* row = hist + (int64_t)node * kWinRow;
+        uint32_t v[2];
+        uint64_t below = row[0], inwin = 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int j = 4 * t + r;
-            hb[r] = j < s ? hist[(int64_t)node * kBins + j] : 0u;
-            sum += hb[r];
+        for (int r = 0; r < 2; ++r) {
+            const int e = 2 * t + r;  // entry 0 is #{x < s_jl}, entry e the bin jl + e
+            v[r] = e <= nwin ? row[e] : 0u;
         }
-        uint32_t tot;
-        uint32_t C = block_excl_scan(sum, &tot, wsum);
-        // key = gap * 2048 + j: the minimum gives the smallest gap, then smallest j
-        long long key = LLONG_MAX;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int j = 4 * t + r;
-            C += hb[r];
-            if (j < s && C > 0 && (int64_t)C < c) {
-                long long gap = 2 * (long long)C - c;
-                if (gap < 0) gap = -gap;
-                long long kk = gap * 2048 + j;
-                if (kk < key) key = kk;
-            }
-        }
-        gbest[t] = key;
-        __syncthreads();
-        for (int w = kBlock / 2; w >= 1; w >>= 1) {
-            if (t < w && gbest[t + w] < gbest[t]) gbest[t] = gbest[t + w];
+        for (int e = 1; e <= nwin; ++e) inwin += row[e];
+        long long key;
+        if (2 * (int64_t)below <= c && 2 * (int64_t)(below + inwin) >= c) {
+            key = block_split_key<2>(v, jl, jh + 1, c, wsum, gbest);
+        } else {
+            // the middle lies outside the window: full histogram of the node
+            for (int i = t; i < s; i += kBlock) sv[i] = samples[(int64_t)node * kSampleMax + i];
+            for (int i = t; i < kBins; i += kBlock) hfull[i] = 0u;
             __syncthreads();
+            const float* col = cols + (int64_t)dim * n + start;
+            for (int64_t e = t; e < c; e += kBlock) {
+                const float x = col[e];
+                int pos = 0;  // number of sample values <= x
+                for (int step = kSampleMax; step > 0; step >>= 1) {
+                    const int np = pos + step;
+                    if (np <= s && sv[np - 1] <= x) pos = np;
+                }
+                atomicAdd(&hfull[pos], 1u);
+            }
+            __syncthreads();
+            uint32_t vf[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vf[r] = 4 * t + r < s ? hfull[4 * t + r] : 0u;
+            key = block_split_key<4>(vf, 0, s, c, wsum, gbest);
         }
         if (t == 0) {
             // V > 0 guarantees a valid j; the guard only keeps the index in range
-            int j = gbest[0] == LLONG_MAX ? 0 : (int)(gbest[0] % 2048);
+            const int j = key == LLONG_MAX ? 0 : (int)(key % 2048);
             splitv[node] = samples[(int64_t)node * kSampleMax + j];
         }
         return;
@@ -1337,7 +1450,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(splitv.alloc(sizeof(float) * nn_cap));
         KNN_HIP(nleft.alloc(sizeof(int32_t) * nn_cap));
         KNN_HIP(samples.alloc(sizeof(float) * kSampleMax * nn_cap));
-        KNN_HIP(hist.alloc(sizeof(uint32_t) * kBins * nn_cap));
+        KNN_HIP(hist.alloc(sizeof(uint32_t) * kWinRow * nn_cap));
         KNN_HIP(wave_left.alloc(sizeof(uint32_t) * kWavesPerBlock * nb_cap));
         KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
         KNN_HIP(planv.alloc(sizeof(int32_t) * kPlanStride * nn_cap));

@@ -155,6 +155,21 @@ def test_heavy_duplicates_and_identical_big_nodes(knn):
     _full_check(knn, Y, Y[:50], 4, 2, what="constant sample", subtree_points=64)
 
 
+def test_split_outside_sample_window(knn):
+    """The level histogram resolves only the sample ranks around the middle;
+    these inputs put the point closest to half outside that window (the
+    systematic sample positions hit only the large, or only the small,
+    values of the split dimension), so the full-histogram path decides."""
+    rng = np.random.default_rng(5)
+    for big_even in (True, False):
+        x = np.empty(4096, np.float32)
+        hi = (1.0 + rng.random(2048) * 0.01).astype(np.float32)
+        lo = (rng.random(2048) * 0.001).astype(np.float32)
+        x[0::2], x[1::2] = (hi, lo) if big_even else (lo, hi)
+        X = np.stack([x, (rng.random(4096) * 1e-4).astype(np.float32)], 1)
+        _full_check(knn, X, X[::7], 5, 32, self_ids=np.arange(0, 4096, 7), what=f"window big_even={big_even}")
+
+
 def test_determinism_and_order_independence(knn):
     w = inputs.workload("cosmo_clustered", scale=1 / 256)
     log(f"[case] determinism n={len(w.points)}")
