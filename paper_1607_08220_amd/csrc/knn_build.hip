@@ -46,6 +46,7 @@ constexpr int kBins = kSampleMax + 1;                // histogram bins per node 
 // [#{x < s_jl}, the bins jl+1..jh, #{x >= s_jh}].
 constexpr int kWinHalf = 128;
 constexpr int kWinRow = 2 * kWinHalf + 2;
+constexpr int kWinStride = 2 * kWinHalf + 8;  // sorted sample values s_jl..s_jh per node
 // The histogram pass gives each block 8 times more points: every block adds
 // its LDS histogram into the node's global one, so fewer blocks mean fewer
 // global atomics on the same counters.
@@ -120,25 +121,6 @@ __device__ inline float wave_max(float v)
     return v;
 }
 
-// Pairwise FP64 sum over a[0..1023] (zero padded), a[i] += a[i + w] for
-// w = 512 .. 1.  Thread t of the block holds a[t + 256 r], r = 0..3.
-// Zero padding past the sample size leaves the sum equal to the same tree
-// over the next power of two above the sample size.
-__device__ double block_psum(const double a[4], double* red)
-{
-    const int t = threadIdx.x;
-    double x0 = a[0] + a[2];  // w = 512
-    double x1 = a[1] + a[3];
-    red[t] = x0 + x1;         // w = 256
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w) red[t] = red[t] + red[t + w];
-        __syncthreads();
-    }
-    double r = red[0];
-    __syncthreads();
-    return r;
-}
 
 // ---------------------------------------------------------------------------
 // B0: ingest
@@ -156,78 +138,140 @@ __global__ void k_ingest(const float* __restrict__ aos, int64_t n, int d,
 // ---------------------------------------------------------------------------
 // B1-B3: sample, split dimension, sorted sample (one block per node)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_sample(Level L, const float* __restrict__ cols,
-                                                   int64_t n, int d, float* __restrict__ samples,
-                                                   int32_t* __restrict__ out_dim,
-                                                   uint32_t* __restrict__ hist)
-{
-    __shared__ double red[kBlock];
-    __shared__ float sv[kSampleMax];
-    const int node = blockIdx.x, t = threadIdx.x;
-    if (node >= L.cnt[0]) return;
-    const int64_t start = L.start[node], c = L.count[node];
-    for (int i = t; i < kWinRow; i += kBlock) hist[(int64_t)node * kWinRow + i] = 0u;
-    const int s = (int)(c < kSampleMax ? c : kSampleMax);
-    double bestV = -1.0;
-    int best = 0;
-    for (int dd = 0; dd < d; ++dd) {
-        const float* col = cols + (int64_t)dd * n + start;
-        double a[4], q[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int i = t + kBlock * r;
-            a[r] = i < s ? (double)col[sample_pos(i, c, s)] : 0.0;
-        }
-        const double S = block_psum(a, red);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int i = t + kBlock * r;
-            double w = (double)s * a[r] - S;
-            q[r] = i < s ? w * w : 0.0;
-        }
-        const double V = block_psum(q, red);
-        if (V > bestV) {
-            bestV = V;
-            best = dd;
-        }
-    }
-    if (!(bestV > 0.0)) {  // sample constant in every dimension
-        if (t == 0) out_dim[node] = -1;
-        return;
-    }
-    const float* col = cols + (int64_t)best * n + start;
-    int P = 1;
-    while (P < s) P <<= 1;
-    for (int i = t; i < P; i += kBlock) sv[i] = i < s ? col[sample_pos(i, c, s)] : INFINITY;
-    __syncthreads();
-    for (int k = 2; k <= P; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < P; i += kBlock) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    float x = sv[i], y = sv[ixj];
-                    bool asc = (i & k) == 0;
-                    if ((x > y) == asc) {
-                        sv[i] = y;
-                        sv[ixj] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    for (int i = t; i < s; i += kBlock) samples[(int64_t)node * kSampleMax + i] = sv[i];
-    if (t == 0) out_dim[node] = best;
-}
-
-// ---------------------------------------------------------------------------
-// B4: histogram over the sorted sample (blocks over node chunks)
-// ---------------------------------------------------------------------------
 __device__ inline void sample_window(int s, int* jl, int* jh)
 {
     *jl = s / 2 - kWinHalf > 0 ? s / 2 - kWinHalf : 0;
     *jh = s / 2 + kWinHalf < s - 1 ? s / 2 + kWinHalf : s - 1;
 }
 
+// Sample position of rank j (s = kSampleMax is a power of two: a shift).
+__device__ inline int64_t sample_pos_fast(int64_t j, int64_t c, int s)
+{
+    return s == kSampleMax ? ((2 * j + 1) * c) >> 11 : sample_pos(j, c, s);
+}
+static_assert(2 * kSampleMax == 2048, "sample_pos_fast divides by 2 * kSampleMax with a shift");
+
+// Pairwise FP64 sum over a[0..1023] (zero padded past the sample size):
+// a[i] += a[i + w] for w = 512, 256, .., 1, the total in a[0].  Zero padding
+// leaves the sum equal to the same tree over the next power of two above the
+// sample size.  One wavefront: lane L holds a[L + 64 r], r = 0..15, so the
+// strides 512..64 stay inside the lane and 32..1 cross lanes.  The result is
+// returned to every lane.
+__device__ inline double wave_psum(double (&v)[16])
+{
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = v[r] + v[r + 8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = v[r] + v[r + 4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) v[r] = v[r] + v[r + 2];
+    double x = v[0] + v[1];
+    for (int w = 32; w >= 1; w >>= 1) x = x + __shfl_down(x, w);
+    return __shfl(x, 0);
+}
+
+// Bitonic sort of 1024 floats held by one wavefront, element 16 L + r in
+// register r of lane L: strides below 16 stay in the lane, the others pair
+// lane L with lane L ^ (stride / 16).
+__device__ inline void wave_sort1024(float (&u)[16])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 1024; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 16) {
+                const int lm = j >> 4;
+                const bool lower = (lane & lm) == 0;
+                const bool asc = k >= 16 ? ((16 * lane) & k) == 0 : true;
+                const bool keep_min = lower == asc;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float p = __shfl_xor(u[r], lm);
+                    u[r] = keep_min ? fminf(u[r], p) : fmaxf(u[r], p);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    if ((r & j) == 0) {
+                        const bool asc = k >= 16 ? ((16 * lane) & k) == 0 : (r & k) == 0;
+                        const float x = u[r], y = u[r | j];
+                        const float lo = fminf(x, y), hi = fmaxf(x, y);
+                        u[r] = asc ? lo : hi;
+                        u[r | j] = asc ? hi : lo;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// B1-B3: one wavefront per node (kWavesPerBlock nodes per block).  Sample
+// s = min(count, 1024) points at the systematic positions, pick the
+// dimension of largest sample variance (FP64, fixed pairwise order), sort
+// the sample along it and keep the values of ranks jl..jh; clear the node's
+// histogram row.
+__global__ __launch_bounds__(kBlock) void k_sample(Level L, const float* __restrict__ cols,
+                                                   int64_t n, int d, float* __restrict__ samples,
+                                                   int32_t* __restrict__ out_dim,
+                                                   uint32_t* __restrict__ hist)
+{
+    const int lane = threadIdx.x & 63;
+    const int node = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (node >= L.cnt[0]) return;
+    const int64_t start = L.start[node], c = L.count[node];
+    for (int i = lane; i < kWinRow; i += kWave) hist[(int64_t)node * kWinRow + i] = 0u;
+    const int s = (int)(c < kSampleMax ? c : kSampleMax);
+    double bestV = -1.0;
+    int best = 0;
+    for (int dd = 0; dd < d; ++dd) {
+        const float* col = cols + (int64_t)dd * n + start;
+        double v[16], q[16];
+        float f[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int j = lane + 64 * r;
+            f[r] = col[sample_pos_fast(j < s ? j : s - 1, c, s)];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = lane + 64 * r < s ? (double)f[r] : 0.0;
+        const double S = wave_psum(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const double w = (double)s * (double)f[r] - S;
+            q[r] = lane + 64 * r < s ? w * w : 0.0;
+        }
+        const double V = wave_psum(q);
+        if (V > bestV) {
+            bestV = V;
+            best = dd;
+        }
+    }
+    if (!(bestV > 0.0)) {  // sample constant in every dimension
+        if (lane == 0) out_dim[node] = -1;
+        return;
+    }
+    const float* col = cols + (int64_t)best * n + start;
+    float u[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = 16 * lane + r;
+        u[r] = j < s ? col[sample_pos_fast(j, c, s)] : INFINITY;
+    }
+    wave_sort1024(u);
+    int jl, jh;
+    sample_window(s, &jl, &jh);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = 16 * lane + r;
+        if (j >= jl && j <= jh) samples[(int64_t)node * kWinStride + (j - jl)] = u[r];
+    }
+    if (lane == 0) out_dim[node] = best;
+}
+
+// ---------------------------------------------------------------------------
+// B4: histogram over the sorted sample (blocks over node chunks)
+// ---------------------------------------------------------------------------
 // Counts, over the node's points x, #{x < s_jl}, #{x >= s_jh} and the bins
 // b = #{j : s_j <= x} for the points in between (jl < b <= jh), which give
 // C_j = #{x < s_j} exactly for every j in [jl, jh].  Points outside the
@@ -254,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
     const int nwin = jh - jl;  // window bins jl+1 .. jh
     const int64_t beg = L.hbeg[b];
     const int64_t end = beg + kHistChunk < c ? beg + kHistChunk : c;
-    for (int i = t; i <= nwin; i += kBlock) sv[i] = samples[(int64_t)node * kSampleMax + jl + i];
+    for (int i = t; i <= nwin; i += kBlock) sv[i] = samples[(int64_t)node * kWinStride + i];
     for (int i = t; i < kWinRow; i += kBlock) h[i] = 0u;
     __syncthreads();
     const float lo_v = sv[0], hi_v = sv[nwin];
@@ -421,13 +465,33 @@ __global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict_
         }
         for (int e = 1; e <= nwin; ++e) inwin += row[e];
         long long key;
-        if (2 * (int64_t)below <= c && 2 * (int64_t)(below + inwin) >= c) {
+        const bool in_window = 2 * (int64_t)below <= c && 2 * (int64_t)(below + inwin) >= c;
+        if (in_window) {
             key = block_split_key<2>(v, jl, jh + 1, c, wsum, gbest);
         } else {
-            // the middle lies outside the window: full histogram of the node
-            for (int i = t; i < s; i += kBlock) sv[i] = samples[(int64_t)node * kSampleMax + i];
+            // the middle lies outside the window: sort the whole sample again
+            // and count the full histogram of the node
+            const float* scol = cols + (int64_t)dim * n + start;
+            int P = 1;
+            while (P < s) P <<= 1;
+            for (int i = t; i < P; i += kBlock) sv[i] = i < s ? scol[sample_pos(i, c, s)] : INFINITY;
             for (int i = t; i < kBins; i += kBlock) hfull[i] = 0u;
             __syncthreads();
+            for (int k = 2; k <= P; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = t; i < P; i += kBlock) {
+                        const int ixj = i ^ j;
+                        if (ixj > i) {
+                            const float x = sv[i], y = sv[ixj];
+                            const bool asc = (i & k) == 0;
+                            if ((x > y) == asc) {
+                                sv[i] = y;
+                                sv[ixj] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
             const float* col = cols + (int64_t)dim * n + start;
             for (int64_t e = t; e < c; e += kBlock) {
                 const float x = col[e];
@@ -446,8 +510,8 @@ __global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict_
         }
         if (t == 0) {
             // V > 0 guarantees a valid j; the guard only keeps the index in range
-            const int j = key == LLONG_MAX ? 0 : (int)(key % 2048);
-            splitv[node] = samples[(int64_t)node * kSampleMax + j];
+            const int j = key == LLONG_MAX ? (in_window ? jl : 0) : (int)(key % 2048);
+            splitv[node] = in_window ? samples[(int64_t)node * kWinStride + (j - jl)] : sv[j];
         }
         return;
     }
@@ -751,7 +815,7 @@ __device__ inline void wave_tree_n(double (&v)[N], double (&out)[N])
     }
 }
 
-// Lane-local part of the pairwise tree (block_psum's order) for N sums:
+// Lane-local part of the pairwise tree (wave_psum's order) for N sums:
 // element l + 64 r of sum i is val(i, r), for r < RM; registers r >= R are
 // zeros, whose additions are skipped (they would not change the sum), and so
 // are the steps of the 1024-wide tree that pair registers at or above RM.
@@ -1449,7 +1513,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(dimv.alloc(sizeof(int32_t) * nn_cap));
         KNN_HIP(splitv.alloc(sizeof(float) * nn_cap));
         KNN_HIP(nleft.alloc(sizeof(int32_t) * nn_cap));
-        KNN_HIP(samples.alloc(sizeof(float) * kSampleMax * nn_cap));
+        KNN_HIP(samples.alloc(sizeof(float) * kWinStride * nn_cap));
         KNN_HIP(hist.alloc(sizeof(uint32_t) * kWinRow * nn_cap));
         KNN_HIP(wave_left.alloc(sizeof(uint32_t) * kWavesPerBlock * nb_cap));
         KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
@@ -1505,7 +1569,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
             const int32_t* srci = (buf ? idxB : idxA).as<int32_t>();
             float* dst = (buf ? colsA : colsB).as<float>();
             int32_t* dsti = (buf ? idxA : idxB).as<int32_t>();
-            k_sample<<<g_nn, kBlock, 0, st>>>(cur, src, n, d, samples.as<float>(),
+            k_sample<<<(g_nn + kWavesPerBlock - 1) / kWavesPerBlock, kBlock, 0, st>>>(cur, src, n, d, samples.as<float>(),
                                               dimv.as<int32_t>(), hist.as<uint32_t>());
             k_hist<<<g_nbh, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), samples.as<float>(), src, n,
                                              hist.as<uint32_t>());
