@@ -701,16 +701,36 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
         }
     }
     __syncthreads();
-    // columns d .. 0 (d is the index column): stage, then write contiguous runs
+    // columns 0 .. d (d is the index column): stage in LDS, then write the
+    // left and right runs contiguously; the next column's loads are issued
+    // before the barrier so that their latency overlaps this column's writes
+    uint32_t nxt[kR];
+    {
+        const uint32_t* srcw = d > 0 ? reinterpret_cast<const uint32_t*>(src_cols)
+                                     : reinterpret_cast<const uint32_t*>(src_idx);
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int e = kBlock * r + t;
+            nxt[r] = srcw[src0 + (e < len ? e : len - 1)];
+        }
+    }
     for (int col = 0; col <= d; ++col) {
-        const uint32_t* srcw = col < d ? reinterpret_cast<const uint32_t*>(src_cols + (int64_t)col * n)
-                                       : reinterpret_cast<const uint32_t*>(src_idx);
         uint32_t* dstw = col < d ? reinterpret_cast<uint32_t*>(dst_cols + (int64_t)col * n)
                                  : reinterpret_cast<uint32_t*>(dst_idx);
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             const int e = kBlock * r + t;
-            if (e < len) stage[e] = srcw[src0 + e];
+            if (e < len) stage[e] = nxt[r];
+        }
+        if (col < d) {
+            const uint32_t* srcw = col + 1 < d
+                ? reinterpret_cast<const uint32_t*>(src_cols + (int64_t)(col + 1) * n)
+                : reinterpret_cast<const uint32_t*>(src_idx);
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                const int e = kBlock * r + t;
+                nxt[r] = srcw[src0 + (e < len ? e : len - 1)];
+            }
         }
         __syncthreads();
 #pragma unroll
