@@ -47,6 +47,10 @@ typedef struct {
     int32_t max_depth;      /* deepest allowed leaf level, root = 0 (default 64) */
     int32_t subtree_points; /* nodes of at most this many points are finished by one
                                wavefront in LDS (default: derived from dim, at most 1024) */
+    int32_t split_block_nodes; /* level passes of at most this many nodes choose each split
+                                  with a workgroup, larger ones with one wavefront per node
+                                  (default 256; -1: always a wavefront); a scheduling knob,
+                                  the tree does not depend on it */
 } knn_build_params;
 
 #define KNN_QUERY_STATS 9

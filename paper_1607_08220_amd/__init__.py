@@ -35,7 +35,7 @@ class KnnError(RuntimeError):
 
 class _BuildParams(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("max_depth", ctypes.c_int32),
-                ("subtree_points", ctypes.c_int32)]
+                ("subtree_points", ctypes.c_int32), ("split_block_nodes", ctypes.c_int32)]
 
 
 class _QueryParams(ctypes.Structure):
@@ -149,11 +149,12 @@ class Tree:
             pass
 
 
-def knn_build_ex(points, leaf_size: int = 0, max_depth: int = 0, subtree_points: int = 0) -> Tree:
+def knn_build_ex(points, leaf_size: int = 0, max_depth: int = 0, subtree_points: int = 0,
+                 split_block_nodes: int = 0) -> Tree:
     """Build the kd-tree over ``points`` (CUDA float32 [n, dim])."""
     lib = load_library()
     _dev_f32(points, "points")
-    p = _BuildParams(leaf_size, max_depth, subtree_points)
+    p = _BuildParams(leaf_size, max_depth, subtree_points, split_block_nodes)
     out = ctypes.c_void_p()
     _check(lib.knn_build_ex(ctypes.c_void_p(points.data_ptr()), points.shape[0], points.shape[1],
                             ctypes.byref(p), _stream(points), ctypes.byref(out)))

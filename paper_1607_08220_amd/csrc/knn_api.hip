@@ -112,21 +112,22 @@ int knn_build_ex(const float* points, int64_t n, int32_t dim, const knn_build_pa
     if (!points) return fail(KNN_EINVAL, "points is NULL");
     if (n < 1 || n > kMaxPoints) return fail(KNN_EINVAL, "n must be in [1, 2^30]");
     if (dim < 1 || dim > KNN_MAX_DIM) return fail(KNN_EINVAL, "dim must be in [1, 16]");
-    knn_build_params q = p ? *p : knn_build_params{0, 0, 0};
-    if (q.leaf_size < 0 || q.max_depth < 0 || q.subtree_points < 0)
+    knn_build_params q = p ? *p : knn_build_params{0, 0, 0, 0};
+    if (q.leaf_size < 0 || q.max_depth < 0 || q.subtree_points < 0 || q.split_block_nodes < -1)
         return fail(KNN_EINVAL, "negative build parameter");
     const int32_t leaf = q.leaf_size ? q.leaf_size : kDefaultLeaf;
     const int32_t max_depth = q.max_depth ? q.max_depth : kDefaultMaxDepth;
     if (max_depth > 4096) return fail(KNN_EINVAL, "max_depth too large");
     const int32_t W = subtree_points_for(dim, q.subtree_points);
-    return build_tree(points, n, dim, leaf, max_depth, W, static_cast<hipStream_t>(stream), out);
+    const int64_t sbn = q.split_block_nodes ? std::max(q.split_block_nodes, 0) : kDefaultSplitBlockNodes;
+    return build_tree(points, n, dim, leaf, max_depth, W, sbn, static_cast<hipStream_t>(stream), out);
 }
 
 int knn_build(const float* points, int64_t n, int32_t dim, int32_t leaf_size, void* stream,
               knn_tree** out)
 {
     if (leaf_size < 0) return fail(KNN_EINVAL, "leaf_size must be >= 1");
-    knn_build_params p{leaf_size, 0, 0};
+    knn_build_params p{leaf_size, 0, 0, 0};
     return knn_build_ex(points, n, dim, &p, stream, out);
 }
 

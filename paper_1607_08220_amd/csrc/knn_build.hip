@@ -552,6 +552,133 @@ __global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict_
     }
 }
 
+// k_choose with one wavefront per node (kWavesPerBlock nodes per block), for
+// levels of many small nodes; same result.  Lane L holds the window entries
+// 5 L .. 5 L + 4.  The full-histogram path sorts the sample in registers and
+// counts in a per-wavefront LDS histogram.
+__global__ __launch_bounds__(kBlock) void k_choose_wave(Level L, int32_t* __restrict__ dimv,
+                                                        const float* __restrict__ samples,
+                                                        const uint32_t* __restrict__ hist,
+                                                        const float* __restrict__ cols, int64_t n,
+                                                        int d, float* __restrict__ splitv)
+{
+    __shared__ float sv_all[kWavesPerBlock][kSampleMax];
+    __shared__ uint32_t hf_all[kWavesPerBlock][kBins];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int node = blockIdx.x * kWavesPerBlock + w;
+    if (node >= L.cnt[0]) return;  // only wavefront-level synchronization below
+    const int64_t start = L.start[node], c = L.count[node];
+    const int s = (int)(c < kSampleMax ? c : kSampleMax);
+    const int dim = dimv[node];
+    // smallest key gap * 2048 + j over the valid j of this lane's entries
+    auto wave_key = [&](const uint32_t* v, int R, int j0, int jend) -> long long {
+        uint32_t sum = 0;
+        for (int r = 0; r < R; ++r) sum += v[r];
+        uint32_t x = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        uint32_t C = x - sum;
+        long long key = LLONG_MAX;
+        for (int r = 0; r < R; ++r) {
+            const int j = j0 + R * lane + r;
+            C += v[r];
+            if (j < jend && C > 0 && (int64_t)C < c) {
+                long long gap = 2 * (long long)C - c;
+                if (gap < 0) gap = -gap;
+                const long long kk = gap * 2048 + j;
+                if (kk < key) key = kk;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const long long y = __shfl_xor(key, o);
+            key = y < key ? y : key;
+        }
+        return key;
+    };
+    if (dim >= 0) {
+        int jl, jh;
+        sample_window(s, &jl, &jh);
+        const int nwin = jh - jl;
+        const uint32_t* row = hist + (int64_t)node * kWinRow;
+        uint32_t v[5];
+        uint64_t part = 0;
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const int e = 5 * lane + r;
+            v[r] = e <= nwin ? row[e] : 0u;
+            if (e >= 1) part += v[r];
+        }
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+        const uint64_t below = row[0];
+        const bool in_window = 2 * (int64_t)below <= c && 2 * (int64_t)(below + part) >= c;
+        float split;
+        if (in_window) {
+            const long long key = wave_key(v, 5, jl, jh + 1);
+            const int j = key == LLONG_MAX ? jl : (int)(key % 2048);
+            split = samples[(int64_t)node * kWinStride + (j - jl)];
+        } else {
+            float* sv = sv_all[w];
+            uint32_t* hf = hf_all[w];
+            const float* col = cols + (int64_t)dim * n + start;
+            float u[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = 16 * lane + r;
+                u[r] = j < s ? col[sample_pos(j, c, s)] : INFINITY;
+            }
+            wave_sort1024(u);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) sv[16 * lane + r] = u[r];
+            for (int i = lane; i < kBins; i += kWave) hf[i] = 0u;
+            wave_sync();
+            for (int64_t e = lane; e < c; e += kWave) {
+                const float x = col[e];
+                int pos = 0;  // number of sample values <= x
+                for (int step = kSampleMax; step > 0; step >>= 1) {
+                    const int np = pos + step;
+                    if (np <= s && sv[np - 1] <= x) pos = np;
+                }
+                atomicAdd(&hf[pos], 1u);
+            }
+            wave_sync();
+            uint32_t vf[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) vf[r] = 16 * lane + r < s ? hf[16 * lane + r] : 0u;
+            const long long key = wave_key(vf, 16, 0, s);
+            split = sv[key == LLONG_MAX ? 0 : (int)(key % 2048)];
+        }
+        if (lane == 0) splitv[node] = split;
+        return;
+    }
+    // the sample is constant in every dimension (see k_choose)
+    double bext = 0.0;
+    int bd = -1;
+    float bhi = 0.0f;
+    for (int dd = 0; dd < d; ++dd) {
+        const float* col = cols + (int64_t)dd * n + start;
+        float lo = INFINITY, hi = -INFINITY;
+        for (int64_t e = lane; e < c; e += kWave) {
+            const float x = col[e];
+            lo = fminf(lo, x);
+            hi = fmaxf(hi, x);
+        }
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        const double ext = (double)hi - (double)lo;
+        if (ext > bext) {
+            bext = ext;
+            bd = dd;
+            bhi = hi;
+        }
+    }
+    if (lane == 0) {
+        dimv[node] = bd;
+        splitv[node] = bhi;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // B6: stable partition -- count, per-node scan, scatter
 // ---------------------------------------------------------------------------
@@ -1265,28 +1392,31 @@ constexpr int kPlanBlock = 1024;
 // planx), by one block; the totals give the next level's sizes and advance
 // the id and subtree counters.  Every position comes from a prefix sum, so
 // ids and list order do not depend on thread timing.
-__global__ __launch_bounds__(kPlanBlock) void k_plan_scan(
-    Level cur, Level nxt, const int32_t* __restrict__ planv, int32_t* __restrict__ planx,
-    int32_t* __restrict__ g, int32_t* __restrict__ rng, int level, int64_t big_cap,
-    int64_t sub_cap, int64_t nn_cap, int64_t nb_cap, int64_t nbh_cap)
+// Exclusive scan of the per-node plan values, in two kernels: each block of
+// kPlanBlock nodes scans its own (coalesced, one node per thread) and leaves
+// its totals in pblk; k_plan_top scans the block totals, and k_plan_write
+// adds a node's block offset to its in-block prefix.
+__global__ __launch_bounds__(kPlanBlock) void k_plan_local(
+    Level cur, const int32_t* __restrict__ planv, int32_t* __restrict__ planx,
+    int32_t* __restrict__ pblk, int32_t* __restrict__ g)
 {
     __shared__ int wsum[kPlanBlock / 64][kPlanVals];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int nn = cur.cnt[0];
-    const int per = (nn + kPlanBlock - 1) / kPlanBlock;
-    const int i0 = t * per, i1 = min(nn, i0 + per);
-    int sum[kPlanVals] = {0, 0, 0, 0, 0};
+    const int i = blockIdx.x * kPlanBlock + t;
+    if (blockIdx.x * kPlanBlock >= nn) return;  // block-uniform
+    int v[kPlanVals] = {0, 0, 0, 0, 0};
     unsigned long long pts = 0;  // points this level partitions (profiling counter)
-    for (int i = i0; i < i1; ++i) {
+    if (i < nn) {
 #pragma unroll
-        for (int k = 0; k < kPlanVals; ++k) sum[k] += planv[(int64_t)i * kPlanStride + k];
-        pts += (unsigned long long)cur.count[i];
+        for (int k = 0; k < kPlanVals; ++k) v[k] = planv[(int64_t)i * kPlanStride + k];
+        pts = (unsigned long long)cur.count[i];
     }
     for (int o = 32; o > 0; o >>= 1) pts += __shfl_xor(pts, o);
     if (lane == 0 && pts) atomicAdd(reinterpret_cast<unsigned long long*>(g + G_MOVED), pts);
     int x[kPlanVals];
 #pragma unroll
-    for (int k = 0; k < kPlanVals; ++k) x[k] = sum[k];
+    for (int k = 0; k < kPlanVals; ++k) x[k] = v[k];
     for (int o = 1; o < 64; o <<= 1) {
 #pragma unroll
         for (int k = 0; k < kPlanVals; ++k) {
@@ -1298,7 +1428,6 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scan(
 #pragma unroll
         for (int k = 0; k < kPlanVals; ++k) wsum[w][k] = x[k];
     __syncthreads();
-    int run[kPlanVals], tot[kPlanVals];
 #pragma unroll
     for (int k = 0; k < kPlanVals; ++k) {
         int base = 0, all = 0;
@@ -1306,16 +1435,53 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scan(
             if (j < w) base += wsum[j][k];
             all += wsum[j][k];
         }
-        run[k] = base + x[k] - sum[k];
-        tot[k] = all;
+        if (i < nn) planx[(int64_t)i * kPlanStride + k] = base + x[k] - v[k];
+        if (t == 0) pblk[(int64_t)blockIdx.x * kPlanStride + k] = all;
     }
-    for (int i = i0; i < i1; ++i)
+}
+
+__global__ __launch_bounds__(kPlanBlock) void k_plan_top(
+    Level cur, Level nxt, int32_t* __restrict__ pblk, int32_t* __restrict__ g,
+    int32_t* __restrict__ rng, int level, int64_t big_cap, int64_t sub_cap, int64_t nn_cap,
+    int64_t nb_cap, int64_t nbh_cap)
+{
+    __shared__ int wsum[kPlanBlock / 64][kPlanVals];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int nblk = (cur.cnt[0] + kPlanBlock - 1) / kPlanBlock;
+    int carry[kPlanVals] = {0, 0, 0, 0, 0};
+    for (int b0 = 0; b0 < nblk; b0 += kPlanBlock) {  // exclusive scan of the block totals
+        const int b = b0 + t;
+        int v[kPlanVals], x[kPlanVals];
 #pragma unroll
         for (int k = 0; k < kPlanVals; ++k) {
-            planx[(int64_t)i * kPlanStride + k] = run[k];
-            run[k] += planv[(int64_t)i * kPlanStride + k];
+            v[k] = b < nblk ? pblk[(int64_t)b * kPlanStride + k] : 0;
+            x[k] = v[k];
         }
+        for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+            for (int k = 0; k < kPlanVals; ++k) {
+                const int y = __shfl_up(x[k], o);
+                if (lane >= o) x[k] += y;
+            }
+        }
+        if (lane == 63)
+#pragma unroll
+            for (int k = 0; k < kPlanVals; ++k) wsum[w][k] = x[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPlanVals; ++k) {
+            int base = 0, all = 0;
+            for (int j = 0; j < kPlanBlock / 64; ++j) {
+                if (j < w) base += wsum[j][k];
+                all += wsum[j][k];
+            }
+            if (b < nblk) pblk[(int64_t)b * kPlanStride + k] = carry[k] + base + x[k] - v[k];
+            carry[k] += all;
+        }
+        __syncthreads();
+    }
     if (t == 0) {
+        const int* tot = carry;
         const int base_id = g[G_NEXT_ID], base_sub = g[G_NSUB];
         g[G_BASE_ID] = base_id;
         g[G_BASE_SUB] = base_sub;
@@ -1340,15 +1506,18 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scan(
 // all coincide as oversized buckets.
 __global__ __launch_bounds__(kBlock) void k_plan_write(
     Level cur, Level nxt, const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
-    const int32_t* __restrict__ nleft, const int32_t* __restrict__ planx, int leaf, int W,
-    int max_depth, int nbuf, NodeRec* __restrict__ big, SubEntry* __restrict__ subs,
-    int32_t* __restrict__ g)
+    const int32_t* __restrict__ nleft, const int32_t* __restrict__ planx,
+    const int32_t* __restrict__ pblk, int leaf, int W, int max_depth, int nbuf,
+    NodeRec* __restrict__ big, SubEntry* __restrict__ subs, int32_t* __restrict__ g)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cur.cnt[0] || g[G_ERR] == kErrOverflow) return;
     const int st = cur.start[i], cnt = cur.count[i], id = cur.id[i];
     const int par = cur.parent[i], dep = cur.depth[i], dm = dimv[i];
-    const int* x = planx + (int64_t)i * kPlanStride;
+    int x[kPlanVals];
+#pragma unroll
+    for (int k = 0; k < kPlanVals; ++k)
+        x[k] = planx[(int64_t)i * kPlanStride + k] + pblk[(int64_t)(i / kPlanBlock) * kPlanStride + k];
     const int base_id = g[G_BASE_ID], base_sub = g[G_BASE_SUB];
     if (dm < 0) {  // all points identical: an oversized bucket
         subs[base_sub + x[2]] = SubEntry{st, cnt, id, par, nbuf, 1, dep, 0};
@@ -1475,7 +1644,7 @@ int32_t default_subtree_points(int32_t d)
 }
 
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
-               int32_t W, hipStream_t st, knn_tree** out)
+               int32_t W, int64_t split_block_nodes, hipStream_t st, knn_tree** out)
 {
     prof_mark(st, 0);
     prof_part_begin();
@@ -1517,7 +1686,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     const int64_t sub_cap = std::min<int64_t>(n, big_cap);
     LevelMem lvA(st), lvB(st);
     DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), wave_left(st), blk_off(st),
-        d_big(st), d_subs(st), d_rng(st), planv(st), planx(st);
+        d_big(st), d_subs(st), d_rng(st), planv(st), planx(st), pblk(st);
     int32_t n_sub = 0, n_big = 1, n_levels = 0;
     std::vector<int32_t> h_g(G_COUNT, 0);
     if (!needs_level(n)) {
@@ -1539,6 +1708,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
         KNN_HIP(planv.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
         KNN_HIP(planx.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
+        KNN_HIP(pblk.alloc(sizeof(int32_t) * kPlanStride * ((nn_cap + kPlanBlock - 1) / kPlanBlock)));
         KNN_HIP(d_big.alloc(sizeof(NodeRec) * big_cap));
         KNN_HIP(d_subs.alloc(sizeof(SubEntry) * sub_cap));
         KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2 * (lv_cap + 1)));
@@ -1593,8 +1763,13 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                                               dimv.as<int32_t>(), hist.as<uint32_t>());
             k_hist<<<g_nbh, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), samples.as<float>(), src, n,
                                              hist.as<uint32_t>());
-            k_choose<<<g_nn, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), samples.as<float>(),
-                                              hist.as<uint32_t>(), src, n, d, splitv.as<float>());
+            if (nn_l <= split_block_nodes)  // few large nodes: a block each
+                k_choose<<<g_nn, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), samples.as<float>(),
+                                                  hist.as<uint32_t>(), src, n, d, splitv.as<float>());
+            else
+                k_choose_wave<<<(g_nn + kWavesPerBlock - 1) / kWavesPerBlock, kBlock, 0, st>>>(
+                    cur, dimv.as<int32_t>(), samples.as<float>(), hist.as<uint32_t>(), src, n, d,
+                    splitv.as<float>());
             k_count<<<g_nb, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), splitv.as<float>(), src, n,
                                              wave_left.as<uint32_t>());
             k_blkscan<<<g_nn, kBlock, 0, st>>>(cur, wave_left.as<uint32_t>(), dimv.as<int32_t>(), W,
@@ -1605,13 +1780,15 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                                                blk_off.as<uint32_t>(), nleft.as<int32_t>(), src,
                                                srci, dst, dsti, n, d);
             prof_part_mark(st);
-            k_plan_scan<<<1, kPlanBlock, 0, st>>>(cur, nxt, planv.as<int32_t>(), planx.as<int32_t>(),
-                                                  g, d_rng.as<int32_t>(), level, big_cap, sub_cap,
-                                                  nn_cap, nb_cap, nbh_cap);
+            k_plan_local<<<blocks_for(nn_l, kPlanBlock), kPlanBlock, 0, st>>>(
+                cur, planv.as<int32_t>(), planx.as<int32_t>(), pblk.as<int32_t>(), g);
+            k_plan_top<<<1, kPlanBlock, 0, st>>>(cur, nxt, pblk.as<int32_t>(), g,
+                                                 d_rng.as<int32_t>(), level, big_cap, sub_cap,
+                                                 nn_cap, nb_cap, nbh_cap);
             k_plan_write<<<blocks_for(nn_l, kBlock), kBlock, 0, st>>>(
                 cur, nxt, dimv.as<int32_t>(), splitv.as<float>(), nleft.as<int32_t>(),
-                planx.as<int32_t>(), leaf, W, max_depth, buf ^ 1, d_big.as<NodeRec>(),
-                d_subs.as<SubEntry>(), g);
+                planx.as<int32_t>(), pblk.as<int32_t>(), leaf, W, max_depth, buf ^ 1,
+                d_big.as<NodeRec>(), d_subs.as<SubEntry>(), g);
             {
                 const int64_t nn_next = std::min<int64_t>(2 * nn_l, nn_cap);
                 const int64_t fill = std::min<int64_t>(n / kChunk + nn_next + 1, nb_cap);
@@ -1641,6 +1818,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         }
         lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); wave_left.reset();
         blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset(); planv.reset(); planx.reset();
+        pblk.reset();
     }
     prof_mark(st, 2);
 

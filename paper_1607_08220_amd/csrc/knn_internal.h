@@ -27,6 +27,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kSampleMax = 1024;   // sample points per node (Section III-A1)
 constexpr int kDefaultLeaf = 32;   // bucket size the paper found best
 constexpr int kDefaultMaxDepth = 64;
+constexpr int64_t kDefaultSplitBlockNodes = 256;  // see knn_build_params.split_block_nodes
 constexpr int kDefaultLeafBatch = 48;
 constexpr int kRowPad = 8;  // zero rows after the last bucket row: whole row batches may be loaded  // lanes of 64 holding a bucket before a wavefront scans
 
@@ -115,7 +116,7 @@ int32_t finish_max_points(int32_t d);
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w);
 
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
-               int32_t sub_pts, hipStream_t stream, knn_tree** out);
+               int32_t W, int64_t split_block_nodes, hipStream_t stream, knn_tree** out);
 int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
                const int32_t* self_ids, float r2, int32_t order, int32_t batch,
                int32_t* out_idx, float* out_d2, unsigned long long* stats, hipStream_t stream);

@@ -22,13 +22,14 @@ def dev(a, dtype=None):
 
 
 def gpu_knn(points, queries, k, leaf=32, self_ids=None, r2=np.inf, order=0, tree=None,
-            subtree_points=0):
+            subtree_points=0, split_block_nodes=0):
     """Build (unless a tree is given) and query through the C-ABI; host arrays out."""
     import torch
     import paper_1607_08220_amd as knn
     P = dev(np.asarray(points, np.float32))
     if tree is None:
-        tree = knn.knn_build_ex(P, leaf_size=leaf, subtree_points=subtree_points)
+        tree = knn.knn_build_ex(P, leaf_size=leaf, subtree_points=subtree_points,
+                                split_block_nodes=split_block_nodes)
         check_links(tree.export(), len(points))
     Q = dev(np.asarray(queries, np.float32))
     S = dev(np.asarray(self_ids, np.int32)) if self_ids is not None else None

@@ -28,11 +28,13 @@ def knn():
     return knn
 
 
-def _full_check(knn, X, Q, k, leaf, self_ids=None, r2=np.inf, what="", subtree_points=0):
+def _full_check(knn, X, Q, k, leaf, self_ids=None, r2=np.inf, what="", subtree_points=0,
+                split_block_nodes=0):
     log(f"[case] {what} n={len(X)} d={X.shape[1]} m={len(Q)} k={k} leaf={leaf} "
-        f"self={self_ids is not None} r2={r2} W={subtree_points}")
+        f"self={self_ids is not None} r2={r2} W={subtree_points} sbn={split_block_nodes}")
     T = oracle.build(X, leaf)
-    _, _, tree = gpu_knn(X, Q[:1], 1, leaf=leaf, subtree_points=subtree_points)
+    _, _, tree = gpu_knn(X, Q[:1], 1, leaf=leaf, subtree_points=subtree_points,
+                         split_block_nodes=split_block_nodes)
     g = tree.export()
     check_tree(X, g, leaf)
     compare_trees(g, T)
@@ -129,7 +131,9 @@ def test_ragged_sizes_span_level_passes(knn, d, leaf, k):
     else:
         X = inputs.corr_gauss(n, d, seed=78)
     ids = rng.choice(n, 3_001, replace=False).astype(np.int32)
-    _full_check(knn, X, X[ids], k, leaf, self_ids=ids, what=f"ragged d={d}")
+    # some cases choose every split with one wavefront per node
+    sbn = -1 if d in (4, 10, 1) else 0
+    _full_check(knn, X, X[ids], k, leaf, self_ids=ids, what=f"ragged d={d}", split_block_nodes=sbn)
 
 
 def test_small_subtree_width(knn):
@@ -167,7 +171,9 @@ def test_split_outside_sample_window(knn):
         lo = (rng.random(2048) * 0.001).astype(np.float32)
         x[0::2], x[1::2] = (hi, lo) if big_even else (lo, hi)
         X = np.stack([x, (rng.random(4096) * 1e-4).astype(np.float32)], 1)
-        _full_check(knn, X, X[::7], 5, 32, self_ids=np.arange(0, 4096, 7), what=f"window big_even={big_even}")
+        for sbn in (0, -1):  # split chosen by a workgroup, then by a wavefront
+            _full_check(knn, X, X[::7], 5, 32, self_ids=np.arange(0, 4096, 7),
+                        what=f"window big_even={big_even}", split_block_nodes=sbn)
 
 
 def test_determinism_and_order_independence(knn):
