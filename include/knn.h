@@ -152,6 +152,36 @@ int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
                  const int32_t* self_ids, float r2_max, const knn_query_params* p,
                  int32_t* out_idx, float* out_dist2, void* stream);
 
+/*
+ * knn_query_radius -- knn_query_ex with one search radius per query: only
+ * points with D < r2[i] qualify for query i.  This is Algorithm 1 with its
+ * input r given per query, as in the remote step of the distributed query
+ * (Section III-B, steps 2 and 4): a query arrives with r' = the k-th distance
+ * found on its owner, and the search prunes everything at or beyond it.
+ *   r2  device pointer [m] FP32 squared radii (+inf = none; a NaN or a value
+ *       <= 0 admits no point)
+ * Other arguments and errors as knn_query_ex.
+ */
+int knn_query_radius(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+                     const int32_t* self_ids, const float* r2, const knn_query_params* p,
+                     int32_t* out_idx, float* out_dist2, void* stream);
+
+/*
+ * knn_merge -- the k nearest of two candidate lists per query (Section III-B,
+ * step 5: the local and the remote neighbours are merged by distance).
+ *   idx_a, dist2_a  device pointers [m, ka]: one list per query, ascending by
+ *                   (D, idx), padded at the end with (idx -1, D +inf)
+ *   idx_b, dist2_b  device pointers [m, kb], the same form
+ *   out_idx, out_dist2  device pointers [m, k]: the k smallest (D, idx) keys
+ *                   of both lists, ascending, padded with (-1, +inf); an entry
+ *                   present in both lists (same D and idx) counts once
+ * ka, kb, k: 1 .. KNN_MAX_K.  The output may not alias an input.  Work is
+ * enqueued on `stream`.  Errors: KNN_EINVAL, KNN_EDEVICE.
+ */
+int knn_merge(const int32_t* idx_a, const float* dist2_a, int32_t ka, const int32_t* idx_b,
+              const float* dist2_b, int32_t kb, int64_t m, int32_t k, int32_t* out_idx,
+              float* out_dist2, void* stream);
+
 /* Free a tree and its device memory (waits for the device first).  NULL is OK. */
 int knn_tree_free(knn_tree* t);
 

@@ -57,9 +57,9 @@ class _Host(ctypes.Structure):
 
 
 _lib = None
-EXPORTED = ("knn_build", "knn_build_ex", "knn_query", "knn_query_ex", "knn_tree_free",
-            "knn_tree_info", "knn_tree_export", "knn_last_error", "knn_set_profiling",
-            "knn_get_profile")
+EXPORTED = ("knn_build", "knn_build_ex", "knn_query", "knn_query_ex", "knn_query_radius",
+            "knn_merge", "knn_tree_free", "knn_tree_info", "knn_tree_export", "knn_last_error",
+            "knn_set_profiling", "knn_get_profile")
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -78,6 +78,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.knn_query.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     lib.knn_query_ex.argtypes = [vp, vp, i64, i32, vp, ctypes.c_float,
                                  ctypes.POINTER(_QueryParams), vp, vp, vp]
+    lib.knn_query_radius.argtypes = [vp, vp, i64, i32, vp, vp, ctypes.POINTER(_QueryParams), vp,
+                                     vp, vp]
+    lib.knn_merge.argtypes = [vp, vp, i32, vp, vp, i32, i64, i32, vp, vp, vp]
     lib.knn_tree_free.argtypes = [vp]
     lib.knn_tree_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.knn_tree_export.argtypes = [vp, ctypes.POINTER(_Host)]
@@ -223,6 +226,58 @@ def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = mat
                             ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
                             _stream(queries)))
     return idx, d2
+
+
+def _dev_i32_vec(t, name, m):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32
+            and t.is_contiguous() and t.shape == (m,)):
+        raise TypeError(f"{name} must be a contiguous CUDA int32 [{m}] tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def knn_query_radius(tree: Tree, queries, k: int, r2, self_ids=None, order: int = 0, out=None,
+                     leaf_batch: int = 0):
+    """k nearest neighbours with one squared radius per query (CUDA float32 [m])."""
+    import torch
+    lib = load_library()
+    _dev_f32(queries, "queries", tree.dim)
+    m = queries.shape[0]
+    if not (isinstance(r2, torch.Tensor) and r2.is_cuda and r2.dtype == torch.float32
+            and r2.is_contiguous() and r2.shape == (m,)):
+        raise TypeError("r2 must be a contiguous CUDA float32 [m] tensor")
+    idx, d2 = _outputs(queries, k, out)
+    sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
+    p = _QueryParams(order, leaf_batch, None)
+    _check(lib.knn_query_radius(tree.handle, ctypes.c_void_p(queries.data_ptr()), m, k, sp,
+                                ctypes.c_void_p(r2.data_ptr()), ctypes.byref(p),
+                                ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                                _stream(queries)))
+    return idx, d2
+
+
+def knn_merge(a, b, k: int, out=None):
+    """Merge two (idx int32 [m,ka], dist2 float32 [m,ka]) lists into the k nearest."""
+    import torch
+    lib = load_library()
+    (ia, da), (ib, db) = a, b
+    m = ia.shape[0]
+    for t, dt in ((ia, torch.int32), (da, torch.float32), (ib, torch.int32), (db, torch.float32)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.dim() == 2
+                and t.is_contiguous() and t.shape[0] == m):
+            raise TypeError("lists must be contiguous CUDA (int32, float32) [m, k] tensors")
+    if ia.shape != da.shape or ib.shape != db.shape:
+        raise ValueError("index and distance lists differ in shape")
+    if out is None:
+        out = (torch.empty((m, k), dtype=torch.int32, device=ia.device),
+               torch.empty((m, k), dtype=torch.float32, device=ia.device))
+    oi, od = out
+    _check(lib.knn_merge(ctypes.c_void_p(ia.data_ptr()), ctypes.c_void_p(da.data_ptr()),
+                         ia.shape[1], ctypes.c_void_p(ib.data_ptr()),
+                         ctypes.c_void_p(db.data_ptr()), ib.shape[1], m, k,
+                         ctypes.c_void_p(oi.data_ptr()), ctypes.c_void_p(od.data_ptr()),
+                         _stream(ia)))
+    return oi, od
 
 
 def knn_tree_info(tree: Tree) -> dict:

@@ -131,9 +131,11 @@ int knn_build(const float* points, int64_t n, int32_t dim, int32_t leaf_size, vo
     return knn_build_ex(points, n, dim, &p, stream, out);
 }
 
-int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
-                 const int32_t* self_ids, float r2_max, const knn_query_params* p,
-                 int32_t* out_idx, float* out_dist2, void* stream)
+namespace {
+
+int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+                 const int32_t* self_ids, float r2_max, const float* r2s,
+                 const knn_query_params* p, int32_t* out_idx, float* out_dist2, void* stream)
 {
     if (!t) return fail(KNN_EINVAL, "tree is NULL");
     if (m < 0) return fail(KNN_EINVAL, "m must be >= 0");
@@ -147,9 +149,51 @@ int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     const int32_t batch = p && p->leaf_batch ? p->leaf_batch : kDefaultLeafBatch;
     if (batch < 1 || batch > 64) return fail(KNN_EINVAL, "leaf_batch must be in [0, 64]");
     DeviceGuard g(t->device);
-    unsigned long long* stats = p ? reinterpret_cast<unsigned long long*>(p->stats) : nullptr;
-    return query_tree(t, queries, m, k, self_ids, r2_max, order, batch, out_idx, out_dist2,
-                      stats, static_cast<hipStream_t>(stream));
+    QuerySpec qs;
+    qs.queries = queries;
+    qs.m = m;
+    qs.k = k;
+    qs.self_ids = self_ids;
+    qs.r2 = r2_max;
+    qs.r2s = r2s;
+    qs.order = order;
+    qs.batch = batch;
+    qs.out_idx = out_idx;
+    qs.out_d2 = out_dist2;
+    qs.stats = p ? reinterpret_cast<unsigned long long*>(p->stats) : nullptr;
+    return query_tree(t, qs, static_cast<hipStream_t>(stream));
+}
+
+}  // namespace
+
+int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+                 const int32_t* self_ids, float r2_max, const knn_query_params* p,
+                 int32_t* out_idx, float* out_dist2, void* stream)
+{
+    return query_common(t, queries, m, k, self_ids, r2_max, nullptr, p, out_idx, out_dist2,
+                        stream);
+}
+
+int knn_query_radius(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+                     const int32_t* self_ids, const float* r2, const knn_query_params* p,
+                     int32_t* out_idx, float* out_dist2, void* stream)
+{
+    if (m > 0 && !r2) return fail(KNN_EINVAL, "r2 is NULL");
+    return query_common(t, queries, m, k, self_ids, INFINITY, r2, p, out_idx, out_dist2, stream);
+}
+
+int knn_merge(const int32_t* idx_a, const float* dist2_a, int32_t ka, const int32_t* idx_b,
+              const float* dist2_b, int32_t kb, int64_t m, int32_t k, int32_t* out_idx,
+              float* out_dist2, void* stream)
+{
+    if (m < 0) return fail(KNN_EINVAL, "m must be >= 0");
+    if (k < 1 || k > KNN_MAX_K || ka < 1 || ka > KNN_MAX_K || kb < 1 || kb > KNN_MAX_K)
+        return fail(KNN_EINVAL, "ka, kb and k must be in [1, 64]");
+    if (m == 0) return KNN_OK;
+    if (!idx_a || !dist2_a || !idx_b || !dist2_b || !out_idx || !out_dist2)
+        return fail(KNN_EINVAL, "NULL list pointer");
+    return merge_lists(idx_a, dist2_a, ka, idx_b, dist2_b, kb, m, k, out_idx, out_dist2,
+                       static_cast<hipStream_t>(stream));
 }
 
 int knn_query(const knn_tree* t, const float* queries, int64_t m, int32_t k, int32_t* out_idx,

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -117,8 +118,27 @@ size_t finish_lds_bytes_per_wave(int32_t d, int32_t w);
 
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
                int32_t W, int64_t split_block_nodes, hipStream_t stream, knn_tree** out);
-int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
-               const int32_t* self_ids, float r2, int32_t order, int32_t batch,
-               int32_t* out_idx, float* out_d2, unsigned long long* stats, hipStream_t stream);
+// One batch of queries against a tree (or forest).  Per-query arrays are
+// device pointers indexed by query; NULL selects the scalar.
+struct QuerySpec {
+    const float* queries = nullptr;  // [m][d]
+    int64_t m = 0;
+    int32_t k = 1;                   // k, or the largest per-query k
+    const int32_t* self_ids = nullptr;
+    float r2 = INFINITY;
+    const float* r2s = nullptr;      // per-query squared radius
+    const int32_t* qk = nullptr;     // per-query k
+    const int64_t* qout = nullptr;   // per-query first output element
+    const int32_t* qroot = nullptr;  // per-query root node (forests)
+    int32_t order = 0;
+    int32_t batch = 48;
+    int32_t* out_idx = nullptr;
+    float* out_d2 = nullptr;
+    unsigned long long* stats = nullptr;
+};
+
+int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t stream);
+int merge_lists(const int32_t* ia, const float* da, int ka, const int32_t* ib, const float* db,
+                int kb, int64_t m, int k, int32_t* oi, float* od, hipStream_t stream);
 
 }  // namespace knn

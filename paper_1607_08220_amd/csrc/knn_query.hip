@@ -164,6 +164,33 @@ __device__ inline bool ball_inside(const float (&q)[D], const float (&b)[2 * D],
     return in;
 }
 
+}  // namespace
+
+// Arguments of one traversal launch.  Per-query arrays are indexed by the
+// query's position in `queries`; NULL selects the scalar beside it.
+struct TravArgs {
+    const NodeRec* nodes;
+    const float* bbox;
+    const float* pts;
+    const float* queries;   // [m][D]
+    const int32_t* order;   // slot -> query (NULL: identity)
+    const int32_t* home;    // slot -> home leaf (NULL: start at the query's root)
+    const int32_t* root;    // per-query root node (a forest's tree), else node 0
+    const int32_t* self_ids;
+    const float* r2s;       // per-query squared radius, else r2
+    const int32_t* qk;      // per-query k (<= the kernel's capacity), else k
+    const int64_t* qout;    // per-query first output element, else query * k
+    float r2;
+    int k;
+    int batch;
+    int64_t m;
+    int32_t* out_idx;
+    float* out_d2;
+    unsigned long long* stats;
+};
+
+namespace {
+
 // STATS adds visit counters summed per wavefront into stats[0..8]: per lane
 // (nodes entered from above, leaves scanned, points scanned, traversal steps,
 // heap inserts) and per wavefront (traversal-loop iterations, bucket-row
@@ -181,14 +208,18 @@ __device__ inline bool ball_inside(const float (&q)[D], const float (&b)[2 * D],
 // A lane whose search ball lies inside the tight box of the node it is
 // leaving upwards stops: every point outside that box is farther than r'.
 template <int D, int KC, bool STATS, int RB>
-__global__ __launch_bounds__(kBlock) void k_traverse(
-    const NodeRec* __restrict__ nodes, const float* __restrict__ bbox,
-    const float* __restrict__ pts, const float* __restrict__ queries,
-    const int32_t* __restrict__ order, const int32_t* __restrict__ home,
-    const int32_t* __restrict__ self_ids, int64_t m, int k, float r2, int batch,
-    int32_t* __restrict__ out_idx, float* __restrict__ out_d2,
-    unsigned long long* __restrict__ stats)
+__global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
 {
+    const NodeRec* __restrict__ nodes = A.nodes;
+    const float* __restrict__ bbox = A.bbox;
+    const float* __restrict__ pts = A.pts;
+    const float* __restrict__ queries = A.queries;
+    const int32_t* __restrict__ order = A.order;
+    const int32_t* __restrict__ home = A.home;
+    const int32_t* __restrict__ self_ids = A.self_ids;
+    const int64_t m = A.m;
+    const int batch = A.batch;
+    unsigned long long* __restrict__ stats = A.stats;
     // XCD-aware order: consecutive blocks are dispatched to the 8 XCDs in
     // turn, so block b takes chunk (b % 8) * per + b / 8 -- each XCD then
     // walks one contiguous range of the grouped queries and their leaves
@@ -205,11 +236,13 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     for (int t = 0; t < D; ++t) q[t] = queries[qid * D + t];
     const int32_t self = self_ids ? self_ids[qid] : -1;
     uint64_t h[KC];
+    const int k = A.qk ? A.qk[qid] : A.k;
     const int pad = KC - k;
+    const float r2 = A.r2s ? A.r2s[qid] : A.r2;
     const uint64_t empty = r2 > 0.0f ? make_key(r2, 0) : 0;
 #pragma unroll
     for (int j = 0; j < KC; ++j) h[j] = j < pad ? 0 : empty;
-    int cur = home ? home[slot] : 0;
+    int cur = home ? home[slot] : (A.root ? A.root[qid] : 0);
     int from = -1;  // -1: arrived from the parent; otherwise the child we came from
     // The record and box of `cur` are loaded at the end of the step that moves
     // there, together, so one memory latency is exposed per step.
@@ -340,10 +373,10 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
 #pragma unroll
     for (int j = 0; j < KC; ++j) {
         if (j >= pad) {
-            const int64_t o = qid * k + (j - pad);
+            const int64_t o = (A.qout ? A.qout[qid] : qid * k) + (j - pad);
             const bool none = h[j] == empty;
-            out_idx[o] = none ? -1 : (int)(uint32_t)h[j];
-            out_d2[o] = none ? INFINITY : key_dist(h[j]);
+            A.out_idx[o] = none ? -1 : (int)(uint32_t)h[j];
+            A.out_d2[o] = none ? INFINITY : key_dist(h[j]);
         }
     }
     }  // slot < m
@@ -368,7 +401,8 @@ constexpr int kLocQ = 4;
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ nodes,
-                                                   const float* __restrict__ queries, int64_t m,
+                                                   const float* __restrict__ queries,
+                                                   const int32_t* __restrict__ qroot, int64_t m,
                                                    int shift, int32_t* __restrict__ home,
                                                    uint32_t* __restrict__ cnt)
 {
@@ -381,12 +415,13 @@ __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ n
         const int64_t i = min(i0 + (int64_t)u * kBlock, m - 1);  // clamped: extra lanes repeat
 #pragma unroll
         for (int t = 0; t < D; ++t) q[u][t] = queries[i * D + t];
-        cur[u] = 0;
+        cur[u] = qroot ? qroot[i] : 0;
     }
-    const NodeRec root = nodes[0];
 #pragma unroll
-    for (int u = 0; u < kLocQ; ++u) r[u] = root;
-    bool inner = root.dim >= 0;
+    for (int u = 0; u < kLocQ; ++u) r[u] = nodes[cur[u]];
+    bool inner = false;
+#pragma unroll
+    for (int u = 0; u < kLocQ; ++u) inner = inner || r[u].dim >= 0;
     while (inner) {
         inner = false;
 #pragma unroll
@@ -496,10 +531,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t* __restrict__ a, i
     if (i < len) a[i] += bsum[i / kScanChunk];
 }
 
-using TraverseFn = void (*)(const NodeRec*, const float*, const float*, const float*,
-                            const int32_t*, const int32_t*, const int32_t*, int64_t, int, float,
-                            int, int32_t*, float*, unsigned long long*);
-using LocateFn = void (*)(const NodeRec*, const float*, int64_t, int, int32_t*, uint32_t*);
+using TraverseFn = void (*)(TravArgs);
+using LocateFn = void (*)(const NodeRec*, const float*, const int32_t*, int64_t, int, int32_t*,
+                          uint32_t*);
 
 template <int D, bool STATS>
 TraverseFn pick_traverse(int k)
@@ -555,43 +589,101 @@ struct StreamBuf {
 
 }  // namespace
 
-int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
-               const int32_t* self_ids, float r2, int32_t order, int32_t batch,
-               int32_t* out_idx, float* out_d2, unsigned long long* stats, hipStream_t st)
+namespace {
+
+// One thread per query: a two-way merge of two ascending (D, idx) lists,
+// skipping padding (idx < 0) and an entry equal to the one just written.
+__global__ __launch_bounds__(kBlock) void k_merge(const int32_t* __restrict__ ia,
+                                                  const float* __restrict__ da, int ka,
+                                                  const int32_t* __restrict__ ib,
+                                                  const float* __restrict__ db, int kb, int64_t m,
+                                                  int k, int32_t* __restrict__ oi,
+                                                  float* __restrict__ od)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    ia += q * ka;
+    da += q * ka;
+    ib += q * kb;
+    db += q * kb;
+    oi += q * k;
+    od += q * k;
+    int i = 0, j = 0, o = 0;
+    int last_i = -1;
+    float last_d = 0.0f;
+    while (o < k) {
+        const bool a_ok = i < ka && ia[i] >= 0;
+        const bool b_ok = j < kb && ib[j] >= 0;
+        if (!a_ok && !b_ok) break;
+        bool take_a;
+        if (!b_ok) take_a = true;
+        else if (!a_ok) take_a = false;
+        else take_a = da[i] < db[j] || (da[i] == db[j] && ia[i] <= ib[j]);
+        const int id = take_a ? ia[i] : ib[j];
+        const float dv = take_a ? da[i] : db[j];
+        if (take_a) ++i;
+        else ++j;
+        if (o > 0 && id == last_i && dv == last_d) continue;  // the same entry in both lists
+        oi[o] = id;
+        od[o] = dv;
+        last_i = id;
+        last_d = dv;
+        ++o;
+    }
+    for (; o < k; ++o) {
+        oi[o] = -1;
+        od[o] = INFINITY;
+    }
+}
+
+}  // namespace
+
+int merge_lists(const int32_t* ia, const float* da, int ka, const int32_t* ib, const float* db,
+                int kb, int64_t m, int k, int32_t* oi, float* od, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_merge, dim3(grid), dim3(kBlock), 0, st, ia, da, ka, ib, db, kb, m, k, oi, od);
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
+int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
 {
     const int d = t->d;
-    TraverseFn tf = traverse_for(d, k, stats != nullptr);
+    const int64_t m = qs.m;
+    TraverseFn tf = traverse_for(d, qs.k, qs.stats != nullptr);
     LocateFn lf = locate_for(d);
     if (!tf || !lf) return fail(KNN_EINVAL, "unsupported dimension");
     prof_mark(st, 5);
     const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
     const unsigned tgrid = (unsigned)((grid + kXcds - 1) / kXcds * kXcds);  // multiple of 8
+    const bool grouped = qs.order != 1;
     // key range: packed positions >> shift, at most 2^22 buckets
     int shift = 0;
     while ((t->n >> shift) > (int64_t(1) << 22)) ++shift;
-    const int64_t N = order == 1 ? 0 : (t->n >> shift) + 1;
+    const int64_t N = grouped ? (t->n >> shift) + 1 : 0;
     const int64_t nsb = (N + kScanChunk - 1) / kScanChunk;
-    const int64_t mg = order == 1 ? 0 : m;
+    const int64_t mg = grouped ? m : 0;
     // workspace: cnt[N], block sums[nsb], home[m], order[m], shome[m]
     const size_t bytes = sizeof(uint32_t) * (size_t)(N + nsb) + sizeof(int32_t) * 3 * (size_t)mg;
     StreamBuf ws;
     ws.s = st;
-    KNN_HIP(hipMallocAsync(&ws.p, bytes, st));
+    if (bytes) KNN_HIP(hipMallocAsync(&ws.p, bytes, st));
     uint32_t* cnt = static_cast<uint32_t*>(ws.p);
     uint32_t* bsum = cnt + N;
     int32_t* home = reinterpret_cast<int32_t*>(bsum + nsb);
     int32_t* ord = home + mg;
     int32_t* shome = ord + mg;
-    if (order != 1) {
+    if (grouped) {
         // cleared by a kernel, not a memset node, so the call can be captured in a graph
         k_zero<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N);
         const unsigned lgrid = (unsigned)((m + kBlock * kLocQ - 1) / (kBlock * kLocQ));
-        hipLaunchKernelGGL(lf, dim3(lgrid), dim3(kBlock), 0, st, t->nodes, queries, m, shift, home,
-                           cnt);
+        hipLaunchKernelGGL(lf, dim3(lgrid), dim3(kBlock), 0, st, t->nodes, qs.queries, qs.qroot, m,
+                           shift, home, cnt);
         KNN_HIP(hipGetLastError());
     }
     prof_mark(st, 6);
-    if (order != 1) {
+    if (grouped) {
         k_scan_local<<<(unsigned)nsb, kBlock, 0, st>>>(cnt, N, bsum);
         k_scan_sums<<<1, kBlock, 0, st>>>(bsum, nsb);
         k_scan_add<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N, bsum);
@@ -599,10 +691,26 @@ int query_tree(const knn_tree* t, const float* queries, int64_t m, int32_t k,
         KNN_HIP(hipGetLastError());
     }
     prof_mark(st, 7);
-    const int32_t* o = order == 1 ? nullptr : ord;
-    const int32_t* hm = order == 1 ? nullptr : shome;
-    hipLaunchKernelGGL(tf, dim3(tgrid), dim3(kBlock), 0, st, t->nodes, t->bbox, t->pts, queries,
-                       o, hm, self_ids, m, k, r2, batch, out_idx, out_d2, stats);
+    TravArgs A{};
+    A.nodes = t->nodes;
+    A.bbox = t->bbox;
+    A.pts = t->pts;
+    A.queries = qs.queries;
+    A.order = grouped ? ord : nullptr;
+    A.home = grouped ? shome : nullptr;
+    A.root = qs.qroot;
+    A.self_ids = qs.self_ids;
+    A.r2s = qs.r2s;
+    A.qk = qs.qk;
+    A.qout = qs.qout;
+    A.r2 = qs.r2;
+    A.k = qs.k;
+    A.batch = qs.batch;
+    A.m = m;
+    A.out_idx = qs.out_idx;
+    A.out_d2 = qs.out_d2;
+    A.stats = qs.stats;
+    hipLaunchKernelGGL(tf, dim3(tgrid), dim3(kBlock), 0, st, A);
     KNN_HIP(hipGetLastError());
     prof_mark(st, 8);
     return KNN_OK;

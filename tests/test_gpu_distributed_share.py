@@ -1,0 +1,99 @@
+"""The single-GPU share of the distributed query (Section III-B): local k-NN
+on the owner's tree, a radius-bounded search on another rank's tree with the
+owner's k-th distance r' (per query), and the merge of the two lists, checked
+bit for bit against brute force over all points."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same, dev, log
+from paper_1607_08220_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def knn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1607_08220_amd as knn
+    knn.load_library()
+    return knn
+
+
+def _local_self(ids_global, members):
+    """Global point ids -> positions in `members` (sorted), -1 if absent."""
+    pos = np.searchsorted(members, ids_global)
+    pos = np.minimum(pos, len(members) - 1)
+    return np.where(members[pos] == ids_global, pos, -1).astype(np.int32)
+
+
+@pytest.mark.parametrize("k", [1, 8, 33])
+def test_two_owner_query_with_radius_and_merge(knn, k):
+    import torch
+    w = inputs.workload("cosmo_clustered", scale=1 / 512)
+    X, Q, S = w.points, w.queries, w.self_ids
+    log(f"[case] two owners n={len(X)} m={len(Q)} k={k}")
+    cut = np.float32(np.median(X[:, 0]))
+    own = [np.flatnonzero(X[:, 0] < cut), np.flatnonzero(X[:, 0] >= cut)]
+    trees = [knn.knn_build(dev(X[o]), 32) for o in own]
+    owner = (Q[:, 0] >= cut).astype(int)
+    res = np.empty((len(Q), k), np.int32), np.empty((len(Q), k), np.float32)
+    for r in (0, 1):
+        sel = np.flatnonzero(owner == r)
+        q = dev(Q[sel])
+        # step 2: local k-NN on the owner, r' = its k-th distance
+        li, ld = knn.knn_query_ex(trees[r], q, k, self_ids=dev(_local_self(S[sel], own[r])))
+        li_g = torch.where(li >= 0, dev(own[r].astype(np.int32))[li.clamp(min=0).long()], li)
+        rp = torch.nextafter(ld[:, -1].contiguous(), torch.tensor(np.inf, device=ld.device))
+        # step 4: the other rank searches within r' (D <= r' admitted)
+        o = 1 - r
+        ri, rd = knn.knn_query_radius(trees[o], q, k, rp.contiguous(),
+                                      self_ids=dev(_local_self(S[sel], own[o])))
+        ri_g = torch.where(ri >= 0, dev(own[o].astype(np.int32))[ri.clamp(min=0).long()], ri)
+        # step 5: merge
+        mi, md = knn.knn_merge((li_g.contiguous(), ld), (ri_g.contiguous(), rd), k)
+        torch.cuda.synchronize()
+        res[0][sel], res[1][sel] = mi.cpu().numpy(), md.cpu().numpy()
+    bi, bd = oracle.bf32(X, Q, k, self_ids=S)
+    assert_same(res[0], res[1], bi, bd, f"two owners k={k}")
+    for t in trees:
+        t.free()
+
+
+def test_merge_edges(knn):
+    import torch
+    log("[case] merge edges")
+    inf = np.inf
+    ia = np.array([[3, 5, -1], [1, 2, 4]], np.int32)
+    da = np.array([[1.0, 2.0, inf], [0.5, 0.5, 3.0]], np.float32)
+    ib = np.array([[5, 7], [-1, -1]], np.int32)
+    db = np.array([[2.0, 2.0], [inf, inf]], np.float32)
+    oi, od = knn.knn_merge((dev(ia), dev(da)), (dev(ib), dev(db)), 4)
+    torch.cuda.synchronize()
+    assert oi.cpu().numpy().tolist() == [[3, 5, 7, -1], [1, 2, 4, -1]]
+    assert od.cpu().numpy().tolist() == [[1.0, 2.0, 2.0, inf], [0.5, 0.5, 3.0, inf]]
+    oi, od = knn.knn_merge((dev(ia), dev(da)), (dev(ib), dev(db)), 1)
+    torch.cuda.synchronize()
+    assert oi.cpu().numpy().ravel().tolist() == [3, 1]
+    with pytest.raises(knn.KnnError):
+        knn.knn_merge((dev(ia), dev(da)), (dev(ib), dev(db)), 65)
+
+
+def test_radius_per_query_matches_scalar(knn):
+    """A per-query radius equal for all queries gives the scalar-radius result."""
+    import torch
+    w = inputs.workload("tiny_uniform")
+    log("[case] per-query radius")
+    t = knn.knn_build(dev(w.points), 32)
+    q = dev(w.queries)
+    for r2 in (0.0, 1e-4, 2e-3, np.inf):
+        a = knn.knn_query_ex(t, q, 7, r2_max=r2)
+        b = knn.knn_query_radius(t, q, 7, torch.full((len(w.queries),), r2, device=q.device))
+        torch.cuda.synchronize()
+        assert_same(a[0].cpu().numpy(), a[1].cpu().numpy(), b[0].cpu().numpy(),
+                    b[1].cpu().numpy(), f"r2={r2}")
+        oi, od = oracle.bf32(w.points, w.queries, 7, r2=r2)
+        assert_same(b[0].cpu().numpy(), b[1].cpu().numpy(), oi, od, f"oracle r2={r2}")
+    t.free()
