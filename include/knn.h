@@ -80,6 +80,8 @@ typedef struct {
     int64_t nodes;        /* inner nodes + leaves */
     int64_t leaves;
     int64_t device_bytes; /* device memory held by the tree */
+    int32_t trees;        /* 1, or the number of trees of a forest (knn_build_batch) */
+    int32_t pad_;
 } knn_tree_info_t;
 
 /* Host copy of a tree (knn_tree_export).  The caller allocates every array
@@ -127,8 +129,23 @@ int knn_build_ex(const float* points, int64_t n, int32_t dim, const knn_build_pa
                  void* stream, knn_tree** out);
 
 /*
+ * knn_build_batch -- build many independent trees in one call: tree t is built
+ * over rows offsets[t] .. offsets[t+1]-1 of `points`, exactly as knn_build_ex
+ * would build it from those rows alone (same splits, buckets and boxes).  All
+ * trees go through the same level passes and subtree kernels, so the launch
+ * count does not grow with the number of trees.  The result is one forest
+ * handle whose tree t has root node t; query it with knn_query_batch.
+ *   points   device pointer [offsets[trees], dim] FP32, the trees' rows concatenated
+ *   offsets  HOST pointer [trees + 1]: offsets[0] = 0, strictly increasing
+ *   trees    >= 1; all points together at most 2^30
+ * Neighbour indices are rows of the concatenated array.  Errors as knn_build_ex.
+ */
+int knn_build_batch(const float* points, const int64_t* offsets, int32_t trees, int32_t dim,
+                    const knn_build_params* p, void* stream, knn_tree** out);
+
+/*
  * knn_query -- the k nearest neighbours of m queries (Algorithm 1).
- *   t         a tree from knn_build
+ *   t         a tree from knn_build (a forest from knn_build_batch is rejected)
  *   queries   device pointer, row-major [m, dim] FP32
  *   m         >= 0 (0 is a no-op)
  *   k         1 .. KNN_MAX_K (k > n pads)
@@ -151,6 +168,17 @@ int knn_query(const knn_tree* t, const float* queries, int64_t m, int32_t k, int
 int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
                  const int32_t* self_ids, float r2_max, const knn_query_params* p,
                  int32_t* out_idx, float* out_dist2, void* stream);
+
+/*
+ * knn_query_batch -- knn_query_ex on a forest: query i searches only tree
+ * tree_ids[i] (device pointer [m] int32, each in [0, trees); a value outside
+ * that range is undefined behaviour).  All queries run in one batch of
+ * launches whatever trees they address.  Indices are rows of the
+ * concatenated points; self_ids use the same numbering.
+ */
+int knn_query_batch(const knn_tree* t, const float* queries, const int32_t* tree_ids,
+                    int64_t m, int32_t k, const int32_t* self_ids, float r2_max,
+                    const knn_query_params* p, int32_t* out_idx, float* out_dist2, void* stream);
 
 /*
  * knn_query_radius -- knn_query_ex with one search radius per query: only

@@ -47,7 +47,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("subtree_points", ctypes.c_int32),
                 ("nodes", ctypes.c_int64), ("leaves", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("trees", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class _Host(ctypes.Structure):
@@ -57,8 +58,8 @@ class _Host(ctypes.Structure):
 
 
 _lib = None
-EXPORTED = ("knn_build", "knn_build_ex", "knn_query", "knn_query_ex", "knn_query_radius",
-            "knn_merge", "knn_tree_free", "knn_tree_info", "knn_tree_export", "knn_last_error",
+EXPORTED = ("knn_build", "knn_build_ex", "knn_build_batch", "knn_query", "knn_query_ex",
+            "knn_query_batch", "knn_query_radius", "knn_merge", "knn_tree_free", "knn_tree_info", "knn_tree_export", "knn_last_error",
             "knn_set_profiling", "knn_get_profile")
 
 
@@ -75,7 +76,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.knn_build.argtypes = [vp, i64, i32, i32, vp, ctypes.POINTER(vp)]
     lib.knn_build_ex.argtypes = [vp, i64, i32, ctypes.POINTER(_BuildParams), vp,
                                  ctypes.POINTER(vp)]
+    lib.knn_build_batch.argtypes = [vp, vp, i32, i32, ctypes.POINTER(_BuildParams), vp,
+                                    ctypes.POINTER(vp)]
     lib.knn_query.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    lib.knn_query_batch.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.c_float,
+                                    ctypes.POINTER(_QueryParams), vp, vp, vp]
     lib.knn_query_ex.argtypes = [vp, vp, i64, i32, vp, ctypes.c_float,
                                  ctypes.POINTER(_QueryParams), vp, vp, vp]
     lib.knn_query_radius.argtypes = [vp, vp, i64, i32, vp, vp, ctypes.POINTER(_QueryParams), vp,
@@ -173,6 +178,25 @@ def knn_build(points, leaf_size: int = 32) -> Tree:
     return Tree(out.value, points.shape[1], points.device)
 
 
+def knn_build_batch(points, offsets, leaf_size: int = 0, max_depth: int = 0,
+                    subtree_points: int = 0, split_block_nodes: int = 0) -> Tree:
+    """Build one tree per row range: tree t over rows offsets[t]..offsets[t+1]-1
+    of ``points`` (CUDA float32 [N, dim]); ``offsets`` is a host sequence of
+    trees + 1 increasing integers starting at 0."""
+    lib = load_library()
+    _dev_f32(points, "points")
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or len(off) < 2 or off[-1] != points.shape[0]:
+        raise ValueError("offsets must be trees + 1 values ending at the number of rows")
+    p = _BuildParams(leaf_size, max_depth, subtree_points, split_block_nodes)
+    out = ctypes.c_void_p()
+    _check(lib.knn_build_batch(ctypes.c_void_p(points.data_ptr()),
+                               off.ctypes.data_as(ctypes.c_void_p), len(off) - 1,
+                               points.shape[1], ctypes.byref(p), _stream(points),
+                               ctypes.byref(out)))
+    return Tree(out.value, points.shape[1], points.device)
+
+
 def _outputs(queries, k, out):
     import torch
     m = queries.shape[0]
@@ -234,6 +258,24 @@ def _dev_i32_vec(t, name, m):
             and t.is_contiguous() and t.shape == (m,)):
         raise TypeError(f"{name} must be a contiguous CUDA int32 [{m}] tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def knn_query_batch(forest: Tree, queries, tree_ids, k: int, self_ids=None,
+                    r2_max: float = math.inf, order: int = 0, out=None, leaf_batch: int = 0):
+    """k nearest neighbours of each query within its own tree of a forest
+    (``tree_ids``: CUDA int32 [m])."""
+    lib = load_library()
+    _dev_f32(queries, "queries", forest.dim)
+    m = queries.shape[0]
+    idx, d2 = _outputs(queries, k, out)
+    tp = _dev_i32_vec(tree_ids, "tree_ids", m)
+    sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
+    p = _QueryParams(order, leaf_batch, None)
+    _check(lib.knn_query_batch(forest.handle, ctypes.c_void_p(queries.data_ptr()), tp, m, k, sp,
+                               ctypes.c_float(r2_max), ctypes.byref(p),
+                               ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                               _stream(queries)))
+    return idx, d2
 
 
 def knn_query_radius(tree: Tree, queries, k: int, r2, self_ids=None, order: int = 0, out=None,

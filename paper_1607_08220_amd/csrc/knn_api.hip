@@ -104,8 +104,10 @@ extern "C" {
 
 const char* knn_last_error(void) { return g_err.c_str(); }
 
-int knn_build_ex(const float* points, int64_t n, int32_t dim, const knn_build_params* p,
-                 void* stream, knn_tree** out)
+namespace {
+
+int build_common(const float* points, int64_t n, int32_t dim, const int64_t* offsets,
+                 int32_t trees, const knn_build_params* p, void* stream, knn_tree** out)
 {
     if (!out) return fail(KNN_EINVAL, "out is NULL");
     *out = nullptr;
@@ -120,7 +122,30 @@ int knn_build_ex(const float* points, int64_t n, int32_t dim, const knn_build_pa
     if (max_depth > 4096) return fail(KNN_EINVAL, "max_depth too large");
     const int32_t W = subtree_points_for(dim, q.subtree_points);
     const int64_t sbn = q.split_block_nodes ? std::max(q.split_block_nodes, 0) : kDefaultSplitBlockNodes;
-    return build_tree(points, n, dim, leaf, max_depth, W, sbn, static_cast<hipStream_t>(stream), out);
+    return build_tree(points, n, dim, leaf, max_depth, W, sbn, offsets, trees,
+                      static_cast<hipStream_t>(stream), out);
+}
+
+}  // namespace
+
+int knn_build_ex(const float* points, int64_t n, int32_t dim, const knn_build_params* p,
+                 void* stream, knn_tree** out)
+{
+    const int64_t offsets[2] = {0, n};
+    return build_common(points, n, dim, offsets, 1, p, stream, out);
+}
+
+int knn_build_batch(const float* points, const int64_t* offsets, int32_t trees, int32_t dim,
+                    const knn_build_params* p, void* stream, knn_tree** out)
+{
+    if (out) *out = nullptr;
+    if (!offsets) return fail(KNN_EINVAL, "offsets is NULL");
+    if (trees < 1) return fail(KNN_EINVAL, "trees must be >= 1");
+    if (offsets[0] != 0) return fail(KNN_EINVAL, "offsets[0] must be 0");
+    for (int32_t t = 0; t < trees; ++t)
+        if (offsets[t + 1] <= offsets[t]) return fail(KNN_EINVAL, "every tree needs >= 1 point");
+    if (offsets[trees] > kMaxPoints) return fail(KNN_EINVAL, "more than 2^30 points in all");
+    return build_common(points, offsets[trees], dim, offsets, trees, p, stream, out);
 }
 
 int knn_build(const float* points, int64_t n, int32_t dim, int32_t leaf_size, void* stream,
@@ -134,7 +159,7 @@ int knn_build(const float* points, int64_t n, int32_t dim, int32_t leaf_size, vo
 namespace {
 
 int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
-                 const int32_t* self_ids, float r2_max, const float* r2s,
+                 const int32_t* self_ids, float r2_max, const float* r2s, const int32_t* roots,
                  const knn_query_params* p, int32_t* out_idx, float* out_dist2, void* stream)
 {
     if (!t) return fail(KNN_EINVAL, "tree is NULL");
@@ -156,6 +181,7 @@ int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     qs.self_ids = self_ids;
     qs.r2 = r2_max;
     qs.r2s = r2s;
+    qs.qroot = roots;
     qs.order = order;
     qs.batch = batch;
     qs.out_idx = out_idx;
@@ -170,8 +196,18 @@ int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
                  const int32_t* self_ids, float r2_max, const knn_query_params* p,
                  int32_t* out_idx, float* out_dist2, void* stream)
 {
-    return query_common(t, queries, m, k, self_ids, r2_max, nullptr, p, out_idx, out_dist2,
-                        stream);
+    if (t && t->n_trees != 1) return fail(KNN_EINVAL, "a forest is queried with knn_query_batch");
+    return query_common(t, queries, m, k, self_ids, r2_max, nullptr, nullptr, p, out_idx,
+                        out_dist2, stream);
+}
+
+int knn_query_batch(const knn_tree* t, const float* queries, const int32_t* tree_ids,
+                    int64_t m, int32_t k, const int32_t* self_ids, float r2_max,
+                    const knn_query_params* p, int32_t* out_idx, float* out_dist2, void* stream)
+{
+    if (m > 0 && !tree_ids) return fail(KNN_EINVAL, "tree_ids is NULL");
+    return query_common(t, queries, m, k, self_ids, r2_max, nullptr, tree_ids, p, out_idx,
+                        out_dist2, stream);
 }
 
 int knn_query_radius(const knn_tree* t, const float* queries, int64_t m, int32_t k,
@@ -179,7 +215,9 @@ int knn_query_radius(const knn_tree* t, const float* queries, int64_t m, int32_t
                      int32_t* out_idx, float* out_dist2, void* stream)
 {
     if (m > 0 && !r2) return fail(KNN_EINVAL, "r2 is NULL");
-    return query_common(t, queries, m, k, self_ids, INFINITY, r2, p, out_idx, out_dist2, stream);
+    if (t && t->n_trees != 1) return fail(KNN_EINVAL, "a forest is queried with knn_query_batch");
+    return query_common(t, queries, m, k, self_ids, INFINITY, r2, nullptr, p, out_idx, out_dist2,
+                        stream);
 }
 
 int knn_merge(const int32_t* idx_a, const float* dist2_a, int32_t ka, const int32_t* idx_b,
@@ -225,8 +263,10 @@ int knn_tree_info(const knn_tree* t, knn_tree_info_t* info)
     info->depth = t->depth;
     info->subtree_points = t->sub_pts;
     info->nodes = t->n_nodes;
-    info->leaves = (t->n_nodes + 1) / 2;  // a full binary tree
+    info->leaves = (t->n_nodes + t->n_trees) / 2;  // full binary trees
     info->device_bytes = t->bytes;
+    info->trees = t->n_trees;
+    info->pad_ = 0;
     return KNN_OK;
 }
 

@@ -1644,7 +1644,8 @@ int32_t default_subtree_points(int32_t d)
 }
 
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
-               int32_t W, int64_t split_block_nodes, hipStream_t st, knn_tree** out)
+               int32_t W, int64_t split_block_nodes, const int64_t* offsets, int32_t T,
+               hipStream_t st, knn_tree** out)
 {
     prof_mark(st, 0);
     prof_part_begin();
@@ -1682,20 +1683,37 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     const int64_t nbh_cap = n / kHistChunk + nn_cap + 1;
     const int64_t lv_cap = (int64_t)max_depth + 2;
     // every level-pass node and subtree entry descends from a level node
-    const int64_t big_cap = 2 * nn_cap * lv_cap + 2;
+    const int64_t big_cap = T + 2 * nn_cap * lv_cap + 2;
     const int64_t sub_cap = std::min<int64_t>(n, big_cap);
     LevelMem lvA(st), lvB(st);
     DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), wave_left(st), blk_off(st),
         d_big(st), d_subs(st), d_rng(st), planv(st), planx(st), pblk(st);
-    int32_t n_sub = 0, n_big = 1, n_levels = 0;
+    int32_t n_sub = 0, n_big = T, n_levels = 1;
     std::vector<int32_t> h_g(G_COUNT, 0);
-    if (!needs_level(n)) {
-        const SubEntry root{0, (int32_t)n, 0, -1, 0, 0, 0, 0};
-        KNN_HIP(d_subs.alloc(sizeof(SubEntry)));
-        KNN_HIP(hipMemcpyAsync(d_subs.p, &root, sizeof(root), hipMemcpyHostToDevice, st));
-        KNN_HIP(d_big.alloc(sizeof(NodeRec)));
+    // Tree t has root node t.  Roots of at most W points (or at most a bucket)
+    // go straight to the subtree finish; the others form level 0.
+    std::vector<SubEntry> small;
+    std::vector<int32_t> big_roots;
+    int64_t largest = 0;
+    for (int32_t r = 0; r < T; ++r) {
+        const int64_t c = offsets[r + 1] - offsets[r];
+        if (needs_level(c)) {
+            big_roots.push_back(r);
+            largest = std::max(largest, c);
+        } else {
+            small.push_back(SubEntry{(int32_t)offsets[r], (int32_t)c, r, -1, 0, 0, 0, 0});
+        }
+    }
+    const int32_t r0[2] = {0, T};
+    if (big_roots.empty()) {
+        n_sub = (int32_t)small.size();
+        KNN_HIP(d_subs.alloc(sizeof(SubEntry) * small.size()));
+        KNN_HIP(hipMemcpyAsync(d_subs.p, small.data(), sizeof(SubEntry) * small.size(),
+                               hipMemcpyHostToDevice, st));
+        KNN_HIP(d_big.alloc(sizeof(NodeRec) * T));
         KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2));
-        n_sub = 1;
+        KNN_HIP(hipMemcpyAsync(d_rng.p, r0, sizeof(r0), hipMemcpyHostToDevice, st));
+        KNN_HIP(hipStreamSynchronize(st));  // the host staging vector dies here
     } else {
         KNN_HIP(lvA.alloc(nn_cap, nb_cap, nbh_cap));
         KNN_HIP(lvB.alloc(nn_cap, nb_cap, nbh_cap));
@@ -1712,46 +1730,60 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(d_big.alloc(sizeof(NodeRec) * big_cap));
         KNN_HIP(d_subs.alloc(sizeof(SubEntry) * sub_cap));
         KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2 * (lv_cap + 1)));
-        {   // level 0: the root and its block tables
-            const int32_t nb = (int32_t)((n + kChunk - 1) / kChunk);
-            const int32_t nbh = (int32_t)((n + kHistChunk - 1) / kHistChunk);
-            std::vector<int32_t> h(2 * (size_t)nb + 2 * (size_t)nbh);
-            for (int32_t j = 0; j < nb; ++j) {
-                h[j] = 0;
-                h[nb + j] = j * kChunk;
+        {   // level 0: the large roots and their block tables
+            const int32_t nn0 = (int32_t)big_roots.size();
+            std::vector<int32_t> f[8];  // start, count, id, parent, depth, blk0, nblk, hblk0
+            std::vector<int32_t> bnode, bbeg, hnode, hbeg;
+            for (int32_t i = 0; i < nn0; ++i) {
+                const int32_t r = big_roots[i];
+                const int64_t c = offsets[r + 1] - offsets[r];
+                const int32_t nb = (int32_t)((c + kChunk - 1) / kChunk);
+                const int32_t nbh = (int32_t)((c + kHistChunk - 1) / kHistChunk);
+                const int32_t vals[8] = {(int32_t)offsets[r], (int32_t)c, r, -1, 0,
+                                         (int32_t)bnode.size(), nb, (int32_t)hnode.size()};
+                for (int k = 0; k < 8; ++k) f[k].push_back(vals[k]);
+                for (int32_t j = 0; j < nb; ++j) {
+                    bnode.push_back(i);
+                    bbeg.push_back(j * kChunk);
+                }
+                for (int32_t j = 0; j < nbh; ++j) {
+                    hnode.push_back(i);
+                    hbeg.push_back(j * kHistChunk);
+                }
             }
-            for (int32_t j = 0; j < nbh; ++j) {
-                h[2 * nb + j] = 0;
-                h[2 * nb + nbh + j] = j * kHistChunk;
-            }
-            const int32_t node[8] = {0, (int32_t)n, 0, -1, 0, 0, nb, 0};
             const Level& L0 = lvA.L;
             int32_t* dst[8] = {L0.start, L0.count, L0.id, L0.parent, L0.depth, L0.blk0, L0.nblk,
                                L0.hblk0};
-            for (int f = 0; f < 8; ++f)
-                KNN_HIP(hipMemcpyAsync(dst[f], &node[f], sizeof(int32_t), hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(L0.bnode, h.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(L0.bbeg, h.data() + nb, sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(L0.hnode, h.data() + 2 * nb, sizeof(int32_t) * nbh,
+            for (int k = 0; k < 8; ++k)
+                KNN_HIP(hipMemcpyAsync(dst[k], f[k].data(), sizeof(int32_t) * nn0,
+                                       hipMemcpyHostToDevice, st));
+            KNN_HIP(hipMemcpyAsync(L0.bnode, bnode.data(), sizeof(int32_t) * bnode.size(),
                                    hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(L0.hbeg, h.data() + 2 * nb + nbh, sizeof(int32_t) * nbh,
+            KNN_HIP(hipMemcpyAsync(L0.bbeg, bbeg.data(), sizeof(int32_t) * bbeg.size(),
                                    hipMemcpyHostToDevice, st));
-            const int32_t cnt[3] = {1, nb, nbh};
+            KNN_HIP(hipMemcpyAsync(L0.hnode, hnode.data(), sizeof(int32_t) * hnode.size(),
+                                   hipMemcpyHostToDevice, st));
+            KNN_HIP(hipMemcpyAsync(L0.hbeg, hbeg.data(), sizeof(int32_t) * hbeg.size(),
+                                   hipMemcpyHostToDevice, st));
+            const int32_t cnt[3] = {nn0, (int32_t)bnode.size(), (int32_t)hnode.size()};
             KNN_HIP(hipMemcpyAsync(L0.cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice, st));
-            const int32_t g0[G_COUNT] = {1, 0, 0, 0, 0, 0, 0, 0};
+            if (!small.empty())
+                KNN_HIP(hipMemcpyAsync(d_subs.p, small.data(), sizeof(SubEntry) * small.size(),
+                                       hipMemcpyHostToDevice, st));
+            const int32_t g0[G_COUNT] = {T, (int32_t)small.size(), 0, 0, 0, 0, 0, 0};
             KNN_HIP(hipMemcpyAsync(g, g0, sizeof(g0), hipMemcpyHostToDevice, st));
-            const int32_t r0[2] = {0, 1};
             KNN_HIP(hipMemcpyAsync(d_rng.p, r0, sizeof(r0), hipMemcpyHostToDevice, st));
             KNN_HIP(hipStreamSynchronize(st));  // the host staging vectors die here
         }
         // levels expected for balanced splits; the host checks for more after that
         int expected = 1;
-        for (int64_t c = n; needs_level(c); c = (c + 1) / 2) ++expected;
+        for (int64_t c = largest; needs_level(c); c = (c + 1) / 2) ++expected;
         Level cur = lvA.L, nxt = lvB.L;
         int buf = 0;
         for (int level = 0;; ++level) {
             if (level >= lv_cap) return fail(KNN_EDEPTH, "tree deeper than max_depth");
-            const int64_t nn_l = std::min<int64_t>(level < 40 ? (int64_t(1) << level) : nn_cap, nn_cap);
+            const int64_t nn_l = std::min<int64_t>(
+                level < 40 ? (int64_t)big_roots.size() << std::min(level, 40) : nn_cap, nn_cap);
             const unsigned g_nn = (unsigned)nn_l;
             const unsigned g_nb = (unsigned)std::min<int64_t>(n / kChunk + nn_l + 1, nb_cap);
             const unsigned g_nbh = (unsigned)std::min<int64_t>(n / kHistChunk + nn_l + 1, nbh_cap);
@@ -1872,7 +1904,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                                           bbox.as<float>());
     KNN_HIP(hipGetLastError());
     for (int dep = n_levels - 1; dep >= 0; --dep) {
-        const int64_t cap = std::min<int64_t>(dep < 40 ? (int64_t(1) << dep) : total, total);
+        const int64_t cap = std::min<int64_t>(dep < 40 ? (int64_t)T << dep : total, total);
         k_bbox_up<<<blocks_for(cap, kBlock), kBlock, 0, st>>>(d_rng.as<int32_t>() + 2 * dep,
                                                              nodes.as<NodeRec>(), bbox.as<float>(), d);
         KNN_HIP(hipGetLastError());
@@ -1884,6 +1916,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     t->n = n;
     t->d = d;
     t->leaf = leaf;
+    t->n_trees = T;
     t->depth = h_flags[1];
     t->sub_pts = W;
     t->n_nodes = total;

@@ -41,6 +41,7 @@ struct knn_tree {
     int32_t leaf = 0;
     int32_t depth = 0;
     int32_t sub_pts = 0;
+    int32_t n_trees = 1;             // a forest's tree t has root node t
     int64_t n_nodes = 0;
     int64_t n_leaves = 0;
     int32_t device = 0;
@@ -117,7 +118,8 @@ int32_t finish_max_points(int32_t d);
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w);
 
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
-               int32_t W, int64_t split_block_nodes, hipStream_t stream, knn_tree** out);
+               int32_t W, int64_t split_block_nodes, const int64_t* offsets, int32_t trees,
+               hipStream_t stream, knn_tree** out);
 // One batch of queries against a tree (or forest).  Per-query arrays are
 // device pointers indexed by query; NULL selects the scalar.
 struct QuerySpec {

@@ -104,6 +104,46 @@ def sample_queries(n: int, m: int, seed: int) -> np.ndarray:
 
 
 @dataclass
+class ForestWorkload:
+    name: str
+    points: np.ndarray      # all trees' points, concatenated [N, d]
+    offsets: np.ndarray     # [trees + 1] int64 row offsets
+    queries: np.ndarray     # [m, d]
+    tree_ids: np.ndarray    # [m] int32: the tree each query searches
+    self_ids: np.ndarray    # [m] int32: the query's own row (excluded)
+    k: int
+    leaf: int
+
+
+def forest(n_trees: int, d: int = 6, lo_exp: float = 10.0, hi_exp: float = 20.0,
+           q_per_tree: int = 1024, seed: int = 1004, k: int = 5, leaf: int = 32) -> ForestWorkload:
+    """Many independent trees of log-uniform sizes round(2^(lo + (hi - lo) u)),
+    each a correlated Gaussian with its own rotation (eigenvalues 1/i), each
+    queried by up to q_per_tree of its own points with the point excluded.
+    Tree t draws from its own stream (seed, t), so a prefix of the trees does
+    not depend on how many follow."""
+    sizes = np.rint(2.0 ** (lo_exp + (hi_exp - lo_exp) * _rng(seed).random(n_trees))).astype(np.int64)
+    sizes = np.maximum(sizes, 1)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pts, qs, tids, sids = [], [], [], []
+    for t in range(n_trees):
+        rng = np.random.Generator(np.random.PCG64([seed, t]))
+        A = rng.standard_normal((d, d))
+        Qm, R = np.linalg.qr(A)
+        Qm = Qm * np.sign(np.diag(R))[None, :]
+        scale = np.arange(1, d + 1, dtype=np.float64) ** -0.5
+        X = ((rng.standard_normal((int(sizes[t]), d)) * scale[None, :]) @ Qm.T).astype(np.float32)
+        m = min(q_per_tree, int(sizes[t]))
+        own = rng.choice(int(sizes[t]), size=m, replace=False).astype(np.int64)
+        pts.append(X)
+        qs.append(X[own])
+        tids.append(np.full(m, t, np.int32))
+        sids.append((own + offsets[t]).astype(np.int32))
+    return ForestWorkload(f"forest{n_trees}", np.concatenate(pts), offsets, np.concatenate(qs),
+                          np.concatenate(tids), np.concatenate(sids), k, leaf)
+
+
+@dataclass
 class Workload:
     name: str
     points: np.ndarray
