@@ -210,6 +210,47 @@ int knn_merge(const int32_t* idx_a, const float* dist2_a, int32_t ka, const int3
               const float* dist2_b, int32_t kb, int64_t m, int32_t k, int32_t* out_idx,
               float* out_dist2, void* stream);
 
+/*
+ * Serving: resident trees answer a stream of query requests with continuous
+ * batching (the query batching of Section III-B, step 2, applied to a request
+ * stream).  A server keeps the given trees (which the caller keeps alive)
+ * and runs one worker thread: pending requests for the same tree and k are
+ * packed into one batch, admitted when a stream is free and the batch's
+ * device memory fits in the budget beside the batches already in flight, so
+ * requests that arrive while others run join the next batch and batches on
+ * different streams overlap.  Each query is answered exactly as by
+ * knn_query_ex, so results do not depend on the mix.
+ */
+typedef struct knn_server knn_server;
+
+/* trees: host array of ntrees (>= 1) single trees on one device;
+ * hbm_budget_bytes: device memory the batches in flight may hold (0 = 4 GiB;
+ * a batch larger than the budget still runs when nothing else is in
+ * flight); streams: concurrent batches, 1..64 (0 = 4). */
+int knn_server_create(const knn_tree* const* trees, int32_t ntrees, int64_t hbm_budget_bytes,
+                      int32_t streams, knn_server** out);
+
+/* Queue one request: m (1 .. 2^18) queries (device pointer [m, dim]) against
+ * tree `tree` with k neighbours, optional self ids (device [m] or NULL);
+ * results go to the caller's device buffers out_idx/out_dist2 [m, k], which
+ * must stay valid until knn_server_wait returns for the ticket.  Thread-safe. */
+int knn_server_submit(knn_server* s, int32_t tree, const float* queries, int64_t m, int32_t k,
+                      const int32_t* self_ids, int32_t* out_idx, float* out_dist2,
+                      int64_t* ticket);
+
+/* Block until the request is complete (its results are in its buffers);
+ * latency_ms (may be NULL) receives the time from submit to completion as
+ * seen by the worker.  Each ticket is waited for once. */
+int knn_server_wait(knn_server* s, int64_t ticket, double* latency_ms);
+
+/* Counters: requests submitted, batches launched, queries answered, peak
+ * device bytes held by batches in flight. */
+int knn_server_stats(knn_server* s, int64_t* out /* [4] */);
+
+/* Finish every queued request, stop the worker and free the server (not the
+ * trees).  NULL is OK. */
+int knn_server_destroy(knn_server* s);
+
 /* Free a tree and its device memory (waits for the device first).  NULL is OK. */
 int knn_tree_free(knn_tree* t);
 

@@ -59,7 +59,8 @@ class _Host(ctypes.Structure):
 
 _lib = None
 EXPORTED = ("knn_build", "knn_build_ex", "knn_build_batch", "knn_query", "knn_query_ex",
-            "knn_query_batch", "knn_query_radius", "knn_merge", "knn_tree_free", "knn_tree_info", "knn_tree_export", "knn_last_error",
+            "knn_query_batch", "knn_query_radius", "knn_merge", "knn_server_create",
+            "knn_server_submit", "knn_server_wait", "knn_server_stats", "knn_server_destroy", "knn_tree_free", "knn_tree_info", "knn_tree_export", "knn_last_error",
             "knn_set_profiling", "knn_get_profile")
 
 
@@ -86,6 +87,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.knn_query_radius.argtypes = [vp, vp, i64, i32, vp, vp, ctypes.POINTER(_QueryParams), vp,
                                      vp, vp]
     lib.knn_merge.argtypes = [vp, vp, i32, vp, vp, i32, i64, i32, vp, vp, vp]
+    lib.knn_server_create.argtypes = [ctypes.POINTER(vp), i32, i64, i32, ctypes.POINTER(vp)]
+    lib.knn_server_submit.argtypes = [vp, i32, vp, i64, i32, vp, vp, vp,
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.knn_server_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+    lib.knn_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.knn_server_destroy.argtypes = [vp]
     lib.knn_tree_free.argtypes = [vp]
     lib.knn_tree_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.knn_tree_export.argtypes = [vp, ctypes.POINTER(_Host)]
@@ -320,6 +327,80 @@ def knn_merge(a, b, k: int, out=None):
                          ctypes.c_void_p(oi.data_ptr()), ctypes.c_void_p(od.data_ptr()),
                          _stream(ia)))
     return oi, od
+
+
+class Server:
+    """Serving loop over resident trees (knn_server_* in knn.h).  Keep the
+    trees, and every submitted request's tensors, alive until waited for."""
+
+    def __init__(self, trees, hbm_budget_bytes: int = 0, streams: int = 0):
+        lib = load_library()
+        self._trees = list(trees)
+        arr = (ctypes.c_void_p * len(self._trees))(*[t.handle.value for t in self._trees])
+        h = ctypes.c_void_p()
+        _check(lib.knn_server_create(arr, len(self._trees), hbm_budget_bytes, streams,
+                                     ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, tree: int, queries, k: int, self_ids=None, out=None) -> int:
+        """Queue a request; returns its ticket.  Results land in ``out`` (or in
+        tensors allocated here) once :meth:`wait` returns."""
+        lib = load_library()
+        dim = self._trees[tree].dim if 0 <= tree < len(self._trees) else None  # else the library rejects it
+        _dev_f32(queries, "queries", dim)
+        m = queries.shape[0]
+        idx, d2 = _outputs(queries, k, out)
+        sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
+        ticket = ctypes.c_int64()
+        _check(lib.knn_server_submit(self._h, tree, ctypes.c_void_p(queries.data_ptr()), m, k, sp,
+                                     ctypes.c_void_p(idx.data_ptr()),
+                                     ctypes.c_void_p(d2.data_ptr()), ctypes.byref(ticket)))
+        self._keep[ticket.value] = (queries, self_ids, idx, d2)
+        return ticket.value
+
+    def wait(self, ticket: int):
+        """Block until the request is done: (idx, dist2, latency_ms)."""
+        lat = ctypes.c_double()
+        _check(load_library().knn_server_wait(self._h, ticket, ctypes.byref(lat)))
+        _, _, idx, d2 = self._keep.pop(ticket)
+        return idx, d2, lat.value
+
+    def stats(self) -> dict:
+        buf = (ctypes.c_int64 * 4)()
+        _check(load_library().knn_server_stats(self._h, buf))
+        return dict(zip(("requests", "batches", "queries", "peak_bytes"), list(buf)))
+
+    def close(self):
+        if self._h and self._h.value:
+            _check(load_library().knn_server_destroy(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def knn_server_create(trees, hbm_budget_bytes: int = 0, streams: int = 0) -> Server:
+    return Server(trees, hbm_budget_bytes, streams)
+
+
+def knn_server_submit(server: Server, tree: int, queries, k: int, self_ids=None, out=None) -> int:
+    return server.submit(tree, queries, k, self_ids=self_ids, out=out)
+
+
+def knn_server_wait(server: Server, ticket: int):
+    return server.wait(ticket)
+
+
+def knn_server_stats(server: Server) -> dict:
+    return server.stats()
+
+
+def knn_server_destroy(server: Server):
+    server.close()
 
 
 def knn_tree_info(tree: Tree) -> dict:
