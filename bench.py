@@ -91,6 +91,175 @@ def cpu_baseline(X: np.ndarray, k: int, log2n: int, m: int, threads: int) -> dic
             "build_mpts_per_s": n / tb / 1e6}
 
 
+def bench_forest(knn, torch, dev) -> dict:
+    """Batched build + query of 512 independent 6-D trees (sizes log-uniform in
+    [2^10, 2^20], each queried by 1,024 of its own points, k = 5) against the
+    same work as 512 per-call builds and queries; identical results required."""
+    from paper_1607_08220_amd import inputs
+    t0 = time.perf_counter()
+    f = inputs.forest(512)
+    log(f"forest: {len(f.offsets) - 1} trees, {len(f.points)} points, {len(f.queries)} queries "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    P = torch.from_numpy(f.points).to(dev)
+    Q = torch.from_numpy(f.queries).to(dev)
+    T = torch.from_numpy(f.tree_ids).to(dev)
+    S = torch.from_numpy(f.self_ids).to(dev)
+    torch.cuda.synchronize()
+
+    def batched():
+        a = time.perf_counter()
+        forest = knn.knn_build_batch(P, f.offsets, leaf_size=f.leaf)
+        b = time.perf_counter()
+        idx, d2 = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        forest.free()
+        return (b - a) * 1e3, (c - b) * 1e3, idx, d2
+
+    batched()
+    runs = [batched() for _ in range(3)]
+    bb = float(np.median([r[0] for r in runs]))
+    bq = float(np.median([r[1] for r in runs]))
+    idx, d2 = runs[-1][2], runs[-1][3]
+
+    # the same work as one call per tree
+    qsel = [np.flatnonzero(f.tree_ids == t) for t in range(len(f.offsets) - 1)]
+    Qt = [Q[torch.from_numpy(s).to(dev)].contiguous() for s in qsel]
+    St = [(S[torch.from_numpy(s).to(dev)] - int(f.offsets[t])).contiguous()
+          for t, s in enumerate(qsel)]
+    torch.cuda.synchronize()
+    outs = []
+    a = time.perf_counter()
+    for t in range(len(f.offsets) - 1):
+        tr = knn.knn_build(P[int(f.offsets[t]):int(f.offsets[t + 1])], f.leaf)
+        outs.append(knn.knn_query_ex(tr, Qt[t], f.k, self_ids=St[t]))
+        tr.free()
+    torch.cuda.synchronize()
+    per_call = (time.perf_counter() - a) * 1e3
+    gi, gd = idx.cpu().numpy(), d2.cpu().numpy()
+    same = True
+    for t, s in enumerate(qsel):
+        oi, od = outs[t][0].cpu().numpy(), outs[t][1].cpu().numpy()
+        oi = np.where(oi >= 0, oi + int(f.offsets[t]), oi)
+        same &= bool(np.array_equal(gi[s], oi) and np.array_equal(gd[s].view(np.uint32),
+                                                                  od.view(np.uint32)))
+    n, m = len(f.points), len(f.queries)
+    log(f"forest: batched build {bb:.1f} ms + query {bq:.2f} ms; per call {per_call:.0f} ms; "
+        f"identical={same}")
+    return {"workload": "forest512_6d", "trees": len(f.offsets) - 1, "points": n, "queries": m,
+            "k": f.k, "leaf_size": f.leaf, "batched_build_ms": bb, "batched_query_ms": bq,
+            "batched_ms": bb + bq, "per_call_ms": per_call, "speedup": per_call / (bb + bq),
+            "build_mpts_per_s": n / (bb * 1e-3) / 1e6, "queries_per_s": m / (bq * 1e-3),
+            "identical_to_per_call": same}
+
+
+def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float) -> dict:
+    """Serving: the resident clustered 3-D tree plus a 10-D correlated-Gaussian
+    tree (n = 2^24); a Poisson stream of requests with sizes floor(2^(16u)),
+    k from {1, 5, 16, 32}, a tree chosen uniformly and queries drawn from that
+    tree's points (self excluded).  The arrival rate puts the per-call loop
+    (each request run alone, in arrival order) at `load` of its capacity, from
+    a calibration of its service time per (tree, k); the server and the
+    per-call loop see the same arrivals; latency is arrival to completion."""
+    import threading
+    from paper_1607_08220_amd import inputs
+    t0 = time.perf_counter()
+    X10 = inputs.corr_gauss(1 << 24, 10, seed=1005)
+    tree10 = knn.knn_build(torch.from_numpy(X10).to(dev), 32)
+    data = [X3, X10]
+    trees = [tree3, tree10]
+    # per-call service time: fixed cost + per-query cost for each (tree, k)
+    cal = np.random.default_rng(7)
+    cost = {}
+    for t in (0, 1):
+        for k in (1, 5, 16, 32):
+            times = []
+            for b in (1, 4096):
+                ids = cal.integers(0, len(data[t]), size=b).astype(np.int32)
+                Q = torch.from_numpy(data[t][ids]).to(dev)
+                S = torch.from_numpy(ids).to(dev)
+                knn.knn_query_ex(trees[t], Q, k, self_ids=S)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                knn.knn_query_ex(trees[t], Q, k, self_ids=S)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - a)
+            cost[(t, k)] = (times[0], max(times[1] - times[0], 0.0) / 4095)
+    mean_b = (2 ** 16 - 1) / (16 * np.log(2))  # E[2^(16u)]
+    mean_s = float(np.mean([o + mean_b * c for o, c in cost.values()]))
+    rate = load / mean_s
+    n_req = max(64, int(rate * seconds))
+    rng = np.random.default_rng(2005)
+    reqs = []
+    for _ in range(n_req):
+        t = int(rng.integers(2))
+        b = int(2 ** (16 * rng.random()))
+        k = int(rng.choice([1, 5, 16, 32]))
+        ids = rng.integers(0, len(data[t]), size=b).astype(np.int32)
+        Q = torch.from_numpy(data[t][ids]).to(dev)
+        S = torch.from_numpy(ids).to(dev)
+        reqs.append((t, Q, S, k, torch.empty((b, k), dtype=torch.int32, device=dev),
+                     torch.empty((b, k), dtype=torch.float32, device=dev)))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    nq = sum(r[1].shape[0] for r in reqs)
+    torch.cuda.synchronize()
+    log(f"serving: {n_req} requests, {nq} queries, rate {rate:.1f}/s for per-call load {load} "
+        f"(prepared in {time.perf_counter() - t0:.1f} s)")
+
+    # continuous batching server
+    server = knn.Server(trees)
+    lat = np.zeros(n_req)
+    lag = np.zeros(n_req)
+    tickets = [0] * n_req
+    start = time.perf_counter() + 0.05
+
+    def submitter():
+        for i, (t, Q, S, k, oi, od) in enumerate(reqs):
+            due = start + arrivals[i]
+            while time.perf_counter() < due:
+                pass
+            lag[i] = time.perf_counter() - due
+            tickets[i] = server.submit(t, Q, k, self_ids=S, out=(oi, od))
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    for i in range(n_req):
+        _, _, ms = server.wait(tickets[i])
+        lat[i] = lag[i] * 1e3 + ms
+    end = max(start + arrivals[i] + lat[i] * 1e-3 for i in range(n_req))
+    st = server.stats()
+    server.close()
+    served = [(r[4].clone(), r[5].clone()) for r in reqs]
+    srv = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "queries_per_s": nq / (end - start), "batches": st["batches"],
+           "peak_batch_bytes": st["peak_bytes"]}
+
+    # per-call baseline on the same arrivals
+    lat_pc = np.zeros(n_req)
+    start = time.perf_counter() + 0.05
+    for i, (t, Q, S, k, oi, od) in enumerate(reqs):
+        due = start + arrivals[i]
+        while time.perf_counter() < due:
+            pass
+        knn.knn_query_ex(trees[t], Q, k, self_ids=S, out=(oi, od))
+        torch.cuda.synchronize()
+        lat_pc[i] = (time.perf_counter() - due) * 1e3
+    end = max(start + arrivals[i] + lat_pc[i] * 1e-3 for i in range(n_req))
+    same = all(torch.equal(a[0], r[4]) and torch.equal(a[1].view(torch.int32), r[5].view(torch.int32))
+               for a, r in zip(served, reqs))
+    tree10.free()
+    pc = {"p50_ms": float(np.percentile(lat_pc, 50)), "p99_ms": float(np.percentile(lat_pc, 99)),
+          "queries_per_s": nq / (end - start)}
+    log(f"serving: server p50 {srv['p50_ms']:.2f} ms p99 {srv['p99_ms']:.2f} ms "
+        f"{srv['queries_per_s'] / 1e6:.1f} Mq/s; per call p50 {pc['p50_ms']:.2f} p99 "
+        f"{pc['p99_ms']:.2f} {pc['queries_per_s'] / 1e6:.1f} Mq/s; identical={same}")
+    return {"workload": "serve_cosmo3d_plus_gauss10d", "requests": n_req, "queries": nq,
+            "rate_per_s": rate, "per_call_load": load,
+            "per_call_cost_ms": {f"tree{t}_k{k}": [o * 1e3, c * 1e3] for (t, k), (o, c) in cost.items()},
+            "server": srv, "per_call": pc, "identical_to_per_call": same}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +269,11 @@ def main() -> int:
                     help="shrink n and m (debugging only; the reported workload is scale 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--skip-next", action="store_true",
+                    help="skip the batched-forest and serving measurements")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the per-call loop's capacity")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -248,8 +422,20 @@ def main() -> int:
                          "~50,000 Xeon cores (2048 nodes); single node (24 cores): "
                          "cosmo_thin 50 M points built in 1.1 s, 5 M queries in 1.1 s",
     }
-    for t in trees:
+    for t in trees[:-1]:
         t.free()
+    if not args.skip_next and args.scale >= 1:
+        out["serving"] = bench_serving(knn, torch, dev, trees[-1], w.points, args.serve_load,
+                                       args.serve_seconds)
+        # twice the per-call loop's capacity: only batching keeps up
+        out["serving_overload"] = bench_serving(knn, torch, dev, trees[-1], w.points, 2.0,
+                                                args.serve_seconds * 0.75)
+        trees[-1].free()
+        del P, Q, S
+        torch.cuda.empty_cache()
+        out["batched"] = bench_forest(knn, torch, dev)
+    else:
+        trees[-1].free()
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
         log(f"timing the oracle on the host ({threads} threads)")
