@@ -105,12 +105,23 @@ def bench_forest(knn, torch, dev) -> dict:
     T = torch.from_numpy(f.tree_ids).to(dev)
     S = torch.from_numpy(f.self_ids).to(dev)
     torch.cuda.synchronize()
+    # the autotuner picks bucket size, leaf batch and order on the first 64 trees
+    from paper_1607_08220_amd import autotune
+    ns = 64
+    sel = torch.from_numpy(np.flatnonzero(f.tree_ids < ns)).to(dev)
+    a = time.perf_counter()
+    tuned = autotune.tune(P[:int(f.offsets[ns])], Q[sel].contiguous(), f.k,
+                          self_ids=S[sel].contiguous(), offsets=f.offsets[:ns + 1],
+                          tree_ids=T[sel].contiguous(), reps=2)
+    log(f"forest: autotuned on {ns} trees in {time.perf_counter() - a:.1f} s: leaf "
+        f"{tuned['leaf_size']}, leaf batch {tuned['leaf_batch']}, order {tuned['order']}")
+    leaf, lb, order = tuned["leaf_size"], tuned["leaf_batch"], tuned["order"]
 
     def batched():
         a = time.perf_counter()
-        forest = knn.knn_build_batch(P, f.offsets, leaf_size=f.leaf)
+        forest = knn.knn_build_batch(P, f.offsets, leaf_size=leaf)
         b = time.perf_counter()
-        idx, d2 = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S)
+        idx, d2 = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb)
         torch.cuda.synchronize()
         c = time.perf_counter()
         forest.free()
@@ -131,8 +142,8 @@ def bench_forest(knn, torch, dev) -> dict:
     outs = []
     a = time.perf_counter()
     for t in range(len(f.offsets) - 1):
-        tr = knn.knn_build(P[int(f.offsets[t]):int(f.offsets[t + 1])], f.leaf)
-        outs.append(knn.knn_query_ex(tr, Qt[t], f.k, self_ids=St[t]))
+        tr = knn.knn_build(P[int(f.offsets[t]):int(f.offsets[t + 1])], leaf)
+        outs.append(knn.knn_query_ex(tr, Qt[t], f.k, self_ids=St[t], order=order, leaf_batch=lb))
         tr.free()
     torch.cuda.synchronize()
     per_call = (time.perf_counter() - a) * 1e3
@@ -147,7 +158,8 @@ def bench_forest(knn, torch, dev) -> dict:
     log(f"forest: batched build {bb:.1f} ms + query {bq:.2f} ms; per call {per_call:.0f} ms; "
         f"identical={same}")
     return {"workload": "forest512_6d", "trees": len(f.offsets) - 1, "points": n, "queries": m,
-            "k": f.k, "leaf_size": f.leaf, "batched_build_ms": bb, "batched_query_ms": bq,
+            "k": f.k, "autotuned": {"leaf_size": leaf, "leaf_batch": lb, "order": order},
+            "batched_build_ms": bb, "batched_query_ms": bq,
             "batched_ms": bb + bq, "per_call_ms": per_call, "speedup": per_call / (bb + bq),
             "build_mpts_per_s": n / (bb * 1e-3) / 1e6, "queries_per_s": m / (bq * 1e-3),
             "identical_to_per_call": same}

@@ -85,3 +85,15 @@ def test_forest_argument_errors(knn):
     for bad in ([0, 5, 5, 10], [1, 10], [0, 4, 11]):
         with pytest.raises((knn.KnnError, ValueError)):
             knn.knn_build_batch(X, bad)
+
+
+def test_autotune_picks_a_listed_config(knn):
+    from paper_1607_08220_amd import autotune
+    f = inputs.forest(6, d=4, lo_exp=6.0, hi_exp=12.0, q_per_tree=128, seed=3)
+    log("[case] autotune")
+    r = autotune.tune(dev(f.points), dev(f.queries), f.k, self_ids=dev(f.self_ids),
+                      offsets=f.offsets, tree_ids=dev(f.tree_ids), leaf_sizes=(16, 32),
+                      leaf_batches=(48, 64), orders=(0, 1), reps=1)
+    assert (r["leaf_size"], r["leaf_batch"], r["order"]) in {
+        (a["leaf_size"], a["leaf_batch"], a["order"]) for a in r["table"]}
+    assert len(r["table"]) == 8 and r["ms"] == min(a["ms"] for a in r["table"])
