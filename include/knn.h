@@ -251,6 +251,32 @@ int knn_server_stats(knn_server* s, int64_t* out /* [4] */);
  * trees).  NULL is OK. */
 int knn_server_destroy(knn_server* s);
 
+/*
+ * knn_classify -- k-NN classification of each query by a majority vote of its
+ * neighbours' labels, the baseline method the paper applies to its labelled
+ * data (Section V-C).
+ *   idx        device [m, k] int32 neighbour lists from a query, ascending by
+ *              distance, -1 padding; every index < the number of labels
+ *   labels     device int32 label of every point
+ *   out_class  device [m] int32: the label with the most votes; between labels
+ *              with equally many, the one whose first neighbour is nearer;
+ *              -1 when the query has no neighbour
+ *   out_votes  device [m] int32 or NULL: that label's vote count
+ * Errors: KNN_EINVAL, KNN_EDEVICE.
+ */
+int knn_classify(const int32_t* idx, int64_t m, int32_t k, const int32_t* labels,
+                 int32_t* out_class, int32_t* out_votes, void* stream);
+
+/*
+ * knn_regress -- k-NN regression (Section I names classification and
+ * regression): the mean of the neighbours' values, summed in FP32 left to
+ * right in neighbour order and divided by the neighbour count; NaN when the
+ * query has no neighbour.  idx as in knn_classify; values device FP32 per
+ * point; out device [m] FP32.
+ */
+int knn_regress(const int32_t* idx, int64_t m, int32_t k, const float* values, float* out,
+                void* stream);
+
 /* Free a tree and its device memory (waits for the device first).  NULL is OK. */
 int knn_tree_free(knn_tree* t);
 

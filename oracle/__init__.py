@@ -11,6 +11,9 @@ Functions and the passages they follow (arXiv 1607.08220):
                 split dimension, stable index shuffle, buckets, packing)
   query         Algorithm 1 of Section III-B/C with the readings listed at the
                 top of oracle.c (R1-R10)
+  merge         Section III-B step 5: the k nearest of two candidate lists
+  vote          the majority vote of the k neighbours' labels (Section V-C)
+  regress       the mean of the neighbours' values (Section I)
 """
 from __future__ import annotations
 
@@ -202,3 +205,53 @@ def build(points, leaf=32, max_depth=64, lib=None) -> Tree:
                                                       "packed")])
     return Tree(n=n, d=d, leaf=leaf, depth=int(lib.orc_tree_depth(h)), _handle=h, _lib=lib,
                 **arrs)
+
+
+def merge(ia, da, ib, db, k):
+    """k smallest (D, idx) keys of two per-query lists (padding idx < 0
+    ignored, an entry present in both counted once), padded (-1, +inf)."""
+    m = ia.shape[0]
+    oi = np.full((m, k), -1, np.int32)
+    od = np.full((m, k), np.inf, np.float32)
+    for q in range(m):
+        keys = {(float(d), int(i)) for i, d in zip(ia[q], da[q]) if i >= 0}
+        keys |= {(float(d), int(i)) for i, d in zip(ib[q], db[q]) if i >= 0}
+        for j, (d, i) in enumerate(sorted(keys)[:k]):
+            oi[q, j], od[q, j] = i, d
+    return oi, od
+
+
+def vote(idx, labels):
+    """Majority label of each row of neighbour indices (ascending distance,
+    -1 padding): most votes; among equally many, the label whose first
+    neighbour comes first; -1 for an empty row.  Returns (label, votes)."""
+    m = idx.shape[0]
+    out = np.full(m, -1, np.int32)
+    votes = np.zeros(m, np.int32)
+    for q in range(m):
+        row = [int(labels[i]) for i in idx[q] if i >= 0]
+        counts = {}
+        for c in row:
+            counts[c] = counts.get(c, 0) + 1
+        best = None
+        for c in row:  # the first occurrence order is the distance order
+            if best is None or counts[c] > counts[best]:
+                best = c
+        if best is not None:
+            out[q], votes[q] = best, counts[best]
+    return out, votes
+
+
+def regress(idx, values):
+    """Mean of the neighbours' values: float32 sum in neighbour order, left to
+    right, divided by the count (NaN for an empty row)."""
+    m = idx.shape[0]
+    out = np.full(m, np.nan, np.float32)
+    for q in range(m):
+        vals = [np.float32(values[i]) for i in idx[q] if i >= 0]
+        if vals:
+            acc = vals[0]
+            for v in vals[1:]:
+                acc = np.float32(acc + v)
+            out[q] = np.float32(acc / np.float32(len(vals)))
+    return out

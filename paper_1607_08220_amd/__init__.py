@@ -59,7 +59,8 @@ class _Host(ctypes.Structure):
 
 _lib = None
 EXPORTED = ("knn_build", "knn_build_ex", "knn_build_batch", "knn_query", "knn_query_ex",
-            "knn_query_batch", "knn_query_radius", "knn_merge", "knn_server_create",
+            "knn_query_batch", "knn_query_radius", "knn_merge", "knn_classify", "knn_regress",
+            "knn_server_create",
             "knn_server_submit", "knn_server_wait", "knn_server_stats", "knn_server_destroy", "knn_tree_free", "knn_tree_info", "knn_tree_export", "knn_last_error",
             "knn_set_profiling", "knn_get_profile")
 
@@ -93,6 +94,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.knn_server_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
     lib.knn_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.knn_server_destroy.argtypes = [vp]
+    lib.knn_classify.argtypes = [vp, i64, i32, vp, vp, vp, vp]
+    lib.knn_regress.argtypes = [vp, i64, i32, vp, vp, vp]
     lib.knn_tree_free.argtypes = [vp]
     lib.knn_tree_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.knn_tree_export.argtypes = [vp, ctypes.POINTER(_Host)]
@@ -401,6 +404,45 @@ def knn_server_stats(server: Server) -> dict:
 
 def knn_server_destroy(server: Server):
     server.close()
+
+
+def _idx_list(idx):
+    import torch
+    if not (isinstance(idx, torch.Tensor) and idx.is_cuda and idx.dtype == torch.int32
+            and idx.dim() == 2 and idx.is_contiguous()):
+        raise TypeError("idx must be a contiguous CUDA int32 [m, k] tensor")
+    return idx.shape[0], idx.shape[1]
+
+
+def knn_classify(idx, labels, votes: bool = False):
+    """Majority label of each query's neighbours: int32 [m] (and the vote counts)."""
+    import torch
+    m, k = _idx_list(idx)
+    if not (isinstance(labels, torch.Tensor) and labels.is_cuda and labels.dtype == torch.int32
+            and labels.is_contiguous()):
+        raise TypeError("labels must be a contiguous CUDA int32 tensor")
+    out = torch.empty(m, dtype=torch.int32, device=idx.device)
+    vo = torch.empty(m, dtype=torch.int32, device=idx.device) if votes else None
+    _check(load_library().knn_classify(ctypes.c_void_p(idx.data_ptr()), m, k,
+                                       ctypes.c_void_p(labels.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(vo.data_ptr()) if votes else None,
+                                       _stream(idx)))
+    return (out, vo) if votes else out
+
+
+def knn_regress(idx, values):
+    """Mean of each query's neighbours' values: float32 [m]."""
+    import torch
+    m, k = _idx_list(idx)
+    if not (isinstance(values, torch.Tensor) and values.is_cuda and values.dtype == torch.float32
+            and values.is_contiguous()):
+        raise TypeError("values must be a contiguous CUDA float32 tensor")
+    out = torch.empty(m, dtype=torch.float32, device=idx.device)
+    _check(load_library().knn_regress(ctypes.c_void_p(idx.data_ptr()), m, k,
+                                      ctypes.c_void_p(values.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream(idx)))
+    return out
 
 
 def knn_tree_info(tree: Tree) -> dict:

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libknn.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["knn_api.hip", "knn_build.hip", "knn_query.hip", "knn_serve.hip"]
+SOURCES = ["knn_api.hip", "knn_build.hip", "knn_query.hip", "knn_serve.hip", "knn_classify.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KNN_OFFLOAD_ARCH", "gfx950")

@@ -97,3 +97,35 @@ def test_radius_per_query_matches_scalar(knn):
         oi, od = oracle.bf32(w.points, w.queries, 7, r2=r2)
         assert_same(b[0].cpu().numpy(), b[1].cpu().numpy(), oi, od, f"oracle r2={r2}")
     t.free()
+
+
+def test_merge_random_lists_match_oracle(knn):
+    """Random sorted lists with shared entries, ties and padding."""
+    import torch
+    rng = np.random.default_rng(4)
+    m, ka, kb, k = 3000, 9, 5, 8
+    def lists(kk):
+        i = rng.integers(0, 40, size=(m, kk)).astype(np.int32)
+        d = rng.integers(0, 6, size=(m, kk)).astype(np.float32)  # many equal distances
+        pad = rng.random((m, kk)) < 0.2
+        d = np.where(pad, np.inf, d).astype(np.float32)
+        i = np.where(pad, -1, i).astype(np.int32)
+        o = np.lexsort((i, d), axis=1)  # ascending (D, idx), padding last
+        return np.take_along_axis(i, o, 1), np.take_along_axis(d, o, 1)
+    ia, da = lists(ka)
+    ib, db = lists(kb)
+    # drop duplicate indices inside one list (a list never repeats a point)
+    for arr_i, arr_d in ((ia, da), (ib, db)):
+        for q in range(m):
+            seen = set()
+            for j in range(arr_i.shape[1]):
+                if arr_i[q, j] in seen:
+                    arr_i[q, j], arr_d[q, j] = -1, np.inf
+                seen.add(arr_i[q, j])
+            o = np.lexsort((np.where(arr_i[q] < 0, 1 << 30, arr_i[q]), arr_d[q]))
+            arr_i[q], arr_d[q] = arr_i[q][o], arr_d[q][o]
+    log("[case] random merges")
+    oi, od = knn.knn_merge((dev(ia), dev(da)), (dev(ib), dev(db)), k)
+    torch.cuda.synchronize()
+    ei, ed = oracle.merge(ia, da, ib, db, k)
+    assert_same(oi.cpu().numpy(), od.cpu().numpy(), ei, ed, "random merges")

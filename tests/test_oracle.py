@@ -60,3 +60,24 @@ def test_oracle_depth_matches_log(orc):
     T = oracle.build(X, 32, lib=orc)
     base = int(np.ceil(np.log2(len(X) / 32)))
     assert base <= T.depth <= base + 3, T.depth
+
+
+def test_vote_regress_merge_hand_examples():
+    """Hand-worked cases of the application functions (Section V-C majority
+    vote, Section I regression, Section III-B step 5 merge)."""
+    labels = np.array([2, 0, 1, 0, 2, 1], np.int32)
+    idx = np.array([[4, 1, 3, 0],    # labels 2, 0, 0, 2 -> tie 2:2, the nearer (2) wins
+                    [1, 2, 5, -1],   # labels 0, 1, 1     -> 1 with 2 votes
+                    [-1, -1, -1, -1],
+                    [5, 0, 4, 1]], np.int32)  # 1, 2, 2, 0 -> 2 with 2 votes
+    c, v = oracle.vote(idx, labels)
+    assert c.tolist() == [2, 1, -1, 2] and v.tolist() == [2, 2, 0, 2]
+    vals = np.array([1.0, 2.0 ** -24, 2.0 ** -24, 3.0, 0.5, 1e8], np.float32)
+    r = oracle.regress(np.array([[0, 1, 2, -1], [5, 0, -1, -1], [-1, -1, -1, -1]], np.int32), vals)
+    # 1 + 2^-24 rounds back to 1 twice (left to right), then / 3
+    assert r[0] == np.float32(np.float32(1.0) / np.float32(3.0))
+    assert r[1] == np.float32(np.float32(1e8 + 1.0) / np.float32(2.0)) and np.isnan(r[2])
+    ia = np.array([[3, 5, -1]], np.int32); da = np.array([[1.0, 2.0, np.inf]], np.float32)
+    ib = np.array([[5, 7]], np.int32); db = np.array([[2.0, 2.0]], np.float32)
+    oi, od = oracle.merge(ia, da, ib, db, 4)
+    assert oi.tolist() == [[3, 5, 7, -1]] and od[0, :3].tolist() == [1.0, 2.0, 2.0]
