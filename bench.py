@@ -133,6 +133,36 @@ def bench_forest(knn, torch, dev) -> dict:
     bq = float(np.median([r[1] for r in runs]))
     idx, d2 = runs[-1][2], runs[-1][3]
 
+    # the batched query captured once in a graph and replayed
+    forest = knn.knn_build_batch(P, f.offsets, leaf_size=leaf)
+    gi_t = torch.empty_like(idx)
+    gd_t = torch.empty_like(d2)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
+                            out=(gi_t, gd_t))
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
+                            out=(gi_t, gd_t))
+    reps = []
+    graph_same = True
+    for _ in range(5):
+        gi_t.fill_(-1)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - a) * 1e3)
+        graph_same &= bool(torch.equal(gi_t, idx) and torch.equal(gd_t.view(torch.int32),
+                                                                   d2.view(torch.int32)))
+    del graph
+    forest.free()
+    bqg = float(np.median(reps))
+
     # the same work as one call per tree
     qsel = [np.flatnonzero(f.tree_ids == t) for t in range(len(f.offsets) - 1)]
     Qt = [Q[torch.from_numpy(s).to(dev)].contiguous() for s in qsel]
@@ -155,11 +185,12 @@ def bench_forest(knn, torch, dev) -> dict:
         same &= bool(np.array_equal(gi[s], oi) and np.array_equal(gd[s].view(np.uint32),
                                                                   od.view(np.uint32)))
     n, m = len(f.points), len(f.queries)
-    log(f"forest: batched build {bb:.1f} ms + query {bq:.2f} ms; per call {per_call:.0f} ms; "
-        f"identical={same}")
+    log(f"forest: batched build {bb:.1f} ms + query {bq:.2f} ms (graph replay {bqg:.2f} ms, "
+        f"identical={graph_same}); per call {per_call:.0f} ms; identical={same}")
     return {"workload": "forest512_6d", "trees": len(f.offsets) - 1, "points": n, "queries": m,
             "k": f.k, "autotuned": {"leaf_size": leaf, "leaf_batch": lb, "order": order},
-            "batched_build_ms": bb, "batched_query_ms": bq,
+            "batched_build_ms": bb, "batched_query_ms": bq, "graph_replay_query_ms": bqg,
+            "graph_replay_identical": graph_same,
             "batched_ms": bb + bq, "per_call_ms": per_call, "speedup": per_call / (bb + bq),
             "build_mpts_per_s": n / (bb * 1e-3) / 1e6, "queries_per_s": m / (bq * 1e-3),
             "identical_to_per_call": same}

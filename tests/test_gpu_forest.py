@@ -97,3 +97,37 @@ def test_autotune_picks_a_listed_config(knn):
     assert (r["leaf_size"], r["leaf_batch"], r["order"]) in {
         (a["leaf_size"], a["leaf_batch"], a["order"]) for a in r["table"]}
     assert len(r["table"]) == 8 and r["ms"] == min(a["ms"] for a in r["table"])
+
+
+def test_forest_query_graph_replay(knn):
+    """The batched query captured once in a graph and replayed, with eager
+    work and synchronization between replays, gives the eager result every
+    time."""
+    import torch
+    f = inputs.forest(20, d=6, lo_exp=8.0, hi_exp=15.0, q_per_tree=256, seed=21)
+    log(f"[case] graph replay rows={len(f.points)}")
+    forest = knn.knn_build_batch(dev(f.points), f.offsets, leaf_size=32)
+    Q, T, S = dev(f.queries), dev(f.tree_ids), dev(f.self_ids)
+    ei, ed = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S)
+    torch.cuda.synchronize()
+    ei, ed = ei.cpu().numpy(), ed.cpu().numpy()
+    oi = torch.empty((len(f.queries), f.k), dtype=torch.int32, device="cuda")
+    od = torch.empty((len(f.queries), f.k), dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm up on the capture stream
+        knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, out=(oi, od))
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, out=(oi, od))
+    for rep in range(4):
+        oi.fill_(-7)
+        od.fill_(-7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert_same(oi.cpu().numpy(), od.cpu().numpy(), ei, ed, f"replay {rep}")
+    del g
+    forest.free()
