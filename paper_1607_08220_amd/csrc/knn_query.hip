@@ -538,7 +538,7 @@ using LocateFn = void (*)(const NodeRec*, const float*, const int32_t*, int64_t,
 template <int D, bool STATS>
 TraverseFn pick_traverse(int k)
 {
-    constexpr int RB = D <= 4 ? 8 : 4;  // bucket rows per batch
+    constexpr int RB = D <= 10 ? 8 : 4;  // bucket rows per batch
     if (k <= 4) return k_traverse<D, 4, STATS, RB>;
     if (k <= 8) return k_traverse<D, 8, STATS, RB>;
     if (k <= 16) return k_traverse<D, 16, STATS, RB>;
