@@ -69,6 +69,11 @@ typedef struct {
                        steps, 4 heap inserts; summed over wavefronts (64 queries):
                        5 traversal-loop iterations, 6 bucket-row batches, 7 leaf
                        rounds, 8 heap-insert executions */
+    int32_t traversal; /* 0 (default): chosen by dimension; 1: stack-free walk from the
+                          query's home leaf (each node keeps its parent); 2: Algorithm 1's
+                          explicit stack, kept in LDS (used when the tree's depth fits);
+                          a scheduling knob, the result does not depend on it */
+    int32_t pad2_;
 } knn_query_params;
 
 typedef struct {

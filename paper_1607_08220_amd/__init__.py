@@ -40,7 +40,8 @@ class _BuildParams(ctypes.Structure):
 
 class _QueryParams(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("leaf_batch", ctypes.c_int32),
-                ("stats", ctypes.c_void_p)]
+                ("stats", ctypes.c_void_p), ("traversal", ctypes.c_int32),
+                ("pad2_", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -232,7 +233,7 @@ def knn_query(tree: Tree, queries, k: int, out=None):
 
 
 def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = math.inf,
-                 order: int = 0, out=None, stats=None, leaf_batch: int = 0):
+                 order: int = 0, out=None, stats=None, leaf_batch: int = 0, traversal: int = 0):
     """knn_query with self exclusion (int32 [m], -1 = none), radius and order.
     ``stats``: optional CUDA int64 [KNN_QUERY_STATS] tensor the traversal adds
     its counters to (see knn_query_params in knn.h)."""
@@ -254,7 +255,7 @@ def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = mat
             raise TypeError(f"stats must be a contiguous CUDA int64 tensor of "
                             f"{KNN_QUERY_STATS} counters")
         st = stats.data_ptr()
-    p = _QueryParams(order, leaf_batch, st)
+    p = _QueryParams(order, leaf_batch, st, traversal)
     _check(lib.knn_query_ex(tree.handle, ctypes.c_void_p(queries.data_ptr()), queries.shape[0],
                             k, sp, ctypes.c_float(r2_max), ctypes.byref(p),
                             ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
@@ -271,7 +272,8 @@ def _dev_i32_vec(t, name, m):
 
 
 def knn_query_batch(forest: Tree, queries, tree_ids, k: int, self_ids=None,
-                    r2_max: float = math.inf, order: int = 0, out=None, leaf_batch: int = 0):
+                    r2_max: float = math.inf, order: int = 0, out=None, leaf_batch: int = 0,
+                    traversal: int = 0):
     """k nearest neighbours of each query within its own tree of a forest
     (``tree_ids``: CUDA int32 [m])."""
     lib = load_library()
@@ -280,7 +282,7 @@ def knn_query_batch(forest: Tree, queries, tree_ids, k: int, self_ids=None,
     idx, d2 = _outputs(queries, k, out)
     tp = _dev_i32_vec(tree_ids, "tree_ids", m)
     sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
-    p = _QueryParams(order, leaf_batch, None)
+    p = _QueryParams(order, leaf_batch, None, traversal)
     _check(lib.knn_query_batch(forest.handle, ctypes.c_void_p(queries.data_ptr()), tp, m, k, sp,
                                ctypes.c_float(r2_max), ctypes.byref(p),
                                ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),

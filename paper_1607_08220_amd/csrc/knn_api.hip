@@ -173,6 +173,8 @@ int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     if (order != 0 && order != 1) return fail(KNN_EINVAL, "order must be 0 or 1");
     const int32_t batch = p && p->leaf_batch ? p->leaf_batch : kDefaultLeafBatch;
     if (batch < 1 || batch > 64) return fail(KNN_EINVAL, "leaf_batch must be in [0, 64]");
+    const int32_t traversal = p ? p->traversal : 0;
+    if (traversal < 0 || traversal > 2) return fail(KNN_EINVAL, "traversal must be 0, 1 or 2");
     DeviceGuard g(t->device);
     QuerySpec qs;
     qs.queries = queries;
@@ -184,6 +186,7 @@ int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     qs.qroot = roots;
     qs.order = order;
     qs.batch = batch;
+    qs.traversal = traversal;
     qs.out_idx = out_idx;
     qs.out_d2 = out_dist2;
     qs.stats = p ? reinterpret_cast<unsigned long long*>(p->stats) : nullptr;

@@ -134,6 +134,7 @@ struct QuerySpec {
     const int32_t* qroot = nullptr;  // per-query root node (forests)
     int32_t order = 0;
     int32_t batch = 48;
+    int32_t traversal = 0;           // 0 auto, 1 stack-free walk from the home leaf, 2 explicit stack
     int32_t* out_idx = nullptr;
     float* out_d2 = nullptr;
     unsigned long long* stats = nullptr;

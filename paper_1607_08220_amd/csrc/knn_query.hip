@@ -34,7 +34,9 @@ namespace knn {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
+constexpr int kXcds = 8;
+constexpr size_t kMaxStackLds = 160 * 1024;  // LDS of one workgroup on gfx950
+constexpr int kStackMinDim = 5;               // default: explicit stack from 5 dimensions  // accelerator complex dies of an MI355X, each with its own L2
 
 // q[dim] as a chain of selects.  The empty asm keeps the compiler from
 // turning the chain back into a dynamically indexed array (which it would
@@ -391,6 +393,185 @@ __global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
     }
 }
 
+// Algorithm 1 with its explicit stack, for deep walks (high dimensions):
+// each lane starts at its query's root and keeps the far children it has
+// still to visit, with their split-plane bounds, in a stack in LDS (at most
+// one entry per level of the path, so depth + 1 entries).  A popped entry
+// whose bound exceeds r' is dropped without touching HBM, where the
+// stack-free walk pays one dependent load per ancestor it climbs back
+// through.  Bucket scans, the heap and the wavefront vote are those of
+// k_traverse.
+constexpr int kPopAfterScan = -2;
+
+template <int D, int KC, bool STATS, int RB>
+__global__ __launch_bounds__(kBlock) void k_traverse_stack(TravArgs A, int sdepth)
+{
+    extern __shared__ int2 stk[];  // [sdepth][kBlock]: entry j of lane t at j * kBlock + t
+    const NodeRec* __restrict__ nodes = A.nodes;
+    const float* __restrict__ bbox = A.bbox;
+    const float* __restrict__ pts = A.pts;
+    const int64_t m = A.m;
+    const int batch = A.batch;
+    const int64_t per = gridDim.x / kXcds;
+    const int64_t blk = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int64_t slot = blk * blockDim.x + threadIdx.x;
+    unsigned long long n_enter = 0, n_leaf = 0, n_pts = 0, n_step = 0, n_ins = 0;
+    unsigned long long w_step = 0, w_rows = 0, w_round = 0, w_ins = 0;
+    if (slot < m) {  // every lane meets the counter sums below
+    const int64_t qid = A.order ? A.order[slot] : slot;
+    float q[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) q[t] = A.queries[qid * D + t];
+    const int32_t self = A.self_ids ? A.self_ids[qid] : -1;
+    uint64_t h[KC];
+    const int k = A.qk ? A.qk[qid] : A.k;
+    const int pad = KC - k;
+    const float r2 = A.r2s ? A.r2s[qid] : A.r2;
+    const uint64_t empty = r2 > 0.0f ? make_key(r2, 0) : 0;
+#pragma unroll
+    for (int j = 0; j < KC; ++j) h[j] = j < pad ? 0 : empty;
+    int2* my = stk + threadIdx.x;
+    int sp = 0;
+    int cur = A.root ? A.root[qid] : 0;
+    NodeRec r = nodes[cur];
+    float bb[2 * D];
+    load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+    int lstart = 0, lcnt = 0;
+    // the next pending far child whose bound does not exceed thr, or -1
+    auto pop = [&](float thr) {
+        while (sp > 0) {
+            --sp;
+            const int2 e = my[sp * kBlock];
+            if (__int_as_float(e.y) <= thr) return e.x;
+        }
+        return -1;
+    };
+    while (true) {
+        if constexpr (STATS) w_round += first_active_lane();
+        while (true) {
+            const bool walking = cur != -1 && lcnt == 0;
+            const unsigned long long wb = __ballot(walking);
+            if (wb == 0) break;
+            const int held = __popcll(__ballot(lcnt > 0));
+            if (held * 64 >= batch * (held + __popcll(wb))) break;
+            if (walking) {
+                if constexpr (STATS) {
+                    ++n_step;
+                    w_step += first_active_lane();
+                }
+                const float thr = key_dist(h[KC - 1]);
+                int next;
+                if (cur == kPopAfterScan) {
+                    next = pop(thr);
+                } else {
+                    if constexpr (STATS) ++n_enter;
+                    const float b = box_bound<D>(q, bb);
+                    if (b > thr) {  // no point of this node can enter H
+                        next = pop(thr);
+                    } else if (r.dim < 0) {  // a bucket: scan it, then pop
+                        lstart = r.a;
+                        lcnt = -r.dim;
+                        next = kPopAfterScan;
+                    } else {
+                        const float qd = select_dim<D>(q, r.dim);
+                        const bool left_near = qd < r.split;
+                        const float o = left_near ? r.split - qd : qd - r.split;
+                        if (sp < sdepth) {  // always: a path holds at most depth pending entries
+                            my[sp * kBlock] =
+                                make_int2(left_near ? r.a + 1 : r.a, __float_as_int(o * o));
+                            ++sp;
+                        }
+                        next = left_near ? r.a : r.a + 1;  // near child first
+                    }
+                }
+                cur = next;
+                if (cur >= 0) {
+                    r = nodes[cur];
+                    load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+                }
+            }
+        }
+        if (__ballot(lcnt > 0) == 0) break;  // no lane walks and none holds a bucket
+        if constexpr (STATS) {
+            n_leaf += lcnt > 0;
+            n_pts += lcnt;
+        }
+        constexpr int B = RB;
+        static_assert(B <= kRowPad, "row batches must fit in the padding rows");
+        const float* row0 = pts + (int64_t)lstart * (D + 1);
+        if (__ballot(lcnt > 0 && h[KC - 1] == empty) != 0) {
+            for (int j0 = 0; j0 < lcnt; j0 += B) {
+                if constexpr (STATS) w_rows += first_active_lane();
+                float x[B][D + 1];
+#pragma unroll
+                for (int b = 0; b < B; ++b) load_row<D>(row0 + (j0 + b) * (D + 1), x[b]);
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const int id = __float_as_int(x[b][D]);
+                    const uint64_t key = make_key(distance<D>(q, x[b]), id);
+                    if (j0 + b < lcnt && key < h[KC - 1] && id != self) {
+                        if constexpr (STATS) {
+                            ++n_ins;
+                            w_ins += first_active_lane();
+                        }
+                        heap_insert<KC>(h, key);
+                    }
+                }
+            }
+        } else {
+            for (int j0 = 0; j0 < lcnt; j0 += B) {
+                if constexpr (STATS) w_rows += first_active_lane();
+                float x[B][D + 1];
+#pragma unroll
+                for (int b = 0; b < B; ++b) load_row<D>(row0 + (j0 + b) * (D + 1), x[b]);
+                uint64_t keys[B];
+                unsigned cand = 0;
+                const uint64_t top = h[KC - 1];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const int id = __float_as_int(x[b][D]);
+                    keys[b] = make_key(distance<D>(q, x[b]), id);
+                    if (j0 + b < lcnt && keys[b] < top && id != self) cand |= 1u << b;
+                }
+                while (cand) {
+                    const int j = __builtin_ctz(cand);
+                    cand &= cand - 1;
+                    uint64_t key = keys[0];
+#pragma unroll
+                    for (int b = 1; b < B; ++b) key = j == b ? keys[b] : key;
+                    if (key < h[KC - 1]) {
+                        if constexpr (STATS) {
+                            ++n_ins;
+                            w_ins += first_active_lane();
+                        }
+                        heap_insert<KC>(h, key);
+                    }
+                }
+            }
+        }
+        lcnt = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        if (j >= pad) {
+            const int64_t o = (A.qout ? A.qout[qid] : qid * k) + (j - pad);
+            const bool none = h[j] == empty;
+            A.out_idx[o] = none ? -1 : (int)(uint32_t)h[j];
+            A.out_d2[o] = none ? INFINITY : key_dist(h[j]);
+        }
+    }
+    }  // slot < m
+    if constexpr (STATS) {
+        unsigned long long c[9] = {n_enter, n_leaf, n_pts, n_step, n_ins,
+                                   w_step, w_rows, w_round, w_ins};
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            for (int o = 32; o > 0; o >>= 1) c[j] += __shfl_xor(c[j], o);
+            if ((threadIdx.x & 63) == 0) atomicAdd(&A.stats[j], c[j]);
+        }
+    }
+}
+
 // Home leaf of every query: descend with the near-child rule (x < split
 // left).  Queries are grouped by key = (first packed position of the home
 // leaf) >> shift: buckets are contiguous in packed order, so key order is the
@@ -544,6 +725,35 @@ TraverseFn pick_traverse(int k)
     if (k <= 16) return k_traverse<D, 16, STATS, RB>;
     if (k <= 32) return k_traverse<D, 32, STATS, RB>;
     return k_traverse<D, 64, STATS, RB>;
+}
+
+using StackFn = void (*)(TravArgs, int);
+
+template <int D, bool STATS>
+StackFn pick_stack(int k)
+{
+    constexpr int RB = D <= 10 ? 8 : 4;
+    if (k <= 4) return k_traverse_stack<D, 4, STATS, RB>;
+    if (k <= 8) return k_traverse_stack<D, 8, STATS, RB>;
+    if (k <= 16) return k_traverse_stack<D, 16, STATS, RB>;
+    if (k <= 32) return k_traverse_stack<D, 32, STATS, RB>;
+    return k_traverse_stack<D, 64, STATS, RB>;
+}
+
+StackFn stack_for(int d, int k, bool stats)
+{
+    switch (d) {
+#define KNN_DIM_CASE(DD) \
+    case DD:             \
+        return stats ? pick_stack<DD, true>(k) : pick_stack<DD, false>(k);
+        KNN_DIM_CASE(1) KNN_DIM_CASE(2) KNN_DIM_CASE(3) KNN_DIM_CASE(4)
+        KNN_DIM_CASE(5) KNN_DIM_CASE(6) KNN_DIM_CASE(7) KNN_DIM_CASE(8)
+        KNN_DIM_CASE(9) KNN_DIM_CASE(10) KNN_DIM_CASE(11) KNN_DIM_CASE(12)
+        KNN_DIM_CASE(13) KNN_DIM_CASE(14) KNN_DIM_CASE(15) KNN_DIM_CASE(16)
+#undef KNN_DIM_CASE
+    default:
+        return nullptr;
+    }
 }
 
 TraverseFn traverse_for(int d, int k, bool stats)
@@ -710,7 +920,20 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     A.out_idx = qs.out_idx;
     A.out_d2 = qs.out_d2;
     A.stats = qs.stats;
-    hipLaunchKernelGGL(tf, dim3(tgrid), dim3(kBlock), 0, st, A);
+    // the explicit stack needs (depth + 1) entries of 8 bytes per lane in LDS
+    const size_t stk_bytes = sizeof(int2) * (size_t)(t->depth + 1) * kBlock;
+    const bool use_stack = stk_bytes <= kMaxStackLds &&
+                           (qs.traversal == 2 || (qs.traversal == 0 && d >= kStackMinDim));
+    if (use_stack) {
+        StackFn sf = stack_for(d, qs.k, qs.stats != nullptr);
+        if (stk_bytes > 64 * 1024)
+            KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(sf),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)stk_bytes));
+        hipLaunchKernelGGL(sf, dim3(tgrid), dim3(kBlock), stk_bytes, st, A, t->depth + 1);
+    } else {
+        hipLaunchKernelGGL(tf, dim3(tgrid), dim3(kBlock), 0, st, A);
+    }
     KNN_HIP(hipGetLastError());
     prof_mark(st, 8);
     return KNN_OK;

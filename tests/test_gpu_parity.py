@@ -259,3 +259,23 @@ def test_fp64_cross_check(knn):
             b = bd[r, c]
             assert a == b or abs(a - b) < 1e-6 * max(a, b)
         t.free()
+
+
+@pytest.mark.parametrize("d", [1, 3, 6, 10, 16])
+def test_both_traversals_match_oracle(knn, d):
+    """The stack-free walk and the explicit-stack form give the oracle's
+    result on the same tree, in both query orders."""
+    import torch
+    n = 60_011
+    X = inputs.clustered(n, seed=90, n_clusters=40) if d == 3 else inputs.corr_gauss(n, d, seed=91)
+    ids = np.random.default_rng(d).choice(n, 2_000, replace=False).astype(np.int32)
+    log(f"[case] traversals d={d}")
+    t = knn.knn_build(dev(X), 32)
+    bi, bd = oracle.bf32(X, X[ids], 9, self_ids=ids)
+    for trav in (1, 2):
+        for order in (0, 1):
+            gi, gd = knn.knn_query_ex(t, dev(X[ids]), 9, self_ids=dev(ids), traversal=trav,
+                                      order=order)
+            torch.cuda.synchronize()
+            assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"traversal {trav} order {order}")
+    t.free()
