@@ -114,14 +114,17 @@ def bench_forest(knn, torch, dev) -> dict:
                           self_ids=S[sel].contiguous(), offsets=f.offsets[:ns + 1],
                           tree_ids=T[sel].contiguous(), reps=2)
     log(f"forest: autotuned on {ns} trees in {time.perf_counter() - a:.1f} s: leaf "
-        f"{tuned['leaf_size']}, leaf batch {tuned['leaf_batch']}, order {tuned['order']}")
-    leaf, lb, order = tuned["leaf_size"], tuned["leaf_batch"], tuned["order"]
+        f"{tuned['leaf_size']}, leaf batch {tuned['leaf_batch']}, order {tuned['order']}, "
+        f"traversal {tuned['traversal']}")
+    leaf, lb, order, trav = (tuned["leaf_size"], tuned["leaf_batch"], tuned["order"],
+                             tuned["traversal"])
 
     def batched():
         a = time.perf_counter()
         forest = knn.knn_build_batch(P, f.offsets, leaf_size=leaf)
         b = time.perf_counter()
-        idx, d2 = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb)
+        idx, d2 = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
+                                      traversal=trav)
         torch.cuda.synchronize()
         c = time.perf_counter()
         forest.free()
@@ -141,13 +144,13 @@ def bench_forest(knn, torch, dev) -> dict:
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
-                            out=(gi_t, gd_t))
+                            traversal=trav, out=(gi_t, gd_t))
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
-                            out=(gi_t, gd_t))
+                            traversal=trav, out=(gi_t, gd_t))
     reps = []
     graph_same = True
     for _ in range(5):
@@ -173,7 +176,8 @@ def bench_forest(knn, torch, dev) -> dict:
     a = time.perf_counter()
     for t in range(len(f.offsets) - 1):
         tr = knn.knn_build(P[int(f.offsets[t]):int(f.offsets[t + 1])], leaf)
-        outs.append(knn.knn_query_ex(tr, Qt[t], f.k, self_ids=St[t], order=order, leaf_batch=lb))
+        outs.append(knn.knn_query_ex(tr, Qt[t], f.k, self_ids=St[t], order=order, leaf_batch=lb,
+                                     traversal=trav))
         tr.free()
     torch.cuda.synchronize()
     per_call = (time.perf_counter() - a) * 1e3
@@ -188,7 +192,8 @@ def bench_forest(knn, torch, dev) -> dict:
     log(f"forest: batched build {bb:.1f} ms + query {bq:.2f} ms (graph replay {bqg:.2f} ms, "
         f"identical={graph_same}); per call {per_call:.0f} ms; identical={same}")
     return {"workload": "forest512_6d", "trees": len(f.offsets) - 1, "points": n, "queries": m,
-            "k": f.k, "autotuned": {"leaf_size": leaf, "leaf_batch": lb, "order": order},
+            "k": f.k, "autotuned": {"leaf_size": leaf, "leaf_batch": lb, "order": order,
+                                    "traversal": trav},
             "batched_build_ms": bb, "batched_query_ms": bq, "graph_replay_query_ms": bqg,
             "graph_replay_identical": graph_same,
             "batched_ms": bb + bq, "per_call_ms": per_call, "speedup": per_call / (bb + bq),

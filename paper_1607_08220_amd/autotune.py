@@ -3,9 +3,11 @@
 The knobs change speed only, never results: the bucket size (Section III-A1
 reports 32 as the best for its data; other data and hardware may differ),
 the traversal's leaf batch (how many of a wavefront's 64 lanes must hold a
-bucket before it scans) and the query order (grouped by home leaf, or as
-given).  ``tune`` builds the trees for each bucket size, times the queries
-for every leaf batch and order, and returns the fastest combination.  Every
+bucket before it scans), the query order (grouped by home leaf, or as given)
+and the traversal form (stack-free walk from the home leaf, or Algorithm 1's
+explicit stack).  ``tune`` builds the trees for each bucket size, times the
+queries for every leaf batch, order and traversal form, and returns the
+fastest combination.  Every
 timed call goes through the C-ABI (``knn_build_batch``/``knn_query_batch``
 for forests, ``knn_build_ex``/``knn_query_ex`` otherwise).
 """
@@ -33,9 +35,9 @@ def _time(fn, reps: int) -> float:
 
 
 def tune(points, queries, k: int, self_ids=None, offsets=None, tree_ids=None,
-         leaf_sizes=(16, 32, 64), leaf_batches=(32, 48, 64), orders=(0, 1), reps: int = 3,
-         build_weight: float = 1.0) -> dict:
-    """Return {"leaf_size", "leaf_batch", "order", "ms", "table"}: the knobs
+         leaf_sizes=(16, 32, 64), leaf_batches=(32, 48, 64), orders=(0, 1),
+         traversals=(1, 2), reps: int = 3, build_weight: float = 1.0) -> dict:
+    """Return {"leaf_size", "leaf_batch", "order", "traversal", "ms", "table"}: the knobs
     minimising build_weight * build time + query time on this sample.
     ``points``/``queries`` are CUDA float32 tensors; for a forest pass the host
     ``offsets`` and the CUDA int32 ``tree_ids`` of the queries."""
@@ -47,18 +49,19 @@ def tune(points, queries, k: int, self_ids=None, offsets=None, tree_ids=None,
             build = lambda: knn.knn_build_ex(points, leaf_size=leaf)  # noqa: E731
         t_build = _time(lambda: build().free(), reps)
         tree = build()
-        for lb, order in itertools.product(leaf_batches, orders):
+        for lb, order, trav in itertools.product(leaf_batches, orders, traversals):
             if offsets is not None:
                 q = lambda: knn.knn_query_batch(tree, queries, tree_ids, k,  # noqa: E731
-                                                self_ids=self_ids, order=order, leaf_batch=lb)
+                                                self_ids=self_ids, order=order, leaf_batch=lb,
+                                                traversal=trav)
             else:
                 q = lambda: knn.knn_query_ex(tree, queries, k, self_ids=self_ids,  # noqa: E731
-                                             order=order, leaf_batch=lb)
+                                             order=order, leaf_batch=lb, traversal=trav)
             t_query = _time(q, reps)
-            table.append({"leaf_size": leaf, "leaf_batch": lb, "order": order,
+            table.append({"leaf_size": leaf, "leaf_batch": lb, "order": order, "traversal": trav,
                           "build_ms": t_build * 1e3, "query_ms": t_query * 1e3,
                           "ms": (build_weight * t_build + t_query) * 1e3})
         tree.free()
     best = min(table, key=lambda r: r["ms"])
-    return {**{key: best[key] for key in ("leaf_size", "leaf_batch", "order", "ms")},
+    return {**{key: best[key] for key in ("leaf_size", "leaf_batch", "order", "traversal", "ms")},
             "table": table}

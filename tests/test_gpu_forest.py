@@ -96,7 +96,7 @@ def test_autotune_picks_a_listed_config(knn):
                       leaf_batches=(48, 64), orders=(0, 1), reps=1)
     assert (r["leaf_size"], r["leaf_batch"], r["order"]) in {
         (a["leaf_size"], a["leaf_batch"], a["order"]) for a in r["table"]}
-    assert len(r["table"]) == 8 and r["ms"] == min(a["ms"] for a in r["table"])
+    assert len(r["table"]) == 16 and r["ms"] == min(a["ms"] for a in r["table"])
 
 
 def test_forest_query_graph_replay(knn):
