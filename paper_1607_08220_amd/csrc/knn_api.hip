@@ -1,6 +1,6 @@
 // C-ABI entry points of libknn.so: argument checks, error reporting, tree
-// lifetime, export and profiling.  The arithmetic lives in knn_build.hip and
-// knn_query.hip.
+// lifetime, export and profiling.  The arithmetic lives in knn_build.hip,
+// knn_query.hip and knn_classify.hip; the serving loop in knn_serve.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -5,23 +5,30 @@
 // (III-A iii), then packs buckets (III-A iv).  Here:
 //   * ingest:    caller AoS [n,d] -> SoA columns + index column
 //   * level pass (nodes above `W` points), one node list per level:
-//       k_sample   sample of min(1024, cnt) points, FP64 variance per dim,
-//                  split dim = argmax, sorted sample of that dim (LDS bitonic)
-//       k_hist     histogram of every node point over the sorted sample
-//                  (per-lane binary search in LDS, LDS atomics)
-//       k_choose   running counts C_j, j* = argmin |2 C_j - cnt|
+//       k_sample   one wavefront per node: sample of min(1024, cnt) points,
+//                  FP64 variance per dim, split dim = argmax, the sample of
+//                  that dim sorted in registers; keeps the ranks around the
+//                  middle that the histogram resolves
+//       k_hist     counts below / above that window of ranks and the bins
+//                  inside it (per-wavefront LDS queue, LDS binary search)
+//       k_choose   C_j over the window, j* = argmin |2 C_j - cnt| once the
+//                  window is shown to hold it, else the node's full histogram
+//                  (k_choose_wave: the same with one wavefront per node)
 //       k_count    per-wavefront count of points going left (ballot)
 //       k_blkscan  per-node exclusive scan of block counts
 //       k_scatter  stable partition of coordinates + index into the other
-//                  ping-pong buffer (ballot + mbcnt ranks)
+//                  ping-pong buffer (ballot + mbcnt ranks, LDS staging)
+//       k_plan_*   children ids, next level's node list and block tables,
+//                  subtree entries: prefix sums on the device
 //   * k_finish:  one wavefront per node of at most W points builds its whole
 //                subtree in LDS (every point is a sample there, so the split
 //                is the exact value the histogram rule selects), computes the
 //                tight boxes and writes the packed bucket rows
 //   * k_compact: gives every subtree node its final id; k_bbox_up fills the
 //                boxes of the level-pass nodes bottom-up.
-// Node ids are deterministic: level-pass nodes in breadth-first order, then
-// each subtree's nodes in the order the subtree list is kept.
+// Node ids are deterministic: the roots first (tree t of a forest is node t),
+// then level-pass nodes in breadth-first order, then each subtree's nodes in
+// the order the subtree list is kept.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

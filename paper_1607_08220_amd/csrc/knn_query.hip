@@ -10,7 +10,8 @@
 // split-plane bound of the far child and descends there if it may hold a
 // closer point; coming back from the far child it goes up again.  This visits
 // the same nodes as Algorithm 1 with the near child pushed last, with the
-// bounds re-tested against the current r'.
+// bounds re-tested against the current r'.  For deep high-dimensional walks
+// k_traverse_stack keeps Algorithm 1's explicit stack instead (in LDS).
 //
 // Queries are first grouped by the leaf that contains them (k_locate +
 // counting sort), and a lane starts at its query's home leaf: the leaf is
