@@ -1003,11 +1003,12 @@ __device__ inline void lane_tree_n(int R, Val val, double (&out)[N])
 }
 
 // Registers per lane of the largest node a finish wavefront handles: the
-// subtree limit is 64 * kFinishMaxR<D> points (1024 up to 3 dimensions, 512
-// up to 8, else 256), which keeps the larger dimensions within the register
-// file.
+// subtree limit is 64 * kFinishMaxR<D> points (512 up to 8 dimensions, else
+// 256).  The finish is latency-bound, so this limit is set by occupancy: a
+// 1024-point subtree needs twice the LDS and, for its 16-row nodes, about
+// twice the registers, which halves the wavefronts a SIMD can switch between.
 template <int D>
-constexpr int kFinishMaxR = D <= 3 ? 16 : (D <= 8 ? 8 : 4);
+constexpr int kFinishMaxR = D <= 8 ? 8 : 4;
 
 // Context of one wavefront's subtree build.
 struct FinishCtx {
@@ -1054,8 +1055,9 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
     }
     const bool small = lc <= leaf;
     // box, and the FP64 variance of every dimension (all node points),
-    // DC dimensions at a time so their reductions overlap
-    constexpr int DC = D <= 3 ? D : (D <= 8 ? 2 : 1);
+    // DC dimensions at a time so their reductions overlap (one at a time for
+    // the 8-row nodes, whose registers would otherwise set the occupancy)
+    constexpr int DC = RM >= 8 ? 1 : (D <= 3 ? D : (D <= 8 ? 2 : 1));
     float lo_d[D], hi_d[D];
     double bestV = -1.0;
     int best = 0;
@@ -1633,7 +1635,7 @@ inline unsigned blocks_for(int64_t items, int per) { return (unsigned)((items + 
 
 }  // namespace
 
-int32_t finish_max_points(int32_t d) { return d <= 3 ? 1024 : (d <= 8 ? 512 : 256); }
+int32_t finish_max_points(int32_t d) { return d <= 8 ? 512 : 256; }
 
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w)
 {
