@@ -92,7 +92,7 @@ static int32_t subtree_points_for(int32_t d, int32_t requested)
         lds_max = prop.sharedMemPerBlock;
     int32_t w = requested > 0 ? pow2_floor(std::min(requested, kSampleMax)) : default_subtree_points(d);
     w = std::min(w, finish_max_points(d));
-    while (w > 64 && finish_lds_bytes_per_wave(d, w) * 4 > lds_max) w >>= 1;
+    while (w > 64 && finish_lds_bytes_per_wave(d, finish_tile_points(d, w)) * 4 > lds_max) w >>= 1;
     return std::max(w, 64);
 }
 

@@ -224,7 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(Level L, const float* __restr
                                                    uint32_t* __restrict__ hist)
 {
     const int lane = threadIdx.x & 63;
-    const int node = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    // wavefront-uniform: node data loads through the scalar unit
+    const int node = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (node >= L.cnt[0]) return;
     const int64_t start = L.start[node], c = L.count[node];
     for (int i = lane; i < kWinRow; i += kWave) hist[(int64_t)node * kWinRow + i] = 0u;
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_choose_wave(Level L, int32_t* __rest
 {
     __shared__ float sv_all[kWavesPerBlock][kSampleMax];
     __shared__ uint32_t hf_all[kWavesPerBlock][kBins];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int node = blockIdx.x * kWavesPerBlock + w;
     if (node >= L.cnt[0]) return;  // only wavefront-level synchronization below
     const int64_t start = L.start[node], c = L.count[node];
@@ -694,7 +695,8 @@ __global__ __launch_bounds__(kBlock) void k_count(Level L, const int32_t* __rest
                                                   const float* __restrict__ cols, int64_t n,
                                                   uint32_t* __restrict__ wave_left)
 {
-    const int b = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = blockIdx.x, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (b >= L.cnt[1]) return;
     const int node = L.bnode[b];
     const int64_t start = L.start[node], c = L.count[node];
@@ -1002,13 +1004,63 @@ __device__ inline void lane_tree_n(int R, Val val, double (&out)[N])
     }
 }
 
+// The split of a node whose every point is a sample (the histogram rule
+// with s = cnt): the value of rank floor(lc/2) of the keys, or the next larger
+// value, whichever leaves the count below it closer to lc/2 (ties to the
+// smaller value).  The rank is found by a bitwise search over the ordered keys
+// (wavefront ballots); key[r] is the key of node point lane + 64 r, for
+// r < R, and kmin < kmax are the smallest and largest keys.
+template <int RM>
+__device__ inline void median_split(const uint32_t (&key)[RM], int R, int lc, int lane,
+                                    uint32_t kmin, uint32_t kmax, float& split, int& nl)
+{
+    const int m = lc >> 1;
+    const int hb = 31 - __clz(kmin ^ kmax);
+    uint32_t ans = hb >= 31 ? 0u : (kmin & ~((2u << hb) - 1u));
+    for (int b = hb; b >= 0; --b) {
+        const uint32_t t = ans | ((1u << b) - 1u);
+        int cnt = 0;
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+            if (r < R) cnt += __popcll(__ballot(lane + kWave * r < lc && key[r] <= t));
+        if (cnt <= m) ans |= 1u << b;
+    }
+    int r_lo = 0, r_hi = 0;
+    uint32_t kn = 0xffffffffu;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        if (r < R) {
+            const bool ok = lane + kWave * r < lc;
+            r_lo += __popcll(__ballot(ok && key[r] < ans));
+            r_hi += __popcll(__ballot(ok && key[r] <= ans));
+            if (ok && key[r] > ans) kn = min(kn, key[r]);
+        }
+    }
+    kn = wave_min_u32(kn);
+    const bool ok_star = r_lo > 0, ok_next = r_hi < lc;
+    if (ok_star && (!ok_next || (lc - 2 * r_lo) <= (2 * r_hi - lc))) {
+        split = key_float(ans);
+        nl = r_lo;
+    } else {
+        split = key_float(kn);
+        nl = r_hi;
+    }
+}
+
 // Registers per lane of the largest node a finish wavefront handles: the
 // subtree limit is 64 * kFinishMaxR<D> points (512 up to 8 dimensions, else
 // 256).  The finish is latency-bound, so this limit is set by occupancy: a
 // 1024-point subtree needs twice the LDS and, for its 16-row nodes, about
 // twice the registers, which halves the wavefronts a SIMD can switch between.
+constexpr int finish_rows(int d) { return d <= 8 ? 8 : 4; }
 template <int D>
-constexpr int kFinishMaxR = D <= 8 ? 8 : 4;
+constexpr int kFinishMaxR = finish_rows(D);
+// Rows per lane of a subtree node split straight from HBM: subtrees of up to
+// 64 * kGlobalRows points are handed to the finish, and their nodes above the
+// LDS tile are split in registers, one level per pass over the node.
+constexpr int kGlobalRows = 16;
+// Stack entry flag of a node whose points are in a HBM buffer, not in LDS.
+constexpr int kInHbm = 1 << 17;
 
 // Context of one wavefront's subtree build.
 struct FinishCtx {
@@ -1154,40 +1206,9 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
         v[r] = ok ? xv : 0.0f;
         key[r] = ok ? float_key(v[r]) : 0xffffffffu;
     }
-    const uint32_t kmin = float_key(blo), kmax = float_key(bhi);
-    const int m = lc >> 1;
-    const int hb = 31 - __clz(kmin ^ kmax);  // kmin != kmax because the variance is > 0
-    uint32_t ans = hb >= 31 ? 0u : (kmin & ~((2u << hb) - 1u));
-    for (int b = hb; b >= 0; --b) {
-        const uint32_t t = ans | ((1u << b) - 1u);
-        int cnt = 0;
-#pragma unroll
-        for (int r = 0; r < RM; ++r)
-            if (r < R) cnt += __popcll(__ballot(lane + kWave * r < lc && key[r] <= t));
-        if (cnt <= m) ans |= 1u << b;
-    }
-    int r_lo = 0, r_hi = 0;
-    uint32_t kn = 0xffffffffu;
-#pragma unroll
-    for (int r = 0; r < RM; ++r) {
-        if (r < R) {
-            const bool ok = lane + kWave * r < lc;
-            r_lo += __popcll(__ballot(ok && key[r] < ans));
-            r_hi += __popcll(__ballot(ok && key[r] <= ans));
-            if (ok && key[r] > ans) kn = min(kn, key[r]);
-        }
-    }
-    kn = wave_min_u32(kn);
-    const bool ok_star = r_lo > 0, ok_next = r_hi < lc;
     float split;
     int nl;
-    if (ok_star && (!ok_next || (lc - 2 * r_lo) <= (2 * r_hi - lc))) {
-        split = key_float(ans);
-        nl = r_lo;
-    } else {
-        split = key_float(kn);
-        nl = r_hi;
-    }
+    median_split<RM>(key, R, lc, lane, float_key(blo), float_key(bhi), split, nl);
     // stable partition into the other permutation array
     int run_l = 0, run_r = 0;
 #pragma unroll
@@ -1231,25 +1252,180 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
     return bad ? 0 : 2;
 }
 
-// One wavefront builds the whole subtree of one node of at most W points in
-// LDS.  Every point is a sample here (W <= 1024), so the histogram rule picks
-// the value of rank floor(cnt/2) or the next larger value, whichever has its
+// Split one subtree node of more points than the LDS tile holds, straight
+// from a HBM buffer pair: its lc <= 64 * kGlobalRows points sit at
+// [gs + ls, gs + ls + lc) of columns scol / indices sidx, node order; the
+// stable partition goes to the same range of dcol / didx (the other buffer of
+// the ping-pong pair, which no other subtree uses there).  The box, the split
+// dimension (FP64 variance, the same pairwise tree as finish_node), the split
+// (median_split) and the child records are those of finish_node; a node that
+// is a bucket writes its packed rows from the buffer.  Returns the number of
+// stack entries written (its children, both marked kInHbm for the other
+// buffer).
+template <int D>
+__device__ int finish_global(const FinishCtx& cx, const float* __restrict__ scol,
+                             const int32_t* __restrict__ sidx, float* __restrict__ dcol,
+                             int32_t* __restrict__ didx, int64_t n, int id, int ls, int lc,
+                             int dep, int g, int sp, int& nloc, bool& bad)
+{
+    constexpr int RG = kGlobalRows;
+    constexpr int D2 = 2 * D;
+    const int lane = cx.lane;
+    const int64_t s0 = cx.gs + ls;
+    const int R = (lc + kWave - 1) / kWave;
+    const bool small = lc <= cx.leaf;
+    double bestV = -1.0;
+    int best = 0;
+    float blo = 0.0f, bhi = 0.0f;
+    // one dimension per pass, not unrolled: the registers of this path are
+    // counted against the whole kernel's occupancy
+#pragma unroll 1
+    for (int dd = 0; dd < D; ++dd) {
+        const float* col = scol + (int64_t)dd * n + s0;
+        float v[RG];
+        float lo[1] = {INFINITY}, hi[1] = {-INFINITY};
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {  // whole rows: the buffers have a tail
+            const int j = lane + kWave * r;
+            const float x = r < R ? col[j] : 0.0f;
+            const bool ok = j < lc;
+            v[r] = ok ? x : 0.0f;
+            lo[0] = fminf(lo[0], ok ? x : INFINITY);
+            hi[0] = fmaxf(hi[0], ok ? x : -INFINITY);
+        }
+        wave_minmax<1>(lo, hi);
+        if (lane == 0) {
+            cx.tb[(int64_t)id * D2 + dd] = lo[0];
+            cx.tb[(int64_t)id * D2 + D + dd] = hi[0];
+        }
+        if (!small) {
+            double part[1], S[1], V[1];
+            lane_tree_n<1, RG>(R, [&](int, int r) { return (double)v[r]; }, part);
+            wave_tree_n<1>(part, S);
+            const double dlc = (double)lc;
+            lane_tree_n<1, RG>(
+                R,
+                [&](int, int r) {
+                    const double wv = dlc * (double)v[r] - S[0];
+                    return (lane + kWave * r < lc) ? wv * wv : 0.0;
+                },
+                part);
+            wave_tree_n<1>(part, V);
+            if (V[0] > bestV) {
+                bestV = V[0];
+                best = dd;
+                blo = lo[0];
+                bhi = hi[0];
+            }
+        }
+    }
+    if (small || !(bestV > 0.0)) {  // bucket (or identical points): final rows
+        if (lane == 0) {
+            cx.trec[id].a = (int32_t)s0;
+            cx.trec[id].split = 0.0f;
+            cx.trec[id].dim = -lc;
+        }
+        for (int j = lane; j < lc; j += kWave) {
+            const int64_t row = (s0 + j) * (D + 1);
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) cx.pts[row + dd] = scol[(int64_t)dd * n + s0 + j];
+            cx.pts[row + D] = __int_as_float(sidx[s0 + j]);
+        }
+        return 0;
+    }
+    uint32_t key[RG];
+    {
+        const float* col = scol + (int64_t)best * n + s0;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const int j = lane + kWave * r;
+            const float x = r < R ? col[j] : 0.0f;
+            key[r] = j < lc ? float_key(x) : 0xffffffffu;
+        }
+    }
+    float split;
+    int nl;
+    median_split<RG>(key, R, lc, lane, float_key(blo), float_key(bhi), split, nl);
+    // destinations of the stable partition (left block, then right block);
+    // key order is value order, so the test runs on the keys
+    const uint32_t ks = float_key(split);
+    int dst[RG];
+    int run_l = 0, run_r = 0;
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+        dst[r] = 0;
+        if (r < R) {
+            const bool ok = lane + kWave * r < lc;
+            const bool f = ok && key[r] < ks;
+            const uint64_t bl = __ballot(f), bv = __ballot(ok);
+            dst[r] = f ? run_l + (int)lanes_below(bl) : nl + run_r + (int)lanes_below(bv & ~bl);
+            run_l += __popcll(bl);
+            run_r += __popcll(bv & ~bl);
+        }
+    }
+#pragma unroll 1
+    for (int dd = 0; dd <= D; ++dd) {
+        const float* src = dd < D ? scol + (int64_t)dd * n + s0
+                                  : reinterpret_cast<const float*>(sidx + s0);
+        float* out = dd < D ? dcol + (int64_t)dd * n + s0 : reinterpret_cast<float*>(didx + s0);
+        float t[RG];
+#pragma unroll
+        for (int r = 0; r < RG; ++r) t[r] = r < R ? src[lane + kWave * r] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < RG; ++r)
+            if (r < R && lane + kWave * r < lc) out[dst[r]] = t[r];
+    }
+    const int L = nloc, Rc = nloc + 1;
+    nloc += 2;
+    if (cx.depth0 + dep + 1 > cx.max_depth || sp + 2 > kStack) bad = true;
+    if (lane == 0) {
+        cx.trec[id].a = L;
+        cx.trec[id].split = split;
+        cx.trec[id].dim = best;
+        cx.trec[L].parent = id;
+        cx.trec[Rc].parent = id;
+        if (!bad) {
+            const int wd = (dep + 1) | ((g ^ 1) << 16) | kInHbm;
+            const int4 lft = make_int4(L, ls, nl, wd);
+            const int4 rgt = make_int4(Rc, ls + nl, lc - nl, wd);
+            if (nl <= lc - nl) {
+                cx.stack[sp] = rgt;
+                cx.stack[sp + 1] = lft;
+            } else {
+                cx.stack[sp] = lft;
+                cx.stack[sp + 1] = rgt;
+            }
+        }
+    }
+    // the children are read back from HBM by other lanes of this wavefront:
+    // wait for the stores (the CU's L1 is coherent for its own stores)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return bad ? 0 : 2;
+}
+
+// One wavefront builds the whole subtree of one node of at most 64 *
+// kGlobalRows points.  Nodes larger than the LDS tile of W points are split
+// in registers straight from HBM (finish_global); a node that fits is loaded
+// into the tile and it and its descendants are split there (finish_node).
+// Every point is a sample at these sizes, so the histogram rule picks the
+// value of rank floor(cnt/2) or the next larger value, whichever has its
 // count below closer to cnt/2 (ties to the smaller value); the rank is found
-// by a bitwise search over the ordered keys with wavefront ballots.  The
-// index permutation ping-pongs between two LDS arrays, and each bucket's
+// by a bitwise search over the ordered keys with wavefront ballots.  In LDS
+// the index permutation ping-pongs between two arrays, and each bucket's
 // packed rows are written as soon as the bucket is final.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_finish(
-    const SubEntry* __restrict__ subs, int32_t n_sub, const float* __restrict__ colsA,
-    const int32_t* __restrict__ idxA, const float* __restrict__ colsB,
-    const int32_t* __restrict__ idxB, int64_t n, int leaf, int W, int max_depth,
+    const SubEntry* __restrict__ subs, int32_t n_sub, float* colsA, int32_t* idxA, float* colsB,
+    int32_t* idxB, int64_t n, int leaf, int W, int max_depth,
     size_t per_wave, float* __restrict__ pts, NodeRec* __restrict__ tnodes,
     float* __restrict__ tbox, int32_t* __restrict__ sub_nodes, int32_t* __restrict__ err,
     int32_t* __restrict__ depth_seen)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int D2 = 2 * D;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int sub = blockIdx.x * kWavesPerBlock + w;
     if (sub >= n_sub) return;  // only wavefront-level synchronization below
     const SubEntry e = subs[sub];
@@ -1301,37 +1477,68 @@ __global__ __launch_bounds__(kBlock) void k_finish(
     uint16_t* pb = pa + W;                                           // [W]
     int4* stack = reinterpret_cast<int4*>(pb + W);                   // [kStack]
 
-#pragma unroll
-    for (int dd = 0; dd < D; ++dd)
-        for (int j = lane; j < c; j += kWave) X[dd * W + j] = cols[(int64_t)dd * n + gs + j];
-    for (int j = lane; j < c; j += kWave) pa[j] = (uint16_t)j;
     if (lane == 0) {
-        stack[0] = make_int4(0, 0, c, 0);
+        stack[0] = make_int4(0, 0, c, (e.buf << 16) | kInHbm);
         trec[0].parent = -1;
     }
     wave_sync();
-    int sp = 1, nloc = 1, maxdep = 0;
+    int sp = 1, nloc = 1, maxdep = 0, errc = KNN_EDEPTH;
     bool bad = false;
+    int64_t lbase = gs;          // HBM position of the points now in LDS
+    const int32_t* lidx = gidx;  // and their index buffer
     while (sp > 0) {
         const int4 top = stack[--sp];
-        const int id = top.x, ls = top.y, lc = top.z;
-        const int dep = top.w & 0xffff, buf = top.w >> 16;
+        const int id = __builtin_amdgcn_readfirstlane(top.x);
+        const int lc = __builtin_amdgcn_readfirstlane(top.z);
+        const int tw = __builtin_amdgcn_readfirstlane(top.w);
+        int ls = __builtin_amdgcn_readfirstlane(top.y), buf = (tw >> 16) & 1;
+        const int dep = tw & 0xffff;
         if (dep > maxdep) maxdep = dep;
-        const int R = (lc + kWave - 1) / kWave;
-        FinishCtx ctx{X, pa, pb, stack, W, leaf, max_depth, e.depth0, gs, trec, tb, pts, gidx, lane};
         int pushed;
+        if (tw & kInHbm) {
+            const float* scol = buf ? colsB : colsA;
+            const int32_t* sidx = buf ? idxB : idxA;
+            if (lc > W) {  // larger than the LDS tile: one split in registers
+                if (lc > kWave * kGlobalRows) {
+                    bad = true;
+                    errc = KNN_EDEVICE;
+                    break;
+                }
+                FinishCtx hctx{X, pa, pb, stack, W, leaf, max_depth, e.depth0, gs, trec, tb, pts,
+                               sidx, lane};
+                pushed = finish_global<D>(hctx, scol, sidx, buf ? colsA : colsB,
+                                          buf ? idxA : idxB, n, id, ls, lc, dep, buf, sp, nloc,
+                                          bad);
+                if (bad) break;
+                sp += pushed;
+                continue;
+            }
+            // the node fits the tile: load it, then split it (and its
+            // descendants, all above it on the stack) in LDS
+            wave_sync();
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd)
+                for (int j = lane; j < lc; j += kWave)
+                    X[dd * W + j] = scol[(int64_t)dd * n + gs + ls + j];
+            for (int j = lane; j < lc; j += kWave) pa[j] = (uint16_t)j;
+            wave_sync();
+            lbase = gs + ls;
+            lidx = sidx;
+            ls = 0;
+            buf = 0;
+        }
+        const int R = (lc + kWave - 1) / kWave;
+        FinishCtx ctx{X, pa, pb, stack, W, leaf, max_depth, e.depth0, lbase, trec, tb, pts, lidx, lane};
         if (R <= 1) pushed = finish_node<D, 1>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
         else if (R <= 2) pushed = finish_node<D, 2>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
         else if (R <= 4 || kFinishMaxR<D> == 4)
             pushed = finish_node<D, 4>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
-        else if (R <= 8 || kFinishMaxR<D> == 8)
-            pushed = finish_node<D, 8>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
-        else pushed = finish_node<D, kFinishMaxR<D>>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
+        else pushed = finish_node<D, 8>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
         if (bad) break;
         sp += pushed;
     }
     if (bad) {
-        if (lane == 0) atomicExch(err, KNN_EDEPTH);
+        if (lane == 0) atomicExch(err, errc);
         return;
     }
     if (lane == 0) {
@@ -1351,7 +1558,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const SubEntry* __restrict__
                                                     NodeRec* __restrict__ nodes,
                                                     float* __restrict__ bbox)
 {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int sub = blockIdx.x * kWavesPerBlock + w;
     if (sub >= n_sub) return;
     const SubEntry e = subs[sub];
@@ -1611,8 +1818,8 @@ struct LevelMem {
     }
 };
 
-using FinishFn = void (*)(const SubEntry*, int32_t, const float*, const int32_t*, const float*,
-                          const int32_t*, int64_t, int, int, int, size_t, float*, NodeRec*,
+using FinishFn = void (*)(const SubEntry*, int32_t, float*, int32_t*, float*, int32_t*,
+                          int64_t, int, int, int, size_t, float*, NodeRec*,
                           float*, int32_t*, int32_t*, int32_t*);
 
 FinishFn finish_for(int d)
@@ -1635,7 +1842,14 @@ inline unsigned blocks_for(int64_t items, int per) { return (unsigned)((items + 
 
 }  // namespace
 
-int32_t finish_max_points(int32_t d) { return d <= 8 ? 512 : 256; }
+int32_t finish_max_points(int32_t) { return kWave * kGlobalRows; }
+
+// Points of the LDS tile of a finish wavefront for subtrees of at most W
+// points: the subtree nodes above it are split in registers from HBM.
+int32_t finish_tile_points(int32_t d, int32_t w)
+{
+    return std::min(w, kWave * finish_rows(d));
+}
 
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w)
 {
@@ -1644,13 +1858,7 @@ size_t finish_lds_bytes_per_wave(int32_t d, int32_t w)
     return (b + 15) & ~(size_t)15;
 }
 
-int32_t default_subtree_points(int32_t d)
-{
-    // two blocks of four wavefronts per CU: at most 80 KiB of LDS per block
-    int32_t w = kSampleMax;
-    while (w > 64 && finish_lds_bytes_per_wave(d, w) * kWavesPerBlock > 80 * 1024) w >>= 1;
-    return w;
-}
+int32_t default_subtree_points(int32_t d) { return finish_max_points(d); }
 
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
                int32_t W, int64_t split_block_nodes, const int64_t* offsets, int32_t T,
@@ -1668,10 +1876,13 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     }
     const int64_t nd = n * d;
     DevBuf colsA(st), colsB(st), idxA(st), idxB(st), pts, gbuf(st);
-    KNN_HIP(colsA.alloc(sizeof(float) * nd));
-    KNN_HIP(colsB.alloc(sizeof(float) * nd));
-    KNN_HIP(idxA.alloc(sizeof(int32_t) * n));
-    KNN_HIP(idxB.alloc(sizeof(int32_t) * n));
+    // padded by one finish tile of rows: the finish reads whole rows of 64
+    // points, up to 64 * kGlobalRows - 1 elements past a node's last point
+    const int64_t tail = (int64_t)kWave * kGlobalRows;
+    KNN_HIP(colsA.alloc(sizeof(float) * (nd + tail)));
+    KNN_HIP(colsB.alloc(sizeof(float) * (nd + tail)));
+    KNN_HIP(idxA.alloc(sizeof(int32_t) * (n + tail)));
+    KNN_HIP(idxB.alloc(sizeof(int32_t) * (n + tail)));
     KNN_HIP(pts.alloc(sizeof(float) * (n + kRowPad) * (d + 1)));
     KNN_HIP(hipMemsetAsync(pts.as<float>() + n * (d + 1), 0, sizeof(float) * kRowPad * (d + 1), st));
     KNN_HIP(gbuf.alloc(sizeof(int32_t) * G_COUNT));
@@ -1870,7 +2081,8 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     KNN_HIP(subn.alloc(sizeof(int32_t) * n_sub));
     KNN_HIP(flags.alloc(sizeof(int32_t) * 2));
     KNN_HIP(hipMemsetAsync(flags.p, 0, sizeof(int32_t) * 2, st));
-    const size_t per_wave = finish_lds_bytes_per_wave(d, W);
+    const int32_t Wt = finish_tile_points(d, W);
+    const size_t per_wave = finish_lds_bytes_per_wave(d, Wt);
     const size_t lds = per_wave * kWavesPerBlock;
     const int32_t fblocks = (n_sub + kWavesPerBlock - 1) / kWavesPerBlock;
     FinishFn ff = finish_for(d);
@@ -1880,7 +2092,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(ff, dim3(fblocks), dim3(kBlock), lds, st, d_subs.as<SubEntry>(), n_sub,
                        colsA.as<float>(), idxA.as<int32_t>(), colsB.as<float>(),
-                       idxB.as<int32_t>(), n, leaf, W, max_depth, per_wave, pts.as<float>(),
+                       idxB.as<int32_t>(), n, leaf, Wt, max_depth, per_wave, pts.as<float>(),
                        tnodes.as<NodeRec>(), tbox.as<float>(), subn.as<int32_t>(),
                        flags.as<int32_t>(), flags.as<int32_t>() + 1);
     KNN_HIP(hipGetLastError());

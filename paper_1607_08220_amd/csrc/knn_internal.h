@@ -115,6 +115,7 @@ void prof_part_points(double points);   // points moved by the build's partition
 // Largest subtree (points) one wavefront finishes in LDS for dimension d.
 int32_t default_subtree_points(int32_t d);
 int32_t finish_max_points(int32_t d);
+int32_t finish_tile_points(int32_t d, int32_t w);
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w);
 
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,

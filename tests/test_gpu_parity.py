@@ -159,6 +159,27 @@ def test_heavy_duplicates_and_identical_big_nodes(knn):
     _full_check(knn, Y, Y[:50], 4, 2, what="constant sample", subtree_points=64)
 
 
+def test_subtree_nodes_above_the_lds_tile(knn):
+    """Subtree nodes larger than the finish's LDS tile are split straight from
+    HBM: two such levels at 16 dimensions (tile 256 of 1024 points), buckets
+    larger than the tile (leaf 600), and children still above the tile after
+    an HBM split because of duplicates."""
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((12_000, 16)).astype(np.float32)
+    ids = rng.choice(len(X), 600, replace=False).astype(np.int32)
+    _full_check(knn, X, X[ids], 6, 8, self_ids=ids, what="d=16 two HBM levels")
+    X = (np.floor(rng.random((30_000, 3)) * 40) / 40).astype(np.float32)
+    ids = rng.choice(len(X), 800, replace=False).astype(np.int32)
+    _full_check(knn, X, X[ids], 7, 600, self_ids=ids, what="leaf 600, grid duplicates")
+    x = np.concatenate([np.full(700, 0.25), np.full(200, 0.75), rng.random(100)])
+    X = np.stack([x, np.zeros(1000)], 1).astype(np.float32)
+    X = np.tile(X, (20, 1))
+    X[:, 1] = np.repeat(np.arange(20), 1000).astype(np.float32) * 10.0
+    X = X[rng.permutation(len(X))]
+    _full_check(knn, X, X[::13], 5, 16, self_ids=np.arange(0, len(X), 13),
+                what="duplicate children above the tile", subtree_points=1024)
+
+
 def test_split_outside_sample_window(knn):
     """The level histogram resolves only the sample ranks around the middle;
     these inputs put the point closest to half outside that window (the
