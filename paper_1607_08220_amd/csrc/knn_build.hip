@@ -1059,21 +1059,22 @@ constexpr int kFinishMaxR = finish_rows(D);
 // 64 * kGlobalRows points are handed to the finish, and their nodes above the
 // LDS tile are split in registers, one level per pass over the node.
 constexpr int kGlobalRows = 16;
+// Rows of 64 points in the largest LDS tile (any dimension).
+constexpr int kTileRows = 8;
 // Stack entry flag of a node whose points are in a HBM buffer, not in LDS.
 constexpr int kInHbm = 1 << 17;
 
 // Context of one wavefront's subtree build.
 struct FinishCtx {
-    float* X;
-    uint16_t* pa;
-    uint16_t* pb;
+    float* X;      // LDS tile: coordinates [D][W]
+    int32_t* I;    // LDS tile: input indices [W]
+    uint16_t* pm;  // LDS tile: permutation [W], partitioned in place
     int4* stack;
     int W, leaf, max_depth, depth0;
-    int64_t gs;
+    int64_t gs;    // HBM position of tile element 0
     NodeRec* trec;
     float* tb;
     float* pts;
-    const int32_t* gidx;
     int lane;
 };
 
@@ -1081,28 +1082,26 @@ struct FinishCtx {
 // its box, its split (or bucket rows), the stable partition, and the pushes
 // of its children.  Returns the number of stack entries written.
 template <int D, int RM>
-__device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep, int buf,
-                           int sp, int& nloc, bool& bad)
+__device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep, int sp,
+                           int& nloc, bool& bad)
 {
     constexpr int D2 = 2 * D;
     float* X = cx.X;
-    uint16_t* pa = cx.pa;
-    uint16_t* pb = cx.pb;
+    uint16_t* pm = cx.pm;
     int4* stack = cx.stack;
     const int W = cx.W, leaf = cx.leaf, max_depth = cx.max_depth, lane = cx.lane;
     const int64_t gs = cx.gs;
     NodeRec* trec = cx.trec;
     float* tb = cx.tb;
     float* pts = cx.pts;
-    const int32_t* gidx = cx.gidx;
     const int R = (lc + kWave - 1) / kWave;
-    const uint16_t* pin = buf ? pb : pa;
-    uint16_t* pout = buf ? pa : pb;
+    // the node's whole permutation slice is read into registers before the
+    // partition writes it back in place
     int p[RM];
 #pragma unroll
     for (int r = 0; r < RM; ++r) {  // unconditional LDS loads, clamped in range
         const int j = lane + kWave * r;
-        const int q = pin[ls + (j < lc ? j : lc - 1)];
+        const int q = pm[ls + (j < lc ? j : lc - 1)];
         p[r] = (r < R && j < lc) ? q : 0;
     }
     const bool small = lc <= leaf;
@@ -1181,11 +1180,11 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
             trec[id].dim = -lc;
         }
         for (int j = lane; j < lc; j += kWave) {
-            const int q = pin[ls + j];
+            const int q = pm[ls + j];
             const int64_t row = (gs + ls + j) * (D + 1);
 #pragma unroll
             for (int dd = 0; dd < D; ++dd) pts[row + dd] = X[dd * W + q];
-            pts[row + D] = __int_as_float(gidx[gs + q]);
+            pts[row + D] = __int_as_float(cx.I[q]);
         }
         return 0;
     }
@@ -1220,7 +1219,7 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
             if (ok) {
                 const int dst = f ? ls + run_l + (int)lanes_below(bl)
                                   : ls + nl + run_r + (int)lanes_below(bv & ~bl);
-                pout[dst] = (uint16_t)p[r];
+                pm[dst] = (uint16_t)p[r];
             }
             run_l += __popcll(bl);
             run_r += __popcll(bv & ~bl);
@@ -1236,7 +1235,7 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
         trec[L].parent = id;
         trec[Rc].parent = id;
         if (!bad) {
-            const int wd = (dep + 1) | ((buf ^ 1) << 16);
+            const int wd = dep + 1;
             const int4 lft = make_int4(L, ls, nl, wd);
             const int4 rgt = make_int4(Rc, ls + nl, lc - nl, wd);
             if (nl <= lc - nl) {  // smaller child next keeps the stack shallow
@@ -1277,21 +1276,27 @@ __device__ int finish_global(const FinishCtx& cx, const float* __restrict__ scol
     double bestV = -1.0;
     int best = 0;
     float blo = 0.0f, bhi = 0.0f;
-    // one dimension per pass, not unrolled: the registers of this path are
-    // counted against the whole kernel's occupancy
+    // one dimension per pass, not unrolled (the registers of this path count
+    // against the whole kernel's occupancy), with the next dimension's rows
+    // in flight meanwhile; whole rows are read (the buffers have a tail)
+    float vn[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) vn[r] = r < R ? scol[s0 + lane + kWave * r] : 0.0f;
 #pragma unroll 1
     for (int dd = 0; dd < D; ++dd) {
-        const float* col = scol + (int64_t)dd * n + s0;
         float v[RG];
         float lo[1] = {INFINITY}, hi[1] = {-INFINITY};
 #pragma unroll
-        for (int r = 0; r < RG; ++r) {  // whole rows: the buffers have a tail
-            const int j = lane + kWave * r;
-            const float x = r < R ? col[j] : 0.0f;
-            const bool ok = j < lc;
-            v[r] = ok ? x : 0.0f;
-            lo[0] = fminf(lo[0], ok ? x : INFINITY);
-            hi[0] = fmaxf(hi[0], ok ? x : -INFINITY);
+        for (int r = 0; r < RG; ++r) {
+            const bool ok = lane + kWave * r < lc;
+            v[r] = ok ? vn[r] : 0.0f;
+            lo[0] = fminf(lo[0], ok ? vn[r] : INFINITY);
+            hi[0] = fmaxf(hi[0], ok ? vn[r] : -INFINITY);
+        }
+        if (dd + 1 < D) {
+            const float* col = scol + (int64_t)(dd + 1) * n + s0;
+#pragma unroll
+            for (int r = 0; r < RG; ++r) vn[r] = r < R ? col[lane + kWave * r] : 0.0f;
         }
         wave_minmax<1>(lo, hi);
         if (lane == 0) {
@@ -1363,17 +1368,33 @@ __device__ int finish_global(const FinishCtx& cx, const float* __restrict__ scol
             run_r += __popcll(bv & ~bl);
         }
     }
+    // the D coordinate arrays and the index array, PA at a time (two fit the
+    // registers of the low dimensions only)
+    constexpr int PA = D <= 3 ? 2 : 1;
 #pragma unroll 1
-    for (int dd = 0; dd <= D; ++dd) {
-        const float* src = dd < D ? scol + (int64_t)dd * n + s0
-                                  : reinterpret_cast<const float*>(sidx + s0);
-        float* out = dd < D ? dcol + (int64_t)dd * n + s0 : reinterpret_cast<float*>(didx + s0);
-        float t[RG];
+    for (int d0 = 0; d0 <= D; d0 += PA) {
+        float t[PA][RG];
 #pragma unroll
-        for (int r = 0; r < RG; ++r) t[r] = r < R ? src[lane + kWave * r] : 0.0f;
+        for (int i = 0; i < PA; ++i) {
+            const int dd = d0 + i;
+            if (dd <= D) {
+                const float* src = dd < D ? scol + (int64_t)dd * n + s0
+                                          : reinterpret_cast<const float*>(sidx + s0);
 #pragma unroll
-        for (int r = 0; r < RG; ++r)
-            if (r < R && lane + kWave * r < lc) out[dst[r]] = t[r];
+                for (int r = 0; r < RG; ++r) t[i][r] = r < R ? src[lane + kWave * r] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int dd = d0 + i;
+            if (dd <= D) {
+                float* out = dd < D ? dcol + (int64_t)dd * n + s0
+                                    : reinterpret_cast<float*>(didx + s0);
+#pragma unroll
+                for (int r = 0; r < RG; ++r)
+                    if (r < R && lane + kWave * r < lc) out[dst[r]] = t[i][r];
+            }
+        }
     }
     const int L = nloc, Rc = nloc + 1;
     nloc += 2;
@@ -1472,10 +1493,10 @@ __global__ __launch_bounds__(kBlock) void k_finish(
     }
 
     unsigned char* region = smem + (size_t)w * per_wave;
-    float* X = reinterpret_cast<float*>(region);                    // [D][W]
-    uint16_t* pa = reinterpret_cast<uint16_t*>(X + (size_t)D * W);  // [W]
-    uint16_t* pb = pa + W;                                           // [W]
-    int4* stack = reinterpret_cast<int4*>(pb + W);                   // [kStack]
+    float* X = reinterpret_cast<float*>(region);                  // [D][W]
+    int32_t* I = reinterpret_cast<int32_t*>(X + (size_t)D * W);   // [W]
+    uint16_t* pm = reinterpret_cast<uint16_t*>(I + W);            // [W]
+    int4* stack = reinterpret_cast<int4*>(pm + W);                // [kStack]
 
     if (lane == 0) {
         stack[0] = make_int4(0, 0, c, (e.buf << 16) | kInHbm);
@@ -1484,14 +1505,14 @@ __global__ __launch_bounds__(kBlock) void k_finish(
     wave_sync();
     int sp = 1, nloc = 1, maxdep = 0, errc = KNN_EDEPTH;
     bool bad = false;
-    int64_t lbase = gs;          // HBM position of the points now in LDS
-    const int32_t* lidx = gidx;  // and their index buffer
+    int64_t lbase = gs;  // HBM position of the points now in LDS
     while (sp > 0) {
         const int4 top = stack[--sp];
         const int id = __builtin_amdgcn_readfirstlane(top.x);
         const int lc = __builtin_amdgcn_readfirstlane(top.z);
         const int tw = __builtin_amdgcn_readfirstlane(top.w);
-        int ls = __builtin_amdgcn_readfirstlane(top.y), buf = (tw >> 16) & 1;
+        int ls = __builtin_amdgcn_readfirstlane(top.y);
+        const int buf = (tw >> 16) & 1;
         const int dep = tw & 0xffff;
         if (dep > maxdep) maxdep = dep;
         int pushed;
@@ -1504,8 +1525,8 @@ __global__ __launch_bounds__(kBlock) void k_finish(
                     errc = KNN_EDEVICE;
                     break;
                 }
-                FinishCtx hctx{X, pa, pb, stack, W, leaf, max_depth, e.depth0, gs, trec, tb, pts,
-                               sidx, lane};
+                FinishCtx hctx{X, I, pm, stack, W, leaf, max_depth, e.depth0, gs, trec, tb, pts,
+                               lane};
                 pushed = finish_global<D>(hctx, scol, sidx, buf ? colsA : colsB,
                                           buf ? idxA : idxB, n, id, ls, lc, dep, buf, sp, nloc,
                                           bad);
@@ -1513,27 +1534,38 @@ __global__ __launch_bounds__(kBlock) void k_finish(
                 sp += pushed;
                 continue;
             }
-            // the node fits the tile: load it, then split it (and its
-            // descendants, all above it on the stack) in LDS
+            // the node fits the tile: load it (whole rows, every load of an
+            // array in flight at once; the buffers have a tail), then split
+            // it and its descendants, all above it on the stack, in LDS
             wave_sync();
+            const int R = (lc + kWave - 1) / kWave;
+            const int64_t s0 = gs + ls;
 #pragma unroll
-            for (int dd = 0; dd < D; ++dd)
-                for (int j = lane; j < lc; j += kWave)
-                    X[dd * W + j] = scol[(int64_t)dd * n + gs + ls + j];
-            for (int j = lane; j < lc; j += kWave) pa[j] = (uint16_t)j;
+            for (int dd = 0; dd <= D; ++dd) {
+                const float* src = dd < D ? scol + (int64_t)dd * n + s0
+                                          : reinterpret_cast<const float*>(sidx + s0);
+                float* dst = dd < D ? X + dd * W : reinterpret_cast<float*>(I);
+                float t[kTileRows];
+#pragma unroll
+                for (int r = 0; r < kTileRows; ++r) t[r] = r < R ? src[lane + kWave * r] : 0.0f;
+#pragma unroll
+                for (int r = 0; r < kTileRows; ++r)
+                    if (r < R) dst[lane + kWave * r] = t[r];
+            }
+#pragma unroll
+            for (int r = 0; r < kTileRows; ++r)
+                if (r < R) pm[lane + kWave * r] = (uint16_t)(lane + kWave * r);
             wave_sync();
-            lbase = gs + ls;
-            lidx = sidx;
+            lbase = s0;
             ls = 0;
-            buf = 0;
         }
         const int R = (lc + kWave - 1) / kWave;
-        FinishCtx ctx{X, pa, pb, stack, W, leaf, max_depth, e.depth0, lbase, trec, tb, pts, lidx, lane};
-        if (R <= 1) pushed = finish_node<D, 1>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
-        else if (R <= 2) pushed = finish_node<D, 2>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
+        FinishCtx ctx{X, I, pm, stack, W, leaf, max_depth, e.depth0, lbase, trec, tb, pts, lane};
+        if (R <= 1) pushed = finish_node<D, 1>(ctx, id, ls, lc, dep, sp, nloc, bad);
+        else if (R <= 2) pushed = finish_node<D, 2>(ctx, id, ls, lc, dep, sp, nloc, bad);
         else if (R <= 4 || kFinishMaxR<D> == 4)
-            pushed = finish_node<D, 4>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
-        else pushed = finish_node<D, 8>(ctx, id, ls, lc, dep, buf, sp, nloc, bad);
+            pushed = finish_node<D, 4>(ctx, id, ls, lc, dep, sp, nloc, bad);
+        else pushed = finish_node<D, 8>(ctx, id, ls, lc, dep, sp, nloc, bad);
         if (bad) break;
         sp += pushed;
     }
@@ -1853,8 +1885,8 @@ int32_t finish_tile_points(int32_t d, int32_t w)
 
 size_t finish_lds_bytes_per_wave(int32_t d, int32_t w)
 {
-    // X [d][W] floats, two permutation arrays [W] u16, stack
-    size_t b = (size_t)4 * d * w + (size_t)4 * w + sizeof(int4) * kStack;
+    // X [d][W] floats, indices [W] int32, permutation [W] u16, stack
+    size_t b = (size_t)4 * d * w + (size_t)4 * w + (size_t)2 * w + sizeof(int4) * kStack;
     return (b + 15) & ~(size_t)15;
 }
 
