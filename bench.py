@@ -364,6 +364,8 @@ def main() -> int:
     trees = []
 
     def step():
+        if trees:  # the previous step's tree; its memory returns to the allocator's pool
+            trees.pop().free()
         tree = knn.knn_build(P, w.leaf)
         pb = knn.knn_get_profile()
         knn.knn_query_ex(tree, Q, k, self_ids=S, out=(idx, d2))

@@ -250,9 +250,12 @@ int knn_tree_free(knn_tree* t)
     int rc = KNN_OK;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
-    if (t->pts) (void)hipFree(t->pts);
-    if (t->nodes) (void)hipFree(t->nodes);
-    if (t->bbox) (void)hipFree(t->bbox);
+    // stream-ordered pool allocations of the build; the device is idle here
+    if (t->pts) (void)hipFreeAsync(t->pts, nullptr);
+    if (t->nodes) (void)hipFreeAsync(t->nodes, nullptr);
+    if (t->bbox) (void)hipFreeAsync(t->bbox, nullptr);
+    e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess && rc == KNN_OK) rc = hip_fail(e, "hipStreamSynchronize");
     delete t;
     return rc;
 }

@@ -1907,7 +1907,10 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         }
     }
     const int64_t nd = n * d;
-    DevBuf colsA(st), colsB(st), idxA(st), idxB(st), pts, gbuf(st);
+    // the tree's own buffers (pts, nodes, bbox) come from the stream-ordered
+    // pool too: a build that follows a freed tree reuses its memory instead of
+    // mapping fresh pages while the device waits
+    DevBuf colsA(st), colsB(st), idxA(st), idxB(st), pts(st), gbuf(st);
     // padded by one finish tile of rows: the finish reads whole rows of 64
     // points, up to 64 * kGlobalRows - 1 elements past a node's last point
     const int64_t tail = (int64_t)kWave * kGlobalRows;
@@ -2144,7 +2147,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         h_base[i] = (int32_t)total;
         total += h_subn[i] - 1;
     }
-    DevBuf nodes, bbox, d_base(st);
+    DevBuf nodes(st), bbox(st), d_base(st);
     KNN_HIP(nodes.alloc(sizeof(NodeRec) * total));
     KNN_HIP(bbox.alloc(sizeof(float) * total * 2 * d));
     KNN_HIP(d_base.alloc(sizeof(int32_t) * n_sub));
