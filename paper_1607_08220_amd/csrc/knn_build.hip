@@ -711,9 +711,15 @@ __global__ __launch_bounds__(kBlock) void k_count(Level L, const int32_t* __rest
     } else {
         const float split = splitv[node];
         const float* col = cols + (int64_t)dim * n + start;
-        for (int64_t e0 = wb; e0 < we; e0 += kWave) {
-            int64_t e = e0 + lane;
-            bool f = e < we && col[e] < split;
+        float x[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {  // every load in flight at once, clamped in range
+            const int64_t e = wb + (int64_t)i * kWave + lane;
+            x[i] = col[e < we ? e : we - 1];
+        }
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const bool f = wb + (int64_t)i * kWave + lane < we && x[i] < split;
             cnt += (uint32_t)__popcll(__ballot(f));
         }
     }
@@ -803,11 +809,17 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
     // flags in element order e = 256 r + t; per (r, wave) ballot counts
     uint64_t lmask[kR];
     const float* key = src_cols + (int64_t)(dim >= 0 ? dim : 0) * n + src0;
+    float kv[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {  // every key load in flight at once, clamped in range
+        const int e = kBlock * r + t;
+        kv[r] = key[e < len ? e : len - 1];
+    }
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int e = kBlock * r + t;
         const bool ok = e < len;
-        const bool f = ok && (dim < 0 || key[e] < split);
+        const bool f = ok && (dim < 0 || kv[r] < split);
         lmask[r] = __ballot(f);
         if (lane == 0) cnt[r][w] = (uint32_t)__popcll(lmask[r]);
     }
