@@ -1095,7 +1095,7 @@ struct FinishCtx {
 // of its children.  Returns the number of stack entries written.
 template <int D, int RM>
 __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep, int sp,
-                           int& nloc, bool& bad)
+                           int& nloc, int& maxdep, bool& bad)
 {
     constexpr int D2 = 2 * D;
     float* X = cx.X;
@@ -1220,8 +1220,9 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
     float split;
     int nl;
     median_split<RM>(key, R, lc, lane, float_key(blo), float_key(bhi), split, nl);
-    // stable partition into the other permutation array
+    // stable partition, in place
     int run_l = 0, run_r = 0;
+    int pos0 = 0;  // new position of this lane's point of row 0
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
         if (r < R) {
@@ -1232,6 +1233,7 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
                 const int dst = f ? ls + run_l + (int)lanes_below(bl)
                                   : ls + nl + run_r + (int)lanes_below(bv & ~bl);
                 pm[dst] = (uint16_t)p[r];
+                if (r == 0) pos0 = dst;
             }
             run_l += __popcll(bl);
             run_r += __popcll(bv & ~bl);
@@ -1239,6 +1241,58 @@ __device__ int finish_node(const FinishCtx& cx, int id, int ls, int lc, int dep,
     }
     const int L = nloc, Rc = nloc + 1;
     nloc += 2;
+    if constexpr (RM == 1 && D <= 4) {  // (the 4D box values fit the registers)
+        if (nl <= leaf && lc - nl <= leaf) {
+            // both children are buckets: close them here, one point per lane
+            // (each lane's point goes to row pos0 of the packed order), with
+            // the two boxes reduced together
+            if (cx.depth0 + dep + 1 > max_depth) bad = true;
+            if (dep + 1 > maxdep) maxdep = dep + 1;
+            const bool ok = lane < lc;
+            const bool f = ok && v[0] < split;
+            float x[D], lo[2 * D], hi[2 * D];
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) {
+                x[dd] = X[dd * W + p[0]];
+                lo[dd] = ok && f ? x[dd] : INFINITY;
+                hi[dd] = ok && f ? x[dd] : -INFINITY;
+                lo[D + dd] = ok && !f ? x[dd] : INFINITY;
+                hi[D + dd] = ok && !f ? x[dd] : -INFINITY;
+            }
+            wave_minmax<2 * D>(lo, hi);
+            if (ok) {
+                const int64_t row = (gs + pos0) * (D + 1);
+#pragma unroll
+                for (int dd = 0; dd < D; ++dd) pts[row + dd] = x[dd];
+                pts[row + D] = __int_as_float(cx.I[p[0]]);
+            }
+            if (lane == 0) {
+                trec[id].a = L;
+                trec[id].split = split;
+                trec[id].dim = best;
+                NodeRec cl, cr;
+                cl.a = (int32_t)(gs + ls);
+                cl.parent = id;
+                cl.split = 0.0f;
+                cl.dim = -nl;
+                cr.a = (int32_t)(gs + ls + nl);
+                cr.parent = id;
+                cr.split = 0.0f;
+                cr.dim = -(lc - nl);
+                trec[L] = cl;
+                trec[Rc] = cr;
+#pragma unroll
+                for (int dd = 0; dd < D; ++dd) {
+                    tb[(int64_t)L * D2 + dd] = lo[dd];
+                    tb[(int64_t)L * D2 + D + dd] = hi[dd];
+                    tb[(int64_t)Rc * D2 + dd] = lo[D + dd];
+                    tb[(int64_t)Rc * D2 + D + dd] = hi[D + dd];
+                }
+            }
+            wave_sync();
+            return 0;
+        }
+    }
     if (cx.depth0 + dep + 1 > max_depth || sp + 2 > kStack) bad = true;
     if (lane == 0) {
         trec[id].a = L;
@@ -1573,11 +1627,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(
         }
         const int R = (lc + kWave - 1) / kWave;
         FinishCtx ctx{X, I, pm, stack, W, leaf, max_depth, e.depth0, lbase, trec, tb, pts, lane};
-        if (R <= 1) pushed = finish_node<D, 1>(ctx, id, ls, lc, dep, sp, nloc, bad);
-        else if (R <= 2) pushed = finish_node<D, 2>(ctx, id, ls, lc, dep, sp, nloc, bad);
+        if (R <= 1) pushed = finish_node<D, 1>(ctx, id, ls, lc, dep, sp, nloc, maxdep, bad);
+        else if (R <= 2) pushed = finish_node<D, 2>(ctx, id, ls, lc, dep, sp, nloc, maxdep, bad);
         else if (R <= 4 || kFinishMaxR<D> == 4)
-            pushed = finish_node<D, 4>(ctx, id, ls, lc, dep, sp, nloc, bad);
-        else pushed = finish_node<D, 8>(ctx, id, ls, lc, dep, sp, nloc, bad);
+            pushed = finish_node<D, 4>(ctx, id, ls, lc, dep, sp, nloc, maxdep, bad);
+        else pushed = finish_node<D, 8>(ctx, id, ls, lc, dep, sp, nloc, maxdep, bad);
         if (bad) break;
         sp += pushed;
     }
