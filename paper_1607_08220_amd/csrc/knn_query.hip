@@ -268,6 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
                 }
                 const float thr = key_dist(h[KC - 1]);
                 int next, nfrom;
+                bool up = false;  // leaving upwards: stop if the ball lies inside the box
                 if (from < 0) {
                     if constexpr (STATS) ++n_enter;
                     const float b = box_bound<D>(q, bb);
@@ -277,8 +278,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
                     } else if (r.dim < 0) {  // leaf: scan it, then return to the parent
                         lstart = r.a;
                         lcnt = -r.dim;
-                        next = ball_inside<D>(q, bb, thr) ? -1 : r.parent;
+                        next = r.parent;
                         nfrom = cur;
+                        up = true;
                     } else {
                         const float qd = select_dim<D>(q, r.dim);
                         next = qd < r.split ? r.a : r.a + 1;  // near child first
@@ -293,10 +295,12 @@ __global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
                         next = left_near ? r.a + 1 : r.a;
                         nfrom = -1;
                     } else {
-                        next = ball_inside<D>(q, bb, thr) ? -1 : r.parent;
+                        next = r.parent;
                         nfrom = cur;
+                        up = true;
                     }
                 }
+                if (up && ball_inside<D>(q, bb, thr)) next = -1;
                 cur = next;
                 from = nfrom;
                 if (cur >= 0) {
