@@ -69,9 +69,13 @@ typedef struct {
                        steps, 4 heap inserts; summed over wavefronts (64 queries):
                        5 traversal-loop iterations, 6 bucket-row batches, 7 leaf
                        rounds, 8 heap-insert executions */
-    int32_t traversal; /* 0 (default): chosen by dimension; 1: stack-free walk from the
+    int32_t traversal; /* 0 (default): form 3 for batches of at most 16,384 queries, else
+                          1 below 5 dimensions and 2 from 5; 1: stack-free walk from the
                           query's home leaf (each node keeps its parent); 2: Algorithm 1's
                           explicit stack, kept in LDS (used when the tree's depth fits);
+                          3: Algorithm 1's explicit stack with one wavefront per query
+                          (used when the tree is at most 63 levels deep and stats is
+                          NULL; for deep searches answered with few queries);
                           a scheduling knob, the result does not depend on it */
     int32_t pad2_;
 } knn_query_params;

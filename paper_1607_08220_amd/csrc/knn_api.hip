@@ -174,7 +174,7 @@ int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     const int32_t batch = p && p->leaf_batch ? p->leaf_batch : kDefaultLeafBatch;
     if (batch < 1 || batch > 64) return fail(KNN_EINVAL, "leaf_batch must be in [0, 64]");
     const int32_t traversal = p ? p->traversal : 0;
-    if (traversal < 0 || traversal > 2) return fail(KNN_EINVAL, "traversal must be 0, 1 or 2");
+    if (traversal < 0 || traversal > 3) return fail(KNN_EINVAL, "traversal must be 0, 1, 2 or 3");
     DeviceGuard g(t->device);
     QuerySpec qs;
     qs.queries = queries;

@@ -35,9 +35,11 @@ namespace knn {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kXcds = 8;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kXcds = 8;                      // accelerator complex dies of an MI355X, each with its own L2
 constexpr size_t kMaxStackLds = 160 * 1024;  // LDS of one workgroup on gfx950
-constexpr int kStackMinDim = 5;               // default: explicit stack from 5 dimensions  // accelerator complex dies of an MI355X, each with its own L2
+constexpr int kStackMinDim = 5;               // default: explicit stack from 5 dimensions
+constexpr int64_t kWaveQueriesMax = 16384;    // default: one wavefront per query up to this batch
 
 // q[dim] as a chain of selects.  The empty asm keeps the compiler from
 // turning the chain back into a dynamically indexed array (which it would
@@ -577,6 +579,118 @@ __global__ __launch_bounds__(kBlock) void k_traverse_stack(TravArgs A, int sdept
     }
 }
 
+// One wavefront per query: Algorithm 1's depth-first search with the
+// explicit stack run by the whole wavefront, for deep searches (high
+// dimensions, large k) where a lane-per-query walk leaves one lane to scan
+// thousands of buckets alone.  The control flow is uniform: the stack of
+// pending far children is held across the lanes (entry i in lane i, at most
+// 64 entries), a bucket's rows are scanned one row per lane, and the heap is
+// a sorted list of 64-bit (distance, index) keys, entry j in lane j < k; the
+// rows of a bucket that beat the k-th key are inserted one after the other.
+// Pruning and the result are those of k_traverse_stack.
+__device__ inline uint64_t readlane_u64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
+{
+    const NodeRec* __restrict__ nodes = A.nodes;
+    const float* __restrict__ bbox = A.bbox;
+    const float* __restrict__ pts = A.pts;
+    const int lane = threadIdx.x & 63;
+    const int64_t slot =
+        (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (slot >= A.m) return;  // the whole wavefront
+    const int64_t qid = A.order ? A.order[slot] : slot;
+    float q[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) q[t] = A.queries[qid * D + t];
+    const int32_t self = A.self_ids ? A.self_ids[qid] : -1;
+    const int k = __builtin_amdgcn_readfirstlane(A.qk ? A.qk[qid] : A.k);
+    const float r2 = A.r2s ? A.r2s[qid] : A.r2;
+    const uint64_t empty = r2 > 0.0f ? make_key(r2, 0) : 0;
+    uint64_t h = empty;  // lane j < k: the (j + 1)-th smallest key so far
+    int s_node = 0;      // pending far child of stack entry `lane`
+    float s_bound = 0.0f;
+    int sp = 0;
+    int cur = __builtin_amdgcn_readfirstlane(A.root ? A.root[qid] : 0);
+    while (true) {
+        uint64_t top = readlane_u64(h, k - 1);
+        const float thr = key_dist(top);
+        if (cur < 0) {  // the next pending far child whose bound does not exceed thr
+            while (sp > 0) {
+                --sp;
+                const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s_bound), sp));
+                if (b <= thr) {
+                    cur = __builtin_amdgcn_readlane(s_node, sp);
+                    break;
+                }
+            }
+            if (cur < 0) break;
+        }
+        const NodeRec r = nodes[cur];
+        float bb[2 * D];
+        load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+        if (box_bound<D>(q, bb) > thr) {  // no point of this node can enter H
+            cur = -1;
+            continue;
+        }
+        if (r.dim >= 0) {
+            const float qd = select_dim<D>(q, r.dim);
+            const bool left_near = qd < r.split;
+            const float o = left_near ? r.split - qd : qd - r.split;
+            if (sp < kWave) {  // always: a path holds at most depth pending entries
+                if (lane == sp) {
+                    s_node = left_near ? r.a + 1 : r.a;
+                    s_bound = o * o;
+                }
+                ++sp;
+            }
+            cur = left_near ? r.a : r.a + 1;  // near child first
+            continue;
+        }
+        const int cnt = -r.dim;
+        for (int j0 = 0; j0 < cnt; j0 += kWave) {
+            const int j = j0 + lane;
+            uint64_t key = ~0ull;
+            bool cand = false;
+            if (j < cnt) {
+                float x[D + 1];
+                load_row<D>(pts + (int64_t)(r.a + j) * (D + 1), x);
+                const int id = __float_as_int(x[D]);
+                key = make_key(distance<D>(q, x), id);
+                cand = key < top && id != self;
+            }
+            uint64_t cm = __ballot(cand);
+            while (cm) {
+                const int src = __builtin_ctzll(cm);
+                cm &= cm - 1;
+                const uint64_t kk = readlane_u64(key, src);
+                if (kk < top) {  // insert into the sorted list, dropping entry k - 1
+                    const uint32_t plo = (uint32_t)__shfl_up((int)(uint32_t)h, 1);
+                    const uint32_t phi = (uint32_t)__shfl_up((int)(uint32_t)(h >> 32), 1);
+                    const uint64_t prev = ((uint64_t)phi << 32) | plo;
+                    if (lane < k && kk < h) h = (lane > 0 && kk < prev) ? prev : kk;
+                    top = readlane_u64(h, k - 1);
+                }
+            }
+        }
+        cur = -1;
+    }
+    if (lane < k) {
+        const int64_t o = (A.qout ? A.qout[qid] : qid * k) + lane;
+        const bool none = h == empty;
+        A.out_idx[o] = none ? -1 : (int)(uint32_t)h;
+        A.out_d2[o] = none ? INFINITY : key_dist(h);
+    }
+}
+
+using WaveFn = void (*)(TravArgs);
+
 // Home leaf of every query: descend with the near-child rule (x < split
 // left).  Queries are grouped by key = (first packed position of the home
 // leaf) >> shift: buckets are contiguous in packed order, so key order is the
@@ -777,6 +891,22 @@ TraverseFn traverse_for(int d, int k, bool stats)
     }
 }
 
+WaveFn wave_for(int d)
+{
+    switch (d) {
+#define KNN_DIM_CASE(DD) \
+    case DD:             \
+        return k_traverse_wave<DD>;
+        KNN_DIM_CASE(1) KNN_DIM_CASE(2) KNN_DIM_CASE(3) KNN_DIM_CASE(4)
+        KNN_DIM_CASE(5) KNN_DIM_CASE(6) KNN_DIM_CASE(7) KNN_DIM_CASE(8)
+        KNN_DIM_CASE(9) KNN_DIM_CASE(10) KNN_DIM_CASE(11) KNN_DIM_CASE(12)
+        KNN_DIM_CASE(13) KNN_DIM_CASE(14) KNN_DIM_CASE(15) KNN_DIM_CASE(16)
+#undef KNN_DIM_CASE
+    default:
+        return nullptr;
+    }
+}
+
 LocateFn locate_for(int d)
 {
     switch (d) {
@@ -929,7 +1059,17 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     const size_t stk_bytes = sizeof(int2) * (size_t)(t->depth + 1) * kBlock;
     const bool use_stack = stk_bytes <= kMaxStackLds &&
                            (qs.traversal == 2 || (qs.traversal == 0 && d >= kStackMinDim));
-    if (use_stack) {
+    // one wavefront per query (the tree's depth bounds the lanes' stack):
+    // asked for, or by default for batches too small to fill the device with
+    // one lane per query
+    const bool wave_ok = t->depth + 1 <= kWave && qs.stats == nullptr;
+    const bool use_wave =
+        wave_ok && (qs.traversal == 3 || (qs.traversal == 0 && m <= kWaveQueriesMax));
+    if (use_wave) {
+        WaveFn wf = wave_for(d);
+        const unsigned wgrid = (unsigned)((m + kWavesPerBlock - 1) / kWavesPerBlock);
+        hipLaunchKernelGGL(wf, dim3(wgrid), dim3(kBlock), 0, st, A);
+    } else if (use_stack) {
         StackFn sf = stack_for(d, qs.k, qs.stats != nullptr);
         if (stk_bytes > 64 * 1024)
             KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(sf),

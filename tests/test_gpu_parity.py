@@ -44,6 +44,11 @@ def _full_check(knn, X, Q, k, leaf, self_ids=None, r2=np.inf, what="", subtree_p
     check_knn_lists(gi, gd)
     gi1, gd1, _ = gpu_knn(X, Q, k, self_ids=self_ids, r2=r2, order=1, tree=tree)
     assert_same(gi1, gd1, oi, od, what + " (input order)")
+    # small batches default to one wavefront per query: the lane-per-query
+    # forms answer the same batch too
+    for trav in (1, 2):
+        gi2, gd2, _ = gpu_knn(X, Q, k, self_ids=self_ids, r2=r2, tree=tree, traversal=trav)
+        assert_same(gi2, gd2, oi, od, what + f" (traversal {trav})")
     tree.free()
 
 
@@ -216,7 +221,7 @@ def test_determinism_and_order_independence(knn):
     import torch
     Q, S = dev(w.queries), dev(w.self_ids)
     for lb in (1, 17, 64):
-        idx, d2 = knn.knn_query_ex(t1, Q, w.k, self_ids=S, leaf_batch=lb)
+        idx, d2 = knn.knn_query_ex(t1, Q, w.k, self_ids=S, leaf_batch=lb, traversal=1)
         torch.cuda.synchronize()
         assert_same(idx.cpu().numpy(), d2.cpu().numpy(), a_i, a_d, f"leaf_batch={lb}")
     with pytest.raises(knn.KnnError):
@@ -284,8 +289,9 @@ def test_fp64_cross_check(knn):
 
 @pytest.mark.parametrize("d", [1, 3, 6, 10, 16])
 def test_both_traversals_match_oracle(knn, d):
-    """The stack-free walk and the explicit-stack form give the oracle's
-    result on the same tree, in both query orders."""
+    """The stack-free walk, the explicit-stack form and the one-wavefront-per-
+    query form give the oracle's result on the same tree, in both query
+    orders."""
     import torch
     n = 60_011
     X = inputs.clustered(n, seed=90, n_clusters=40) if d == 3 else inputs.corr_gauss(n, d, seed=91)
@@ -293,10 +299,38 @@ def test_both_traversals_match_oracle(knn, d):
     log(f"[case] traversals d={d}")
     t = knn.knn_build(dev(X), 32)
     bi, bd = oracle.bf32(X, X[ids], 9, self_ids=ids)
-    for trav in (1, 2):
+    for trav in (1, 2, 3):
         for order in (0, 1):
             gi, gd = knn.knn_query_ex(t, dev(X[ids]), 9, self_ids=dev(ids), traversal=trav,
                                       order=order)
             torch.cuda.synchronize()
             assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"traversal {trav} order {order}")
+    t.free()
+
+
+@pytest.mark.parametrize("d", [2, 10])
+def test_wavefront_per_query_edge_cases(knn, d):
+    """One wavefront per query: k up to 64 (every lane a heap entry), a radius
+    at, below and above zero, a single query, and a bucket of 3,000 identical
+    points (larger than a wavefront's 64 lanes)."""
+    import torch
+    rng = np.random.default_rng(40 + d)
+    n = 20_000
+    X = inputs.corr_gauss(n, d, seed=92 + d)
+    X[:3_000] = X[0]  # 3,000 identical points: an oversized bucket of > 64 rows
+    X = X[rng.permutation(n)]
+    ids = rng.choice(n, 300, replace=False).astype(np.int32)
+    log(f"[case] wavefront per query d={d}")
+    t = knn.knn_build(dev(X), 16)
+    for k in (1, 7, 64):
+        bi, bd = oracle.bf32(X, X[ids], k, self_ids=ids)
+        gi, gd = knn.knn_query_ex(t, dev(X[ids]), k, self_ids=dev(ids), traversal=3)
+        torch.cuda.synchronize()
+        assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"wave k={k}")
+    for r2 in (0.0, -1.0, 0.5):
+        bi, bd = oracle.bf32(X, X[ids[:1]], 5, self_ids=ids[:1], r2=r2)
+        gi, gd = knn.knn_query_ex(t, dev(X[ids[:1]]), 5, self_ids=dev(ids[:1]), r2_max=r2,
+                                  traversal=3)
+        torch.cuda.synchronize()
+        assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"wave r2={r2}")
     t.free()
