@@ -4,8 +4,8 @@ The knobs change speed only, never results: the bucket size (Section III-A1
 reports 32 as the best for its data; other data and hardware may differ),
 the traversal's leaf batch (how many of a wavefront's 64 lanes must hold a
 bucket before it scans), the query order (grouped by home leaf, or as given)
-and the traversal form (stack-free walk from the home leaf, or Algorithm 1's
-explicit stack).  ``tune`` builds the trees for each bucket size, times the
+and the traversal form (stack-free walk from the home leaf, Algorithm 1's
+explicit stack with a lane per query, or with a wavefront per query).  ``tune`` builds the trees for each bucket size, times the
 queries for every leaf batch, order and traversal form, and returns the
 fastest combination.  Every
 timed call goes through the C-ABI (``knn_build_batch``/``knn_query_batch``
@@ -36,7 +36,7 @@ def _time(fn, reps: int) -> float:
 
 def tune(points, queries, k: int, self_ids=None, offsets=None, tree_ids=None,
          leaf_sizes=(16, 32, 64), leaf_batches=(32, 48, 64), orders=(0, 1),
-         traversals=(1, 2), reps: int = 3, build_weight: float = 1.0) -> dict:
+         traversals=(1, 2, 3), reps: int = 3, build_weight: float = 1.0) -> dict:
     """Return {"leaf_size", "leaf_batch", "order", "traversal", "ms", "table"}: the knobs
     minimising build_weight * build time + query time on this sample.
     ``points``/``queries`` are CUDA float32 tensors; for a forest pass the host
