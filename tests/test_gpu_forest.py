@@ -96,7 +96,9 @@ def test_autotune_picks_a_listed_config(knn):
                       leaf_batches=(48, 64), orders=(0, 1), reps=1)
     assert (r["leaf_size"], r["leaf_batch"], r["order"]) in {
         (a["leaf_size"], a["leaf_batch"], a["order"]) for a in r["table"]}
-    assert len(r["table"]) == 16 and r["ms"] == min(a["ms"] for a in r["table"])
+    # 2 leaf sizes x 2 leaf batches x 2 orders x 3 traversal forms
+    assert len(r["table"]) == 24 and r["ms"] == min(a["ms"] for a in r["table"])
+    assert {a["traversal"] for a in r["table"]} == {1, 2, 3}
 
 
 def test_forest_query_graph_replay(knn):
