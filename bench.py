@@ -105,14 +105,17 @@ def bench_forest(knn, torch, dev) -> dict:
     T = torch.from_numpy(f.tree_ids).to(dev)
     S = torch.from_numpy(f.self_ids).to(dev)
     torch.cuda.synchronize()
-    # the autotuner picks bucket size, leaf batch and order on the first 64 trees
+    # the autotuner picks bucket size, leaf batch, order and traversal form on
+    # the first 64 trees; the sample has an eighth of the batch's queries, and
+    # the one-wavefront-per-query form pays off only for small batches, so the
+    # sample chooses among the lane-per-query forms, which scale with the batch
     from paper_1607_08220_amd import autotune
     ns = 64
     sel = torch.from_numpy(np.flatnonzero(f.tree_ids < ns)).to(dev)
     a = time.perf_counter()
     tuned = autotune.tune(P[:int(f.offsets[ns])], Q[sel].contiguous(), f.k,
                           self_ids=S[sel].contiguous(), offsets=f.offsets[:ns + 1],
-                          tree_ids=T[sel].contiguous(), reps=2)
+                          tree_ids=T[sel].contiguous(), traversals=(1, 2), reps=2)
     log(f"forest: autotuned on {ns} trees in {time.perf_counter() - a:.1f} s: leaf "
         f"{tuned['leaf_size']}, leaf batch {tuned['leaf_batch']}, order {tuned['order']}, "
         f"traversal {tuned['traversal']}")
