@@ -38,7 +38,10 @@ def tune(points, queries, k: int, self_ids=None, offsets=None, tree_ids=None,
          leaf_sizes=(16, 32, 64), leaf_batches=(32, 48, 64), orders=(0, 1),
          traversals=(1, 2, 3), reps: int = 3, build_weight: float = 1.0) -> dict:
     """Return {"leaf_size", "leaf_batch", "order", "traversal", "ms", "table"}: the knobs
-    minimising build_weight * build time + query time on this sample.
+    minimising build_weight * build time + query time on this sample.  The
+    best traversal form depends on the batch size (one wavefront per query pays
+    off for small batches), so tune on batches of the size the knobs will
+    serve, or leave form 3 out of ``traversals`` when the sample is smaller.
     ``points``/``queries`` are CUDA float32 tensors; for a forest pass the host
     ``offsets`` and the CUDA int32 ``tree_ids`` of the queries."""
     table = []
