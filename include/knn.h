@@ -57,7 +57,8 @@ typedef struct {
 
 /* Query parameters.  Zero selects the default. */
 typedef struct {
-    int32_t order;  /* 0 (default): process queries grouped by the leaf that contains them;
+    int32_t order;  /* 0 (default): process queries grouped by the leaf that contains them
+                       (the one-wavefront-per-query form always takes input order);
                        1: process queries in input order */
     int32_t leaf_batch; /* 1..64, 0 = default: a wavefront scans buckets once at least
                            leaf_batch of every 64 of its unfinished lanes (one per query)

@@ -1002,7 +1002,14 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     prof_mark(st, 5);
     const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
     const unsigned tgrid = (unsigned)((grid + kXcds - 1) / kXcds * kXcds);  // multiple of 8
-    const bool grouped = qs.order != 1;
+    // one wavefront per query (the tree's depth bounds the lanes' stack):
+    // asked for, or by default for batches too small to fill the device with
+    // one lane per query; it runs in input order (grouping by home leaf costs
+    // more than the coherence it buys a wavefront that walks one query)
+    const bool wave_ok = t->depth + 1 <= kWave && qs.stats == nullptr;
+    const bool use_wave =
+        wave_ok && (qs.traversal == 3 || (qs.traversal == 0 && m <= kWaveQueriesMax));
+    const bool grouped = qs.order != 1 && !use_wave;
     // key range: packed positions >> shift, at most 2^22 buckets
     int shift = 0;
     while ((t->n >> shift) > (int64_t(1) << 22)) ++shift;
@@ -1059,12 +1066,6 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     const size_t stk_bytes = sizeof(int2) * (size_t)(t->depth + 1) * kBlock;
     const bool use_stack = stk_bytes <= kMaxStackLds &&
                            (qs.traversal == 2 || (qs.traversal == 0 && d >= kStackMinDim));
-    // one wavefront per query (the tree's depth bounds the lanes' stack):
-    // asked for, or by default for batches too small to fill the device with
-    // one lane per query
-    const bool wave_ok = t->depth + 1 <= kWave && qs.stats == nullptr;
-    const bool use_wave =
-        wave_ok && (qs.traversal == 3 || (qs.traversal == 0 && m <= kWaveQueriesMax));
     if (use_wave) {
         WaveFn wf = wave_for(d);
         const unsigned wgrid = (unsigned)((m + kWavesPerBlock - 1) / kWavesPerBlock);
