@@ -11,7 +11,9 @@
 // closer point; coming back from the far child it goes up again.  This visits
 // the same nodes as Algorithm 1 with the near child pushed last, with the
 // bounds re-tested against the current r'.  For deep high-dimensional walks
-// k_traverse_stack keeps Algorithm 1's explicit stack instead (in LDS).
+// k_traverse_stack keeps Algorithm 1's explicit stack instead (in LDS), and
+// batches too small to fill the device with one lane per query are answered
+// by k_traverse_wave, one wavefront per query.
 //
 // Queries are first grouped by the leaf that contains them (k_locate +
 // counting sort), and a lane starts at its query's home leaf: the leaf is
