@@ -620,6 +620,11 @@ __global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
     float s_bound = 0.0f;
     int sp = 0;
     int cur = __builtin_amdgcn_readfirstlane(A.root ? A.root[qid] : 0);
+    // record and box of the stack's top entry, loaded while a bucket is
+    // scanned: the node the next pop most likely returns
+    int pf = -1;
+    NodeRec pr{};
+    float pbb[2 * D];
     while (true) {
         uint64_t top = readlane_u64(h, k - 1);
         const float thr = key_dist(top);
@@ -634,9 +639,17 @@ __global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
             }
             if (cur < 0) break;
         }
-        const NodeRec r = nodes[cur];
+        NodeRec r;
         float bb[2 * D];
-        load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+        if (cur == pf) {
+            r = pr;
+#pragma unroll
+            for (int t = 0; t < 2 * D; ++t) bb[t] = pbb[t];
+        } else {
+            r = nodes[cur];
+            load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+        }
+        pf = -1;
         if (box_bound<D>(q, bb) > thr) {  // no point of this node can enter H
             cur = -1;
             continue;
@@ -656,6 +669,11 @@ __global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
             continue;
         }
         const int cnt = -r.dim;
+        if (sp > 0) {
+            pf = __builtin_amdgcn_readlane(s_node, sp - 1);
+            pr = nodes[pf];
+            load_box<D>(bbox + (int64_t)pf * (2 * D), pbb);
+        }
         for (int j0 = 0; j0 < cnt; j0 += kWave) {
             const int j = j0 + lane;
             uint64_t key = ~0ull;
