@@ -91,14 +91,26 @@ static float dist32(const float* q, const float* x, int d)
     return acc;
 }
 
+/* FP64 squared distance of the FP32 inputs: the difference of two FP32 values
+ * is exact in FP64 (for values within 2^29 of each other in magnitude), so
+ * each term carries one rounding and the sum d - 1 more. */
 static double dist64(const float* q, const float* x, int d)
 {
+#if ORC_MUTANT == 9
+    float acc = 0.0f; /* accumulates in FP32 */
+    for (int j = 0; j < d; ++j) {
+        float u = q[j] - x[j];
+        acc = acc + u * u;
+    }
+    return (double)acc;
+#else
     double acc = 0.0;
     for (int j = 0; j < d; ++j) {
         double u = (double)q[j] - (double)x[j];
         acc = acc + u * u;
     }
     return acc;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */

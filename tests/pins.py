@@ -13,6 +13,7 @@ from fractions import Fraction
 
 import numpy as np
 
+import fp64rule
 import oracle
 from treecheck import check_tree
 
@@ -139,21 +140,86 @@ def pin_dist32_error_bound(lib, seed=12):
     return None
 
 
-def pin_fp64_cross_check(lib, seed=13):
-    """FP32 and FP64 brute force may disagree only where the FP64 distances of
-    the two differing neighbours are within 1e-6 relative."""
+def pin_bf64_exact_rationals(lib, seed=14):
+    """FP64 brute force against exact rational arithmetic on non-integer data
+    of mixed scales: every returned distance lies within d * 2^-52 of the
+    exact squared distance (relative), and the neighbours are the exact k
+    nearest, ordered by exact distance then index.  An FP32 accumulation
+    misses the distance bound by about eight orders of magnitude."""
     rng = np.random.default_rng(seed)
-    for d in (2, 3, 4, 10):
-        X = rng.random((3000, d)).astype(np.float32)
-        Q = rng.random((64, d)).astype(np.float32)
-        i32, _ = oracle.bf32(X, Q, 8, lib=lib)
-        i64, d64 = oracle.bf64(X, Q, 8, lib=lib)
-        Xd, Qd = X.astype(np.float64), Q.astype(np.float64)
-        for r, c in zip(*np.nonzero(i32 != i64)):
-            a = ((Xd[i32[r, c]] - Qd[r]) ** 2).sum()
-            b = d64[r, c]
-            if abs(a - b) >= 1e-6 * max(a, b) and a != b:
-                return f"d={d}: mismatch with FP64 gap {abs(a - b) / max(a, b):.3g}"
+    for d in (1, 2, 3, 5, 10, 16):
+        n, m, k = 120, 6, 9
+        scale = 10.0 ** rng.integers(-3, 3, size=(1, d))
+        X = (rng.standard_normal((n, d)) * scale).astype(np.float32)
+        Q = (rng.standard_normal((m, d)) * scale).astype(np.float32)
+        oi, od = oracle.bf64(X, Q, k, lib=lib)
+        for r in range(m):
+            q = [Fraction(float(v)) for v in Q[r]]
+            exact = [sum((qj - Fraction(float(xj))) ** 2 for qj, xj in zip(q, X[i]))
+                     for i in range(n)]
+            want = sorted(range(n), key=lambda i: (exact[i], i))[:k]
+            if oi[r].tolist() != want:
+                return f"d={d} query {r}: FP64 brute force {oi[r].tolist()}, exact {want}"
+            bound = Fraction(d, 1 << 52)
+            for j, i in enumerate(want):
+                if abs(Fraction(float(od[r, j])) - exact[i]) > bound * exact[i]:
+                    return f"d={d} query {r} rank {j}: FP64 distance outside d * 2^-52"
+    return None
+
+
+def pin_fp64_near_tie(lib):
+    """Hand-derived near-tie that FP32 and FP64 order differently
+    (tests/golden/fp64_near_tie.json): FP32 ties two points and orders them
+    by index, FP64 separates them by 2^-26; the gap is inside the 1e-6 rule."""
+    g = _gold("fp64_near_tie.json")
+    X = np.array([[_hexf(h) for h in row] for row in g["points_hex"]], np.float32)
+    q = np.array([g["q"]], np.float32)
+    i32, d32 = oracle.bf32(X, q, g["k"], lib=lib)
+    if i32[0].tolist() != g["fp32_idx"] or d32[0].tolist() != g["fp32_d2"]:
+        return f"FP32 brute force gives {i32[0].tolist()} {d32[0].tolist()}"
+    i64, d64 = oracle.bf64(X, q, g["k"], lib=lib)
+    if i64[0].tolist() != g["fp64_idx"] or d64[0].tolist() != g["fp64_d2"]:
+        return f"FP64 brute force gives {i64[0].tolist()} {d64[0].tolist()}"
+    T = oracle.build(X, 1, lib=lib)
+    ti, td = T.query(q, g["k"])
+    if ti[0].tolist() != g["fp32_idx"]:
+        return f"KD32 gives {ti[0].tolist()}"
+    c = fp64rule.classify(X, q, ti, i64, d64)
+    if c["bad"] or c["rule"] != 2:
+        return f"cross-check classification {c}"
+    return None
+
+
+def pin_fp64_cross_check(lib, seed=13):
+    """KD32 equals BF32, and against FP64 brute force every differing rank is
+    allowed by the 1e-6 relative rule or is a legal FP32 reorder (inside the
+    FP32 forward-error bound); both kinds are counted, any other is a bug."""
+    rng = np.random.default_rng(seed)
+    for d in (2, 3, 4, 10, 16):
+        # uniform data, and integer lattice points moved by ~3e-7 with queries
+        # at cell centres: many neighbours whose distances FP32 cannot separate
+        near = (rng.integers(0, 6, size=(3000, d)) +
+                rng.standard_normal((3000, d)) * 3e-7).astype(np.float32)
+        sets = [("uniform", rng.random((3000, d)).astype(np.float32),
+                 rng.random((64, d)).astype(np.float32)),
+                ("near-ties", near, (rng.integers(0, 6, size=(64, d)) + 0.5).astype(np.float32))]
+        for name, X, Q in sets:
+            i32, d32 = oracle.bf32(X, Q, 8, lib=lib)
+            T = oracle.build(X, 8, lib=lib)
+            ti, td = T.query(Q, 8)
+            if not (np.array_equal(ti, i32) and np.array_equal(td, d32)):
+                return f"{name} d={d}: KD32 != BF32"
+            i64, d64 = oracle.bf64(X, Q, 8, lib=lib)
+            c = fp64rule.classify(X, Q, ti, i64, d64)
+            if c["bad"]:
+                return f"{name} d={d}: mismatch beyond the FP32 error bound {c['bad'][:3]}"
+            if name == "near-ties" and c["differing_ranks"] == 0:
+                return f"d={d}: the near-tie set produced no FP32/FP64 difference"
+            # the check itself: a list with a far point in place of a neighbour fails
+            wrong = ti.copy()
+            wrong[0, 0] = int(np.argmax(fp64rule.dist64(X, Q[0], np.arange(len(X)))))
+            if not fp64rule.classify(X, Q, wrong, i64, d64)["bad"]:
+                return f"{name} d={d}: the cross-check accepted a wrong neighbour"
     return None
 
 
@@ -314,5 +380,6 @@ def pin_split_rule(lib, seed=51):
 
 
 ALL_PINS = [pin_golden_alg1, pin_fp32_sum_order, pin_grid_shells, pin_bf64_exact_on_integers,
-            pin_dist32_error_bound, pin_fp64_cross_check, pin_kd_equals_bf, pin_1d_window,
+            pin_dist32_error_bound, pin_bf64_exact_rationals, pin_fp64_near_tie,
+            pin_fp64_cross_check, pin_kd_equals_bf, pin_1d_window,
             pin_tree_invariants, pin_split_rule]

@@ -29,6 +29,8 @@ MUTANTS = {
         [pins.pin_fp32_sum_order]),
     8: ("sample positions shifted",
         [pins.pin_split_rule]),
+    9: ("FP64 brute force accumulates in FP32",
+        [pins.pin_bf64_exact_rationals, pins.pin_fp64_near_tie]),
 }
 
 
