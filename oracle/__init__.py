@@ -56,6 +56,9 @@ def _bind(lib):
     lib.orc_build.argtypes = [_p, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                               ctypes.POINTER(ctypes.c_int)]
     lib.orc_build.restype = _p
+    lib.orc_build_mt.argtypes = [_p, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int)]
+    lib.orc_build_mt.restype = _p
     lib.orc_tree_free.argtypes = [_p]
     lib.orc_tree_free.restype = None
     lib.orc_tree_nodes.argtypes = [_p]
@@ -184,13 +187,20 @@ class Tree:
             pass
 
 
-def build(points, leaf=32, max_depth=64, lib=None) -> Tree:
-    """Build the oracle kd-tree (Section III-A)."""
+def build(points, leaf=32, max_depth=64, lib=None, nthreads=1) -> Tree:
+    """Build the oracle kd-tree (Section III-A).  ``nthreads`` > 1 builds the
+    subtrees below the top levels on their own threads; the tree (node ids
+    included) is the same as with one thread."""
     lib = lib or load()
     X = _f32(points)
     n, d = X.shape
     st = ctypes.c_int(0)
-    h = lib.orc_build(_ptr(X), n, d, leaf, max_depth, ctypes.byref(st))
+    if nthreads == 1:
+        h = lib.orc_build(_ptr(X), n, d, leaf, max_depth, ctypes.byref(st))
+    else:
+        if nthreads <= 0:
+            nthreads = os.cpu_count() or 1
+        h = lib.orc_build_mt(_ptr(X), n, d, leaf, max_depth, nthreads, ctypes.byref(st))
     if not h:
         raise ValueError(f"orc_build failed: {st.value}")
     N = lib.orc_tree_nodes(h)

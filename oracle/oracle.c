@@ -307,14 +307,36 @@ static int bin_of(const float* sorted, int s, float x)
 
 typedef struct {
     const float* X; int d; int leaf; int max_depth;
-    orc_tree* T;
+    orc_tree* T;     /* node store the recursion appends to */
     int32_t* order; int32_t* tmp;
     double* sv; double* sq; double* work; float* sorted; int64_t* hist;
     int err;
+    int spawn;       /* levels below which a right subtree may still get its own thread */
 } build_ctx;
 
-static int64_t new_node(orc_tree* T, int64_t start, int64_t cnt, int level)
+/* Double the node arrays of a store (only the stores of subtrees built by
+ * other threads grow; the tree's own store is sized for 2n nodes). */
+static int grow_store(orc_tree* T)
 {
+    int64_t cap = T->cap ? 2 * T->cap : 64;
+    void* p[7];
+    p[0] = realloc(T->dim, sizeof(int32_t) * (size_t)cap); if (p[0]) T->dim = (int32_t*)p[0];
+    p[1] = realloc(T->split, sizeof(float) * (size_t)cap); if (p[1]) T->split = (float*)p[1];
+    p[2] = realloc(T->left, sizeof(int64_t) * (size_t)cap); if (p[2]) T->left = (int64_t*)p[2];
+    p[3] = realloc(T->right, sizeof(int64_t) * (size_t)cap); if (p[3]) T->right = (int64_t*)p[3];
+    p[4] = realloc(T->start, sizeof(int64_t) * (size_t)cap); if (p[4]) T->start = (int64_t*)p[4];
+    p[5] = realloc(T->count, sizeof(int64_t) * (size_t)cap); if (p[5]) T->count = (int64_t*)p[5];
+    p[6] = realloc(T->level, sizeof(int32_t) * (size_t)cap); if (p[6]) T->level = (int32_t*)p[6];
+    for (int i = 0; i < 7; ++i)
+        if (!p[i]) return -1;
+    T->cap = cap;
+    return 0;
+}
+
+static int64_t new_node(build_ctx* B, int64_t start, int64_t cnt, int level)
+{
+    orc_tree* T = B->T;
+    if (T->n_nodes == T->cap && grow_store(T)) { B->err = -2; return -1; }
     int64_t v = T->n_nodes++;
     T->dim[v] = -1; T->split[v] = 0.0f; T->left[v] = -1; T->right[v] = -1;
     T->start[v] = start; T->count[v] = cnt; T->level[v] = level;
@@ -395,6 +417,9 @@ static int choose_split(build_ctx* B, int64_t lo, int64_t c, int* out_dim, float
     return 1;
 }
 
+static void build_node(build_ctx* B, int64_t v);
+static void build_children(build_ctx* B, int64_t L, int64_t R);
+
 static void build_node(build_ctx* B, int64_t v)
 {
     orc_tree* T = B->T;
@@ -429,10 +454,110 @@ static void build_node(build_ctx* B, int64_t v)
     memcpy(B->order + lo, B->tmp + lo, sizeof(int32_t) * (size_t)c);
     T->dim[v] = dim;
     T->split[v] = split;
-    int64_t L = new_node(T, lo, nl, T->level[v] + 1);
-    int64_t R = new_node(T, lo + nl, c - nl, T->level[v] + 1);
+    int64_t L = new_node(B, lo, nl, T->level[v] + 1);
+    int64_t R = new_node(B, lo + nl, c - nl, T->level[v] + 1);
+    if (B->err) return;
     T->left[v] = L;
     T->right[v] = R;
+    build_children(B, L, R);
+}
+
+/* ---- optional threads: the two children of a node cover disjoint ranges of
+ * the index order, so the right subtree can be built by another thread into
+ * a store of its own.  Appending that store after the left subtree gives every
+ * node the id the one-thread recursion gives it (left subtree first, then the
+ * right one), so the tree is the same with any thread count. */
+
+typedef struct {
+    build_ctx ctx;  /* its T: a store whose node 0 stands for the right child */
+    int64_t R;      /* the right child's id in the parent's store */
+} fork_job;
+
+static int ctx_scratch(build_ctx* B)
+{
+    B->sv = (double*)malloc(sizeof(double) * ORC_SAMPLE_MAX);
+    B->sq = (double*)malloc(sizeof(double) * ORC_SAMPLE_MAX);
+    B->work = (double*)malloc(sizeof(double) * ORC_SAMPLE_MAX);
+    B->sorted = (float*)malloc(sizeof(float) * ORC_SAMPLE_MAX);
+    B->hist = (int64_t*)malloc(sizeof(int64_t) * (ORC_SAMPLE_MAX + 1));
+    return (B->sv && B->sq && B->work && B->sorted && B->hist) ? 0 : -1;
+}
+
+static void ctx_free_scratch(build_ctx* B)
+{
+    free(B->sv); free(B->sq); free(B->work); free(B->sorted); free(B->hist);
+}
+
+static void store_free(orc_tree* S)
+{
+    free(S->dim); free(S->split); free(S->left); free(S->right);
+    free(S->start); free(S->count); free(S->level);
+}
+
+static void* fork_main(void* p)
+{
+    fork_job* J = (fork_job*)p;
+    build_node(&J->ctx, 0);
+    return NULL;
+}
+
+/* Append store S (node 0 = node R of B's store) to B's store. */
+static void append_store(build_ctx* B, const orc_tree* S, int64_t R)
+{
+    orc_tree* T = B->T;
+    int64_t base = T->n_nodes - 1; /* local id j >= 1 becomes base + j */
+    while (T->cap < T->n_nodes + S->n_nodes - 1)
+        if (grow_store(T)) { B->err = -2; return; }
+    for (int64_t j = 0; j < S->n_nodes; ++j) {
+        int64_t g = j == 0 ? R : base + j;
+        T->dim[g] = S->dim[j];
+        T->split[g] = S->split[j];
+        T->left[g] = S->left[j] < 0 ? -1 : base + S->left[j];
+        T->right[g] = S->right[j] < 0 ? -1 : base + S->right[j];
+        T->start[g] = S->start[j];
+        T->count[g] = S->count[j];
+        T->level[g] = S->level[j];
+    }
+    T->n_nodes += S->n_nodes - 1;
+    if (S->depth > T->depth) T->depth = S->depth;
+}
+
+static void build_children(build_ctx* B, int64_t L, int64_t R)
+{
+    orc_tree* T = B->T;
+    if (B->spawn > 0) {
+        fork_job* J = (fork_job*)calloc(1, sizeof(fork_job));
+        orc_tree* S = (orc_tree*)calloc(1, sizeof(orc_tree));
+        pthread_t th;
+        if (J && S && ctx_scratch(&J->ctx) == 0 && grow_store(S) == 0) {
+            J->ctx.X = B->X; J->ctx.d = B->d; J->ctx.leaf = B->leaf;
+            J->ctx.max_depth = B->max_depth; J->ctx.order = B->order; J->ctx.tmp = B->tmp;
+            J->ctx.T = S;
+            J->ctx.spawn = B->spawn - 1;
+            J->R = R;
+            S->depth = T->level[R];
+            S->n_nodes = 1;
+            S->dim[0] = -1; S->split[0] = 0.0f; S->left[0] = -1; S->right[0] = -1;
+            S->start[0] = T->start[R]; S->count[0] = T->count[R]; S->level[0] = T->level[R];
+            if (pthread_create(&th, NULL, fork_main, J) == 0) {
+                B->spawn--;
+                build_node(B, L);
+                B->spawn++;
+                pthread_join(th, NULL);
+                if (J->ctx.err) B->err = J->ctx.err;
+                if (!B->err) append_store(B, S, R);
+                ctx_free_scratch(&J->ctx);
+                store_free(S);
+                free(S);
+                free(J);
+                return;
+            }
+        }
+        if (J) ctx_free_scratch(&J->ctx);
+        if (S) store_free(S);
+        free(S);
+        free(J);
+    }
     build_node(B, L);
     build_node(B, R);
 }
@@ -447,8 +572,10 @@ void orc_tree_free(orc_tree* T)
 }
 
 /* Build the local kd-tree (Section III-A; readings R6-R9).  status: 0 ok,
- * -1 bad argument, -2 out of memory, -4 depth above max_depth. */
-orc_tree* orc_build(const float* X, int64_t n, int d, int leaf, int max_depth, int* status)
+ * -1 bad argument, -2 out of memory, -4 depth above max_depth.  nthreads > 1
+ * builds subtrees of the top levels on their own threads (same tree). */
+orc_tree* orc_build_mt(const float* X, int64_t n, int d, int leaf, int max_depth, int nthreads,
+                       int* status)
 {
     *status = -1;
     if (!X || n < 1 || d < 1 || d > 64 || leaf < 1 || max_depth < 0) return NULL;
@@ -466,21 +593,16 @@ orc_tree* orc_build(const float* X, int64_t n, int d, int leaf, int max_depth, i
     T->packed = (float*)malloc(sizeof(float) * (size_t)n * (size_t)d);
     build_ctx B = {0};
     B.X = X; B.d = d; B.leaf = leaf; B.max_depth = max_depth; B.T = T;
+    for (int t = 1; t < nthreads; t *= 2) B.spawn++; /* 2^spawn subtrees run at once */
     B.tmp = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    B.sv = (double*)malloc(sizeof(double) * ORC_SAMPLE_MAX);
-    B.sq = (double*)malloc(sizeof(double) * ORC_SAMPLE_MAX);
-    B.work = (double*)malloc(sizeof(double) * ORC_SAMPLE_MAX);
-    B.sorted = (float*)malloc(sizeof(float) * ORC_SAMPLE_MAX);
-    B.hist = (int64_t*)malloc(sizeof(int64_t) * (ORC_SAMPLE_MAX + 1));
     if (!T->dim || !T->split || !T->left || !T->right || !T->start || !T->count ||
-        !T->level || !T->perm || !T->packed || !B.tmp || !B.sv || !B.sq || !B.work ||
-        !B.sorted || !B.hist) {
+        !T->level || !T->perm || !T->packed || !B.tmp || ctx_scratch(&B)) {
         *status = -2;
         goto fail;
     }
     B.order = T->perm;
     for (int64_t i = 0; i < n; ++i) T->perm[i] = (int32_t)i;
-    new_node(T, 0, n, 0);
+    new_node(&B, 0, n, 0);
     build_node(&B, 0);
     if (B.err) { *status = B.err; goto fail; }
     /* Bucket packing (III-A iv) and tight boxes over each node's range. */
@@ -500,13 +622,20 @@ orc_tree* orc_build(const float* X, int64_t n, int d, int leaf, int max_depth, i
             T->lo[v * d + t] = mn;
             T->hi[v * d + t] = mx;
         }
-    free(B.tmp); free(B.sv); free(B.sq); free(B.work); free(B.sorted); free(B.hist);
+    free(B.tmp);
+    ctx_free_scratch(&B);
     *status = 0;
     return T;
 fail:
-    free(B.tmp); free(B.sv); free(B.sq); free(B.work); free(B.sorted); free(B.hist);
+    free(B.tmp);
+    ctx_free_scratch(&B);
     orc_tree_free(T);
     return NULL;
+}
+
+orc_tree* orc_build(const float* X, int64_t n, int d, int leaf, int max_depth, int* status)
+{
+    return orc_build_mt(X, n, d, leaf, max_depth, 1, status);
 }
 
 int64_t orc_tree_nodes(const orc_tree* T) { return T->n_nodes; }

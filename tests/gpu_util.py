@@ -54,26 +54,39 @@ def check_links(g: dict, n: int) -> None:
     assert int(ct.sum()) == n, "buckets do not cover the points"
 
 
-def compare_trees(g: dict, o: oracle.Tree) -> int:
-    """Walk the GPU tree and the oracle tree from their roots in lockstep and
-    require identical split dimensions, split values, ranges and boxes, and an
-    identical packed order.  Returns the number of nodes compared."""
-    assert np.array_equal(g["perm"], o.perm), "packed order differs"
-    stack = [(0, 0)]
+def compare_trees(g: dict, o: oracle.Tree, root: int = 0, off: int = 0) -> int:
+    """Walk the GPU tree (from node `root`, rows from `off`: a forest's tree)
+    and the oracle tree from their roots in lockstep, a level at a time, and
+    require identical split dimensions, split values, ranges and boxes, and
+    an identical packed order.  Returns the number of nodes compared."""
+    n_t = len(o.perm)
+    assert np.array_equal(g["perm"][off:off + n_t].astype(np.int64) - off, o.perm), \
+        "packed order differs"
+    a = np.array([root], np.int64)
+    b = np.array([0], np.int64)
     seen = 0
-    while stack:
-        a, b = stack.pop()
-        seen += 1
-        assert g["start"][a] == o.start[b] and g["count"][a] == o.count[b], (a, b)
-        assert np.array_equal(g["lo"][a], o.lo[b]) and np.array_equal(g["hi"][a], o.hi[b]), (a, b)
-        if o.dim[b] < 0:
-            assert g["dim"][a] < 0, f"GPU node {a} splits, oracle node {b} is a leaf"
-            continue
-        assert g["dim"][a] == o.dim[b], f"node {a}/{b}: dim {g['dim'][a]} vs {o.dim[b]}"
-        assert g["split"][a] == o.split[b], f"node {a}/{b}: split {g['split'][a]} vs {o.split[b]}"
-        stack.append((int(g["left"][a]), int(o.left[b])))
-        stack.append((int(g["left"][a]) + 1, int(o.right[b])))
-    assert seen == len(g["dim"]) == len(o.dim), (seen, len(g["dim"]), len(o.dim))
+    while a.size:
+        seen += a.size
+
+        def first_bad(ok, what):
+            if not ok.all():
+                j = int(np.flatnonzero(~ok)[0])
+                raise AssertionError(f"{what}: GPU node {a[j]} vs oracle node {b[j]}")
+        first_bad((g["start"][a].astype(np.int64) - off == o.start[b])
+                  & (g["count"][a] == o.count[b]), "range")
+        first_bad((g["lo"][a] == o.lo[b]).all(1) & (g["hi"][a] == o.hi[b]).all(1), "box")
+        leaf = o.dim[b] < 0
+        first_bad(~leaf | (g["dim"][a] < 0), "GPU splits where the oracle has a leaf")
+        ai, bi = a[~leaf], b[~leaf]
+        a, b = ai, bi
+        first_bad(g["dim"][ai] == o.dim[bi], "split dimension")
+        first_bad(g["split"][ai] == o.split[bi], "split value")
+        gl = g["left"][ai].astype(np.int64)
+        a = np.concatenate([gl, gl + 1])
+        b = np.concatenate([o.left[bi], o.right[bi]])
+    assert seen == len(o.dim), (seen, len(o.dim))
+    if root == 0 and off == 0 and n_t == len(g["perm"]):  # a single tree: nothing else
+        assert seen == len(g["dim"]), (seen, len(g["dim"]))
     return seen
 
 
