@@ -35,6 +35,7 @@ extern "C" {
 #define KNN_ENOMEM -2   /* device or host allocation failed */
 #define KNN_EDEVICE -3  /* a HIP call failed; knn_last_error() holds its message */
 #define KNN_EDEPTH -4   /* the tree would be deeper than max_depth */
+#define KNN_ENOTFINITE -5 /* an input coordinate is NaN or infinite (the build requires finite points) */
 
 #define KNN_MAX_DIM 16  /* dimensions supported: 1..KNN_MAX_DIM */
 #define KNN_MAX_K 64    /* neighbours per query: 1..KNN_MAX_K */
@@ -129,7 +130,9 @@ typedef struct {
  * points (Section III-A1, bucket size); buckets are stored contiguously
  * (Section III-A iv).  The tree copies what it needs: `points` may be reused
  * once the call returns.  The call synchronizes `stream` before returning.
- * Errors: KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH (no tree is returned).
+ * Errors: KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH, KNN_ENOTFINITE (a
+ * coordinate is NaN or infinite: checked while the points are copied in,
+ * before any split is computed); no tree is returned on error.
  */
 int knn_build(const float* points, int64_t n, int32_t dim, int32_t leaf_size, void* stream,
               knn_tree** out);
@@ -181,10 +184,12 @@ int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
 
 /*
  * knn_query_batch -- knn_query_ex on a forest: query i searches only tree
- * tree_ids[i] (device pointer [m] int32, each in [0, trees); a value outside
- * that range is undefined behaviour).  All queries run in one batch of
- * launches whatever trees they address.  Indices are rows of the
- * concatenated points; self_ids use the same numbering.
+ * tree_ids[i] (device pointer [m] int32, each in [0, trees)).  All queries
+ * run in one batch of launches whatever trees they address.  Indices are rows
+ * of the concatenated points; self_ids use the same numbering.  The ids are
+ * checked on the device: a query whose id is outside [0, trees) reads no
+ * node, gets a row of padding (-1, +inf) and is counted; knn_tree_errors
+ * returns KNN_EINVAL and the count.
  */
 int knn_query_batch(const knn_tree* t, const float* queries, const int32_t* tree_ids,
                     int64_t m, int32_t k, const int32_t* self_ids, float r2_max,
@@ -287,8 +292,19 @@ int knn_classify(const int32_t* idx, int64_t m, int32_t k, const int32_t* labels
 int knn_regress(const int32_t* idx, int64_t m, int32_t k, const float* values, float* out,
                 void* stream);
 
-/* Free a tree and its device memory (waits for the device first).  NULL is OK. */
+/* Free a tree and its device memory.  Waits for the latest query enqueued on
+ * each stream that queried the tree (not for other work on the device), then
+ * returns the memory to the device's stream-ordered pool.  Launches of a
+ * captured graph that read the tree are not tracked: the caller waits for
+ * them before freeing.  NULL is OK. */
 int knn_tree_free(knn_tree* t);
+
+/* knn_tree_errors -- waits for `stream`, then reads and clears the count of
+ * queries that, since the previous call, named a tree id outside [0, trees)
+ * in knn_query_batch (each was answered with padding rows).  bad_queries (may
+ * be NULL) receives the count.  Returns KNN_EINVAL, with the count in the
+ * message, when it is nonzero; KNN_OK otherwise. */
+int knn_tree_errors(const knn_tree* t, void* stream, int64_t* bad_queries);
 
 /* Sizes and shape of a tree. */
 int knn_tree_info(const knn_tree* t, knn_tree_info_t* info);
@@ -298,6 +314,10 @@ int knn_tree_export(const knn_tree* t, knn_tree_host* h);
 
 /* Message describing the last failure of the calling thread. */
 const char* knn_last_error(void);
+
+/* Fixed name of a return code ("KNN_OK", "KNN_EINVAL", ...; "unknown" for any
+ * other value).  The string is static. */
+const char* knn_strerror(int code);
 
 /* Per-phase device times of the most recent build and query on this thread,
  * in milliseconds, taken with HIP events on the call's stream while profiling

@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libknn.so")
 
-KNN_OK, KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH = 0, -1, -2, -3, -4
+KNN_OK, KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH, KNN_ENOTFINITE = 0, -1, -2, -3, -4, -5
 KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES, KNN_QUERY_STATS = 16, 64, 12, 9
 PHASES = ("build_ingest", "build_levels", "build_finish", "build_compact", "build_total",
           "query_locate", "query_group", "query_traverse", "query_total",
@@ -62,8 +62,9 @@ _lib = None
 EXPORTED = ("knn_build", "knn_build_ex", "knn_build_batch", "knn_query", "knn_query_ex",
             "knn_query_batch", "knn_query_radius", "knn_merge", "knn_classify", "knn_regress",
             "knn_server_create",
-            "knn_server_submit", "knn_server_wait", "knn_server_stats", "knn_server_destroy", "knn_tree_free", "knn_tree_info", "knn_tree_export", "knn_last_error",
-            "knn_set_profiling", "knn_get_profile")
+            "knn_server_submit", "knn_server_wait", "knn_server_stats", "knn_server_destroy",
+            "knn_tree_free", "knn_tree_errors", "knn_tree_info", "knn_tree_export",
+            "knn_last_error", "knn_strerror", "knn_set_profiling", "knn_get_profile")
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -98,14 +99,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.knn_classify.argtypes = [vp, i64, i32, vp, vp, vp, vp]
     lib.knn_regress.argtypes = [vp, i64, i32, vp, vp, vp]
     lib.knn_tree_free.argtypes = [vp]
+    lib.knn_tree_errors.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.knn_tree_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.knn_tree_export.argtypes = [vp, ctypes.POINTER(_Host)]
     lib.knn_last_error.argtypes = []
     lib.knn_last_error.restype = ctypes.c_char_p
+    lib.knn_strerror.argtypes = [ctypes.c_int]
+    lib.knn_strerror.restype = ctypes.c_char_p
     lib.knn_set_profiling.argtypes = [i32]
     lib.knn_get_profile.argtypes = [ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTED:
-        if name != "knn_last_error":
+        if name not in ("knn_last_error", "knn_strerror"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -113,7 +117,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
 
 def _check(rc: int):
     if rc != KNN_OK:
-        raise KnnError(rc, load_library().knn_last_error().decode())
+        lib = load_library()
+        raise KnnError(rc, f"{lib.knn_strerror(rc).decode()}: {lib.knn_last_error().decode()}")
 
 
 def _stream(t):
@@ -291,7 +296,7 @@ def knn_query_batch(forest: Tree, queries, tree_ids, k: int, self_ids=None,
 
 
 def knn_query_radius(tree: Tree, queries, k: int, r2, self_ids=None, order: int = 0, out=None,
-                     leaf_batch: int = 0):
+                     leaf_batch: int = 0, traversal: int = 0):
     """k nearest neighbours with one squared radius per query (CUDA float32 [m])."""
     import torch
     lib = load_library()
@@ -302,7 +307,7 @@ def knn_query_radius(tree: Tree, queries, k: int, r2, self_ids=None, order: int 
         raise TypeError("r2 must be a contiguous CUDA float32 [m] tensor")
     idx, d2 = _outputs(queries, k, out)
     sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
-    p = _QueryParams(order, leaf_batch, None)
+    p = _QueryParams(order, leaf_batch, None, traversal)
     _check(lib.knn_query_radius(tree.handle, ctypes.c_void_p(queries.data_ptr()), m, k, sp,
                                 ctypes.c_void_p(r2.data_ptr()), ctypes.byref(p),
                                 ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
@@ -471,6 +476,22 @@ def knn_tree_export(tree: Tree) -> dict:
 
 def knn_tree_free(tree: Tree):
     tree.free()
+
+
+def knn_tree_errors(tree: Tree, stream=None) -> int:
+    """Count of queries that named an out-of-range tree id since the last
+    call (waits for the stream, clears the count); raises KnnError
+    (KNN_EINVAL) when it is nonzero."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(tree.device)
+    c = ctypes.c_int64()
+    _check(load_library().knn_tree_errors(tree.handle, ctypes.c_void_p(s.cuda_stream),
+                                          ctypes.byref(c)))
+    return c.value
+
+
+def knn_strerror(code: int) -> str:
+    return load_library().knn_strerror(code).decode()
 
 
 def knn_last_error() -> str:

@@ -104,6 +104,19 @@ extern "C" {
 
 const char* knn_last_error(void) { return g_err.c_str(); }
 
+const char* knn_strerror(int code)
+{
+    switch (code) {
+    case KNN_OK: return "KNN_OK";
+    case KNN_EINVAL: return "KNN_EINVAL";
+    case KNN_ENOMEM: return "KNN_ENOMEM";
+    case KNN_EDEVICE: return "KNN_EDEVICE";
+    case KNN_EDEPTH: return "KNN_EDEPTH";
+    case KNN_ENOTFINITE: return "KNN_ENOTFINITE";
+    default: return "unknown";
+    }
+}
+
 namespace {
 
 int build_common(const float* points, int64_t n, int32_t dim, const int64_t* offsets,
@@ -248,16 +261,39 @@ int knn_tree_free(knn_tree* t)
     if (!t) return KNN_OK;
     DeviceGuard g(t->device);
     int rc = KNN_OK;
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
-    // stream-ordered pool allocations of the build; the device is idle here
+    {   // wait for the latest query on every stream that queried the tree; the
+        // build synchronised its own stream before returning
+        std::lock_guard<std::mutex> lk(t->use_mu);
+        for (auto& u : t->uses) {
+            hipError_t e = hipEventSynchronize(u.second);
+            if (e != hipSuccess && rc == KNN_OK) rc = hip_fail(e, "hipEventSynchronize");
+            (void)hipEventDestroy(u.second);
+        }
+        t->uses.clear();
+    }
+    // stream-ordered pool allocations of the build: no work reads them any
+    // more, so they go back to the pool without waiting for the device
     if (t->pts) (void)hipFreeAsync(t->pts, nullptr);
     if (t->nodes) (void)hipFreeAsync(t->nodes, nullptr);
     if (t->bbox) (void)hipFreeAsync(t->bbox, nullptr);
-    e = hipStreamSynchronize(nullptr);
-    if (e != hipSuccess && rc == KNN_OK) rc = hip_fail(e, "hipStreamSynchronize");
+    if (t->bad) (void)hipFreeAsync(t->bad, nullptr);
     delete t;
     return rc;
+}
+
+int knn_tree_errors(const knn_tree* t, void* stream, int64_t* bad_queries)
+{
+    if (!t) return fail(KNN_EINVAL, "tree is NULL");
+    DeviceGuard g(t->device);
+    unsigned long long c = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    KNN_HIP(hipMemcpyAsync(&c, t->bad, sizeof(c), hipMemcpyDeviceToHost, st));
+    KNN_HIP(hipMemsetAsync(t->bad, 0, sizeof(c), st));
+    KNN_HIP(hipStreamSynchronize(st));
+    if (bad_queries) *bad_queries = (int64_t)c;
+    if (c) return fail(KNN_EINVAL, std::to_string(c) + " queries named a tree id outside [0, " +
+                                       std::to_string(t->n_trees) + ") and got padding rows");
+    return KNN_OK;
 }
 
 int knn_tree_info(const knn_tree* t, knn_tree_info_t* info)

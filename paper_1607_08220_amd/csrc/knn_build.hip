@@ -93,8 +93,9 @@ struct Level {
 
 // Build-wide device counters (the id and subtree counters before the
 // current level are kept in G_BASE_ID / G_BASE_SUB for the plan writes).
+// G_NONFINITE: set by the ingest when an input coordinate is NaN or infinite.
 enum { G_NEXT_ID = 0, G_NSUB = 1, G_ERR = 2, G_BASE_ID = 3, G_BASE_SUB = 4, G_MOVED = 6,
-       G_COUNT = 8 };  // G_MOVED: 64-bit count of points partitioned (slots 6-7)
+       G_NONFINITE = 8, G_COUNT = 9 };  // G_MOVED: 64-bit count of points partitioned (slots 6-7)
 constexpr int kPlanVals = 5;  // split nodes, level children, subtrees, blocks, histogram blocks
 constexpr int kPlanStride = 8;
 constexpr int kErrOverflow = -100;
@@ -132,14 +133,23 @@ __device__ inline float wave_max(float v)
 // ---------------------------------------------------------------------------
 // B0: ingest
 // ---------------------------------------------------------------------------
+// Also flags (g[G_NONFINITE]) an input coordinate that is NaN or infinite:
+// the build requires finite points.
 __global__ void k_ingest(const float* __restrict__ aos, int64_t n, int d,
-                         float* __restrict__ cols, int32_t* __restrict__ idx)
+                         float* __restrict__ cols, int32_t* __restrict__ idx,
+                         int32_t* __restrict__ g)
 {
+    bool bad = false;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        for (int t = 0; t < d; ++t) cols[(int64_t)t * n + i] = aos[i * d + t];
+        for (int t = 0; t < d; ++t) {
+            const float v = aos[i * d + t];
+            bad = bad || !__builtin_isfinite(v);
+            cols[(int64_t)t * n + i] = v;
+        }
         idx[i] = (int32_t)i;
     }
+    if (__ballot(bad) != 0 && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&g[G_NONFINITE], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1988,11 +1998,18 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     KNN_HIP(hipMemsetAsync(pts.as<float>() + n * (d + 1), 0, sizeof(float) * kRowPad * (d + 1), st));
     KNN_HIP(gbuf.alloc(sizeof(int32_t) * G_COUNT));
     int32_t* g = gbuf.as<int32_t>();
+    KNN_HIP(hipMemsetAsync(g, 0, sizeof(int32_t) * G_COUNT, st));
     {
         const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
         k_ingest<<<(unsigned)blocks, kBlock, 0, st>>>(points, n, d, colsA.as<float>(),
-                                                      idxA.as<int32_t>());
+                                                      idxA.as<int32_t>(), g);
         KNN_HIP(hipGetLastError());
+        // stop before any split work if a coordinate is not finite
+        int32_t nonfinite = 0;
+        KNN_HIP(hipMemcpyAsync(&nonfinite, g + G_NONFINITE, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st));
+        KNN_HIP(hipStreamSynchronize(st));
+        if (nonfinite) return fail(KNN_ENOTFINITE, "an input coordinate is NaN or infinite");
     }
     prof_mark(st, 1);
 
@@ -2213,9 +2230,11 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         h_base[i] = (int32_t)total;
         total += h_subn[i] - 1;
     }
-    DevBuf nodes(st), bbox(st), d_base(st);
+    DevBuf nodes(st), bbox(st), d_base(st), badc(st);
     KNN_HIP(nodes.alloc(sizeof(NodeRec) * total));
     KNN_HIP(bbox.alloc(sizeof(float) * total * 2 * d));
+    KNN_HIP(badc.alloc(sizeof(unsigned long long)));
+    KNN_HIP(hipMemsetAsync(badc.p, 0, sizeof(unsigned long long), st));
     KNN_HIP(d_base.alloc(sizeof(int32_t) * n_sub));
     if (n_big > 1)
         KNN_HIP(hipMemcpyAsync(nodes.p, d_big.p, sizeof(NodeRec) * n_big, hipMemcpyDeviceToDevice, st));
@@ -2243,13 +2262,15 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     t->sub_pts = W;
     t->n_nodes = total;
     (void)hipGetDevice(&t->device);
-    t->bytes = (int64_t)(pts.bytes + nodes.bytes + bbox.bytes);
+    t->bytes = (int64_t)(pts.bytes + nodes.bytes + bbox.bytes + badc.bytes);
     t->pts = pts.as<float>();
     t->nodes = nodes.as<NodeRec>();
     t->bbox = bbox.as<float>();
+    t->bad = badc.as<unsigned long long>();
     pts.release();
     nodes.release();
     bbox.release();
+    badc.release();
     *out = t;
     return KNN_OK;
 }

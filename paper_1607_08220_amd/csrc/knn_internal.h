@@ -5,7 +5,9 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "knn.h"
@@ -29,8 +31,10 @@ constexpr int kSampleMax = 1024;   // sample points per node (Section III-A1)
 constexpr int kDefaultLeaf = 32;   // bucket size the paper found best
 constexpr int kDefaultMaxDepth = 64;
 constexpr int64_t kDefaultSplitBlockNodes = 256;  // see knn_build_params.split_block_nodes
+// lanes of 64 holding a bucket before a wavefront scans (knn_query_params.leaf_batch)
 constexpr int kDefaultLeafBatch = 48;
-constexpr int kRowPad = 8;  // zero rows after the last bucket row: whole row batches may be loaded  // lanes of 64 holding a bucket before a wavefront scans
+// zero rows after the last bucket row: whole row batches may be loaded
+constexpr int kRowPad = 8;
 
 }  // namespace knn
 
@@ -48,7 +52,14 @@ struct knn_tree {
     float* pts = nullptr;            // [n][d+1]: packed coordinates, last word = index bits
     knn::NodeRec* nodes = nullptr;   // [n_nodes]
     float* bbox = nullptr;           // [n_nodes][2d]: lo[0..d), hi[0..d)
+    // [1] count of queries that named a tree id outside [0, n_trees) since
+    // knn_tree_errors last read it
+    unsigned long long* bad = nullptr;
     int64_t bytes = 0;
+    // Every stream that queried the tree, with an event recorded after its
+    // latest query there: knn_tree_free waits for these and nothing else.
+    mutable std::mutex use_mu;
+    mutable std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 namespace knn {
@@ -142,6 +153,9 @@ struct QuerySpec {
 };
 
 int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t stream);
+// Record that `stream` has enqueued work reading the tree (skipped while the
+// stream is being captured into a graph).
+int note_tree_use(const knn_tree* t, hipStream_t stream);
 int merge_lists(const int32_t* ia, const float* da, int ka, const int32_t* ib, const float* db,
                 int kb, int64_t m, int k, int32_t* oi, float* od, hipStream_t stream);
 

@@ -183,6 +183,8 @@ struct TravArgs {
     const int32_t* order;   // slot -> query (NULL: identity)
     const int32_t* home;    // slot -> home leaf (NULL: start at the query's root)
     const int32_t* root;    // per-query root node (a forest's tree), else node 0
+    int32_t n_roots;        // valid root ids: [0, n_roots)
+    unsigned long long* bad;  // count of queries whose root id is out of range
     const int32_t* self_ids;
     const float* r2s;       // per-query squared radius, else r2
     const int32_t* qk;      // per-query k (<= the kernel's capacity), else k
@@ -197,6 +199,18 @@ struct TravArgs {
 };
 
 namespace {
+
+// Root node of query qid: its tree's root (tree t of a forest is node t), or
+// -1 when the caller's tree id is out of range -- such a query visits no node,
+// is answered with padding rows, and is counted in A.bad.
+__device__ inline int query_root(const TravArgs& A, int64_t qid)
+{
+    if (!A.root) return 0;
+    const int r = A.root[qid];
+    if ((unsigned)r < (unsigned)A.n_roots) return r;
+    atomicAdd(A.bad, 1ull);
+    return -1;
+}
 
 // STATS adds visit counters summed per wavefront into stats[0..8]: per lane
 // (nodes entered from above, leaves scanned, points scanned, traversal steps,
@@ -249,13 +263,17 @@ __global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
     const uint64_t empty = r2 > 0.0f ? make_key(r2, 0) : 0;
 #pragma unroll
     for (int j = 0; j < KC; ++j) h[j] = j < pad ? 0 : empty;
-    int cur = home ? home[slot] : (A.root ? A.root[qid] : 0);
+    const int root = query_root(A, qid);
+    int cur = root < 0 ? -1 : (home ? home[slot] : root);
     int from = -1;  // -1: arrived from the parent; otherwise the child we came from
     // The record and box of `cur` are loaded at the end of the step that moves
     // there, together, so one memory latency is exposed per step.
-    NodeRec r = nodes[cur];
+    NodeRec r{};
     float bb[2 * D];
-    load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+    if (cur >= 0) {
+        r = nodes[cur];
+        load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+    }
     int lstart = 0, lcnt = 0;  // the bucket waiting to be scanned (lcnt > 0)
     while (true) {
         if constexpr (STATS) w_round += first_active_lane();
@@ -441,10 +459,13 @@ __global__ __launch_bounds__(kBlock) void k_traverse_stack(TravArgs A, int sdept
     for (int j = 0; j < KC; ++j) h[j] = j < pad ? 0 : empty;
     int2* my = stk + threadIdx.x;
     int sp = 0;
-    int cur = A.root ? A.root[qid] : 0;
-    NodeRec r = nodes[cur];
+    int cur = query_root(A, qid);
+    NodeRec r{};
     float bb[2 * D];
-    load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+    if (cur >= 0) {
+        r = nodes[cur];
+        load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+    }
     int lstart = 0, lcnt = 0;
     // the next pending far child whose bound does not exceed thr, or -1
     auto pop = [&](float thr) {
@@ -619,7 +640,12 @@ __global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
     int s_node = 0;      // pending far child of stack entry `lane`
     float s_bound = 0.0f;
     int sp = 0;
-    int cur = __builtin_amdgcn_readfirstlane(A.root ? A.root[qid] : 0);
+    int cur = 0;
+    if (A.root) {  // one lane validates (and counts) the tree id for the wavefront
+        int r0 = 0;
+        if (lane == 0) r0 = query_root(A, qid);
+        cur = __builtin_amdgcn_readfirstlane(r0);
+    }
     // record and box of the stack's top entry, loaded while a bucket is
     // scanned: the node the next pop most likely returns
     int pf = -1;
@@ -719,11 +745,15 @@ using WaveFn = void (*)(TravArgs);
 // that kLocQ independent node loads are in flight per step.
 constexpr int kLocQ = 4;
 
+// A query whose tree id is out of range descends tree 0 here (only its
+// place in the grouped order depends on it); the traversal answers it with
+// padding rows.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ nodes,
                                                    const float* __restrict__ queries,
-                                                   const int32_t* __restrict__ qroot, int64_t m,
-                                                   int shift, int32_t* __restrict__ home,
+                                                   const int32_t* __restrict__ qroot,
+                                                   int32_t n_roots, int64_t m, int shift,
+                                                   int32_t* __restrict__ home,
                                                    uint32_t* __restrict__ cnt)
 {
     const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kLocQ) + threadIdx.x;
@@ -735,7 +765,8 @@ __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ n
         const int64_t i = min(i0 + (int64_t)u * kBlock, m - 1);  // clamped: extra lanes repeat
 #pragma unroll
         for (int t = 0; t < D; ++t) q[u][t] = queries[i * D + t];
-        cur[u] = qroot ? qroot[i] : 0;
+        const int rt = qroot ? qroot[i] : 0;
+        cur[u] = (unsigned)rt < (unsigned)n_roots ? rt : 0;
     }
 #pragma unroll
     for (int u = 0; u < kLocQ; ++u) r[u] = nodes[cur[u]];
@@ -852,8 +883,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t* __restrict__ a, i
 }
 
 using TraverseFn = void (*)(TravArgs);
-using LocateFn = void (*)(const NodeRec*, const float*, const int32_t*, int64_t, int, int32_t*,
-                          uint32_t*);
+using LocateFn = void (*)(const NodeRec*, const float*, const int32_t*, int32_t, int64_t, int,
+                          int32_t*, uint32_t*);
 
 template <int D, bool STATS>
 TraverseFn pick_traverse(int k)
@@ -1012,6 +1043,23 @@ int merge_lists(const int32_t* ia, const float* da, int ka, const int32_t* ib, c
     return KNN_OK;
 }
 
+int note_tree_use(const knn_tree* t, hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    KNN_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return KNN_OK;  // a graph launch is the caller's to wait for
+    std::lock_guard<std::mutex> g(t->use_mu);
+    hipEvent_t ev = nullptr;
+    for (auto& u : t->uses)
+        if (u.first == st) ev = u.second;
+    if (!ev) {
+        KNN_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        t->uses.emplace_back(st, ev);
+    }
+    KNN_HIP(hipEventRecord(ev, st));
+    return KNN_OK;
+}
+
 int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
 {
     const int d = t->d;
@@ -1050,8 +1098,8 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
         // cleared by a kernel, not a memset node, so the call can be captured in a graph
         k_zero<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N);
         const unsigned lgrid = (unsigned)((m + kBlock * kLocQ - 1) / (kBlock * kLocQ));
-        hipLaunchKernelGGL(lf, dim3(lgrid), dim3(kBlock), 0, st, t->nodes, qs.queries, qs.qroot, m,
-                           shift, home, cnt);
+        hipLaunchKernelGGL(lf, dim3(lgrid), dim3(kBlock), 0, st, t->nodes, qs.queries, qs.qroot,
+                           t->n_trees, m, shift, home, cnt);
         KNN_HIP(hipGetLastError());
     }
     prof_mark(st, 6);
@@ -1071,6 +1119,8 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     A.order = grouped ? ord : nullptr;
     A.home = grouped ? shome : nullptr;
     A.root = qs.qroot;
+    A.n_roots = t->n_trees;
+    A.bad = t->bad;
     A.self_ids = qs.self_ids;
     A.r2s = qs.r2s;
     A.qk = qs.qk;
@@ -1102,7 +1152,7 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     }
     KNN_HIP(hipGetLastError());
     prof_mark(st, 8);
-    return KNN_OK;
+    return note_tree_use(t, st);
 }
 
 }  // namespace knn

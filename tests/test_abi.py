@@ -56,3 +56,14 @@ def test_argument_errors_need_no_device():
     assert lib.knn_query(None, None, 1, 5, None, None, None) == knn.KNN_EINVAL
     assert lib.knn_tree_free(None) == knn.KNN_OK
     assert lib.knn_tree_info(None, None) == knn.KNN_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libknn.so not built")
+def test_strerror_and_tree_errors_without_device():
+    import paper_1607_08220_amd as knn
+    lib = knn.load_library()
+    names = {c: knn.knn_strerror(c) for c in (0, -1, -2, -3, -4, -5)}
+    assert names == {0: "KNN_OK", -1: "KNN_EINVAL", -2: "KNN_ENOMEM", -3: "KNN_EDEVICE",
+                     -4: "KNN_EDEPTH", -5: "KNN_ENOTFINITE"}
+    assert knn.knn_strerror(7) == "unknown"
+    assert lib.knn_tree_errors(None, None, None) == knn.KNN_EINVAL

@@ -29,12 +29,13 @@ def _local_self(ids_global, members):
     return np.where(members[pos] == ids_global, pos, -1).astype(np.int32)
 
 
-@pytest.mark.parametrize("k", [1, 8, 33])
-def test_two_owner_query_with_radius_and_merge(knn, k):
+@pytest.mark.parametrize("k,trav,order", [(1, 0, 0), (8, 0, 0), (33, 0, 0), (8, 1, 0),
+                                           (8, 1, 1), (33, 2, 0), (8, 2, 1), (33, 3, 0)])
+def test_two_owner_query_with_radius_and_merge(knn, k, trav, order):
     import torch
     w = inputs.workload("cosmo_clustered", scale=1 / 512)
     X, Q, S = w.points, w.queries, w.self_ids
-    log(f"[case] two owners n={len(X)} m={len(Q)} k={k}")
+    log(f"[case] two owners n={len(X)} m={len(Q)} k={k} traversal={trav} order={order}")
     cut = np.float32(np.median(X[:, 0]))
     own = [np.flatnonzero(X[:, 0] < cut), np.flatnonzero(X[:, 0] >= cut)]
     trees = [knn.knn_build(dev(X[o]), 32) for o in own]
@@ -44,13 +45,15 @@ def test_two_owner_query_with_radius_and_merge(knn, k):
         sel = np.flatnonzero(owner == r)
         q = dev(Q[sel])
         # step 2: local k-NN on the owner, r' = its k-th distance
-        li, ld = knn.knn_query_ex(trees[r], q, k, self_ids=dev(_local_self(S[sel], own[r])))
+        li, ld = knn.knn_query_ex(trees[r], q, k, self_ids=dev(_local_self(S[sel], own[r])),
+                                  traversal=trav, order=order)
         li_g = torch.where(li >= 0, dev(own[r].astype(np.int32))[li.clamp(min=0).long()], li)
         rp = torch.nextafter(ld[:, -1].contiguous(), torch.tensor(np.inf, device=ld.device))
         # step 4: the other rank searches within r' (D <= r' admitted)
         o = 1 - r
         ri, rd = knn.knn_query_radius(trees[o], q, k, rp.contiguous(),
-                                      self_ids=dev(_local_self(S[sel], own[o])))
+                                      self_ids=dev(_local_self(S[sel], own[o])),
+                                      traversal=trav, order=order)
         ri_g = torch.where(ri >= 0, dev(own[o].astype(np.int32))[ri.clamp(min=0).long()], ri)
         # step 5: merge
         mi, md = knn.knn_merge((li_g.contiguous(), ld), (ri_g.contiguous(), rd), k)
@@ -81,16 +84,18 @@ def test_merge_edges(knn):
         knn.knn_merge((dev(ia), dev(da)), (dev(ib), dev(db)), 65)
 
 
-def test_radius_per_query_matches_scalar(knn):
+@pytest.mark.parametrize("trav,order", [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (3, 0)])
+def test_radius_per_query_matches_scalar(knn, trav, order):
     """A per-query radius equal for all queries gives the scalar-radius result."""
     import torch
     w = inputs.workload("tiny_uniform")
-    log("[case] per-query radius")
+    log(f"[case] per-query radius traversal={trav} order={order}")
     t = knn.knn_build(dev(w.points), 32)
     q = dev(w.queries)
     for r2 in (0.0, 1e-4, 2e-3, np.inf):
-        a = knn.knn_query_ex(t, q, 7, r2_max=r2)
-        b = knn.knn_query_radius(t, q, 7, torch.full((len(w.queries),), r2, device=q.device))
+        a = knn.knn_query_ex(t, q, 7, r2_max=r2, traversal=trav, order=order)
+        b = knn.knn_query_radius(t, q, 7, torch.full((len(w.queries),), r2, device=q.device),
+                                 traversal=trav, order=order)
         torch.cuda.synchronize()
         assert_same(a[0].cpu().numpy(), a[1].cpu().numpy(), b[0].cpu().numpy(),
                     b[1].cpu().numpy(), f"r2={r2}")

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import assert_same, dev, log
+from gpu_util import assert_same, compare_trees, dev, log
 from paper_1607_08220_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -25,20 +25,8 @@ def knn():
 def compare_forest_tree(g: dict, t: int, off: int, o: oracle.Tree) -> None:
     """Tree t of the forest export g (root node t, rows from off) against the
     oracle tree over the same rows."""
-    n_t = len(o.perm)
-    assert np.array_equal(g["perm"][off:off + n_t] - off, o.perm), f"tree {t}: packed order"
     assert g["parent"][t] == -1
-    stack = [(t, 0)]
-    while stack:
-        a, b = stack.pop()
-        assert g["start"][a] - off == o.start[b] and g["count"][a] == o.count[b], (t, a, b)
-        assert np.array_equal(g["lo"][a], o.lo[b]) and np.array_equal(g["hi"][a], o.hi[b]), (t, a)
-        if o.dim[b] < 0:
-            assert g["dim"][a] < 0, f"tree {t}: node {a} splits, oracle node {b} is a leaf"
-            continue
-        assert g["dim"][a] == o.dim[b] and g["split"][a] == o.split[b], (t, a, b)
-        stack.append((int(g["left"][a]), int(o.left[b])))
-        stack.append((int(g["left"][a]) + 1, int(o.right[b])))
+    compare_trees(g, o, root=t, off=off)
 
 
 @pytest.mark.parametrize("d,lo,hi,ntrees", [(6, 3.0, 14.0, 37), (3, 5.0, 17.0, 9), (2, 0.0, 6.0, 50)])
@@ -54,10 +42,19 @@ def test_forest_matches_oracle_and_single_trees(knn, d, lo, hi, ntrees):
     g = forest.export()
     Q, T, S = dev(f.queries), dev(f.tree_ids), dev(f.self_ids)
     fi, fd = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S)
-    fi2, fd2 = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=1)
     torch.cuda.synchronize()
-    fi, fd, fi2, fd2 = fi.cpu().numpy(), fd.cpu().numpy(), fi2.cpu().numpy(), fd2.cpu().numpy()
-    assert_same(fi, fd, fi2, fd2, "grouped vs input order")
+    fi, fd = fi.cpu().numpy(), fd.cpu().numpy()
+    # every traversal form in both orders: the lane-per-query forms start at
+    # the home leaf of each query's own tree (grouped across trees) or at its
+    # root; the wavefront form takes input order
+    for trav in (1, 2, 3):
+        for order in (0, 1):
+            ti, td = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order,
+                                         traversal=trav)
+            torch.cuda.synchronize()
+            assert_same(ti.cpu().numpy(), td.cpu().numpy(), fi, fd,
+                        f"traversal {trav} order {order} vs default")
+    assert knn.knn_tree_errors(forest) == 0
     for t in range(ntrees):
         a, b = int(f.offsets[t]), int(f.offsets[t + 1])
         X = f.points[a:b]
@@ -101,29 +98,39 @@ def test_autotune_picks_a_listed_config(knn):
     assert {a["traversal"] for a in r["table"]} == {1, 2, 3}
 
 
-def test_forest_query_graph_replay(knn):
+@pytest.mark.parametrize("trav", [1, 2, 3])
+def test_forest_query_graph_replay(knn, trav):
     """The batched query captured once in a graph and replayed, with eager
     work and synchronization between replays, gives the eager result every
-    time."""
+    time -- for the lane-per-query forms (their grouping kernels, counting
+    sort and workspace included) and the wavefront form."""
     import torch
     f = inputs.forest(20, d=6, lo_exp=8.0, hi_exp=15.0, q_per_tree=256, seed=21)
-    log(f"[case] graph replay rows={len(f.points)}")
+    log(f"[case] graph replay rows={len(f.points)} traversal={trav}")
     forest = knn.knn_build_batch(dev(f.points), f.offsets, leaf_size=32)
     Q, T, S = dev(f.queries), dev(f.tree_ids), dev(f.self_ids)
     ei, ed = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S)
     torch.cuda.synchronize()
     ei, ed = ei.cpu().numpy(), ed.cpu().numpy()
+    bi, bd = [], []
+    for t in range(20):  # brute force over each query's own tree
+        a, b = int(f.offsets[t]), int(f.offsets[t + 1])
+        sel = np.flatnonzero(f.tree_ids == t)
+        ii, dd = oracle.bf32(f.points[a:b], f.queries[sel], f.k, self_ids=f.self_ids[sel] - a)
+        bi.append((sel, np.where(ii >= 0, ii + a, ii), dd))
+    for sel, ii, dd in bi:
+        assert_same(ei[sel], ed[sel], ii, dd, "eager vs brute force")
     oi = torch.empty((len(f.queries), f.k), dtype=torch.int32, device="cuda")
     od = torch.empty((len(f.queries), f.k), dtype=torch.float32, device="cuda")
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):  # warm up on the capture stream
-        knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, out=(oi, od))
+        knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, out=(oi, od), traversal=trav)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, out=(oi, od))
+        knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, out=(oi, od), traversal=trav)
     for rep in range(4):
         oi.fill_(-7)
         od.fill_(-7.0)
@@ -132,4 +139,39 @@ def test_forest_query_graph_replay(knn):
         torch.cuda.synchronize()
         assert_same(oi.cpu().numpy(), od.cpu().numpy(), ei, ed, f"replay {rep}")
     del g
+    forest.free()
+
+
+def test_out_of_range_tree_ids(knn):
+    """Tree ids outside [0, trees) read no node: those queries get padding
+    rows, the others their own tree's answer, in every traversal form and
+    order, and knn_tree_errors reports the count (then clears it)."""
+    import torch
+    f = inputs.forest(5, d=3, lo_exp=6.0, hi_exp=11.0, q_per_tree=40, seed=5)
+    log(f"[case] out-of-range tree ids rows={len(f.points)}")
+    forest = knn.knn_build_batch(dev(f.points), f.offsets, leaf_size=16)
+    ids = f.tree_ids.copy()
+    bad = np.arange(0, len(ids), 7)
+    ids[bad] = np.resize(np.array([-1, 5, 1000, -(2 ** 31), 2 ** 31 - 1], np.int32), len(bad))
+    good = np.setdiff1d(np.arange(len(ids)), bad)
+    ref = {}
+    for t in range(5):
+        a, b = int(f.offsets[t]), int(f.offsets[t + 1])
+        sel = good[f.tree_ids[good] == t]
+        ii, dd = oracle.bf32(f.points[a:b], f.queries[sel], f.k, self_ids=f.self_ids[sel] - a)
+        ref[t] = (sel, np.where(ii >= 0, ii + a, ii), dd)
+    Q, T, S = dev(f.queries), dev(ids), dev(f.self_ids)
+    for trav in (1, 2, 3):
+        for order in (0, 1):
+            gi, gd = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order,
+                                         traversal=trav)
+            torch.cuda.synchronize()
+            gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+            assert (gi[bad] == -1).all() and np.isinf(gd[bad]).all(), (trav, order)
+            for t, (sel, ii, dd) in ref.items():
+                assert_same(gi[sel], gd[sel], ii, dd, f"tree {t} traversal {trav} order {order}")
+            with pytest.raises(knn.KnnError) as e:
+                knn.knn_tree_errors(forest)
+            assert e.value.code == knn.KNN_EINVAL and f"{len(bad)} queries" in str(e.value)
+            assert knn.knn_tree_errors(forest) == 0  # cleared
     forest.free()

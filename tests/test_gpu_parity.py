@@ -47,8 +47,10 @@ def _full_check(knn, X, Q, k, leaf, self_ids=None, r2=np.inf, what="", subtree_p
     # small batches default to one wavefront per query: the lane-per-query
     # forms answer the same batch too
     for trav in (1, 2):
-        gi2, gd2, _ = gpu_knn(X, Q, k, self_ids=self_ids, r2=r2, tree=tree, traversal=trav)
-        assert_same(gi2, gd2, oi, od, what + f" (traversal {trav})")
+        for order in (0, 1):
+            gi2, gd2, _ = gpu_knn(X, Q, k, self_ids=self_ids, r2=r2, tree=tree, traversal=trav,
+                                  order=order)
+            assert_same(gi2, gd2, oi, od, what + f" (traversal {trav}, order {order})")
     tree.free()
 
 
@@ -212,11 +214,16 @@ def test_determinism_and_order_independence(knn):
         assert np.array_equal(e1[key], e2[key]), key
     assert_same(a_i, a_d, b_i, b_d, "repeat")
     p = np.random.default_rng(1).permutation(len(w.queries))
-    c_i, c_d, _ = gpu_knn(w.points, w.queries[p], w.k, self_ids=w.self_ids[p], tree=t1)
-    assert_same(c_i, c_d, a_i[p], a_d[p], "permuted queries")
     half = len(p) // 2
-    d_i, d_d, _ = gpu_knn(w.points, w.queries[:half], w.k, self_ids=w.self_ids[:half], tree=t1)
-    assert_same(d_i, d_d, a_i[:half], a_d[:half], "batch split")
+    for trav in (0, 1, 2, 3):  # every traversal form: order and batch do not matter
+        for order in ((0, 1) if trav in (1, 2) else (0,)):
+            what = f"traversal {trav} order {order}"
+            c_i, c_d, _ = gpu_knn(w.points, w.queries[p], w.k, self_ids=w.self_ids[p], tree=t1,
+                                  traversal=trav, order=order)
+            assert_same(c_i, c_d, a_i[p], a_d[p], "permuted queries, " + what)
+            d_i, d_d, _ = gpu_knn(w.points, w.queries[:half], w.k, self_ids=w.self_ids[:half],
+                                  tree=t1, traversal=trav, order=order)
+            assert_same(d_i, d_d, a_i[:half], a_d[:half], "batch split, " + what)
     # the leaf-batch knob only reschedules the traversal: identical results
     import torch
     Q, S = dev(w.queries), dev(w.self_ids)
@@ -265,6 +272,16 @@ def test_empty_and_degenerate_calls(knn):
         knn.knn_query(t, torch.from_numpy(X).cuda(), 65)
     with pytest.raises(knn.KnnError):
         knn.knn_build_ex(P, leaf_size=1, max_depth=1)  # depth above max_depth
+    # a NaN or infinite coordinate stops the build before any split is computed
+    for bad in (np.nan, np.inf, -np.inf):
+        Xb = np.tile(X, (300, 1))
+        Xb[1234, 1] = bad
+        with pytest.raises(knn.KnnError) as e:
+            knn.knn_build(torch.from_numpy(Xb).cuda(), 8)
+        assert e.value.code == knn.KNN_ENOTFINITE
+        with pytest.raises(knn.KnnError) as e:
+            knn.knn_build_batch(torch.from_numpy(Xb).cuda(), [0, 1000, len(Xb)])
+        assert e.value.code == knn.KNN_ENOTFINITE
     t.free()
     t1.free()
 
