@@ -183,6 +183,30 @@ int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
                  int32_t* out_idx, float* out_dist2, void* stream);
 
 /*
+ * knn_query_noalloc -- knn_query_ex that allocates nothing, for callers that
+ * cannot allocate device memory: code being captured into a graph, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments, result
+ * and errors as knn_query_ex.  Its workspace (the grouping of queries by home
+ * leaf) is a static device array of KNN_NOALLOC_WORKSPACE_BYTES that each
+ * device holds from the first call there until the process ends.
+ *   Workspace a call needs: none with order 1 or when one wavefront answers
+ *   each query (traversal 3, the default for batches of at most 16,384
+ *   queries); otherwise 4 (N + ceil(N / 4096)) + 12 m bytes with
+ *   N = floor(n / 2^s) + 1, s the smallest shift giving n / 2^s <= 2^22 (for
+ *   n >= 2^22, N is about 2^22: up to about 5.5 M queries fit).  A call that
+ *   needs more fails with KNN_EINVAL before anything is launched.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (the counters that must start at zero are cleared by a
+ * kernel of each call): calls that overlap on one device (other streams or
+ * threads) race and corrupt each other's results -- serialise them.
+ * knn_tree_free does not wait for these calls; the caller does.
+ */
+#define KNN_NOALLOC_WORKSPACE_BYTES (80ll << 20)
+int knn_query_noalloc(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+                      const int32_t* self_ids, float r2_max, const knn_query_params* p,
+                      int32_t* out_idx, float* out_dist2, void* stream);
+
+/*
  * knn_query_batch -- knn_query_ex on a forest: query i searches only tree
  * tree_ids[i] (device pointer [m] int32, each in [0, trees)).  All queries
  * run in one batch of launches whatever trees they address.  Indices are rows

@@ -60,7 +60,7 @@ class _Host(ctypes.Structure):
 
 _lib = None
 EXPORTED = ("knn_build", "knn_build_ex", "knn_build_batch", "knn_query", "knn_query_ex",
-            "knn_query_batch", "knn_query_radius", "knn_merge", "knn_classify", "knn_regress",
+            "knn_query_noalloc", "knn_query_batch", "knn_query_radius", "knn_merge", "knn_classify", "knn_regress",
             "knn_server_create",
             "knn_server_submit", "knn_server_wait", "knn_server_stats", "knn_server_destroy",
             "knn_tree_free", "knn_tree_errors", "knn_tree_info", "knn_tree_export",
@@ -87,6 +87,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(_QueryParams), vp, vp, vp]
     lib.knn_query_ex.argtypes = [vp, vp, i64, i32, vp, ctypes.c_float,
                                  ctypes.POINTER(_QueryParams), vp, vp, vp]
+    lib.knn_query_noalloc.argtypes = [vp, vp, i64, i32, vp, ctypes.c_float,
+                                      ctypes.POINTER(_QueryParams), vp, vp, vp]
     lib.knn_query_radius.argtypes = [vp, vp, i64, i32, vp, vp, ctypes.POINTER(_QueryParams), vp,
                                      vp, vp]
     lib.knn_merge.argtypes = [vp, vp, i32, vp, vp, i32, i64, i32, vp, vp, vp]
@@ -265,6 +267,27 @@ def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = mat
                             k, sp, ctypes.c_float(r2_max), ctypes.byref(p),
                             ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
                             _stream(queries)))
+    return idx, d2
+
+
+def knn_query_noalloc(tree: Tree, queries, k: int, self_ids=None, r2_max: float = math.inf,
+                      order: int = 0, out=None, leaf_batch: int = 0, traversal: int = 0):
+    """knn_query_ex on the library's static device workspace (the call
+    allocates no device memory; calls that overlap on one device race).
+    ``out`` (the result tensors) must be given: allocating them here would
+    defeat the purpose."""
+    lib = load_library()
+    _dev_f32(queries, "queries", tree.dim)
+    if out is None:
+        raise ValueError("knn_query_noalloc writes into caller tensors: pass out=(idx, d2)")
+    idx, d2 = _outputs(queries, k, out)
+    m = queries.shape[0]
+    sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
+    p = _QueryParams(order, leaf_batch, None, traversal)
+    _check(lib.knn_query_noalloc(tree.handle, ctypes.c_void_p(queries.data_ptr()), m, k, sp,
+                                 ctypes.c_float(r2_max), ctypes.byref(p),
+                                 ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                                 _stream(queries)))
     return idx, d2
 
 

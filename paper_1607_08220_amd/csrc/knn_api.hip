@@ -173,7 +173,8 @@ namespace {
 
 int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
                  const int32_t* self_ids, float r2_max, const float* r2s, const int32_t* roots,
-                 const knn_query_params* p, int32_t* out_idx, float* out_dist2, void* stream)
+                 const knn_query_params* p, int32_t* out_idx, float* out_dist2, void* stream,
+                 bool noalloc = false)
 {
     if (!t) return fail(KNN_EINVAL, "tree is NULL");
     if (m < 0) return fail(KNN_EINVAL, "m must be >= 0");
@@ -203,6 +204,10 @@ int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     qs.out_idx = out_idx;
     qs.out_d2 = out_dist2;
     qs.stats = p ? reinterpret_cast<unsigned long long*>(p->stats) : nullptr;
+    if (noalloc) {  // the device's static workspace instead of an allocation
+        const int rc = noalloc_workspace(&qs.ws, &qs.ws_bytes);
+        if (rc != KNN_OK) return rc;
+    }
     return query_tree(t, qs, static_cast<hipStream_t>(stream));
 }
 
@@ -215,6 +220,15 @@ int knn_query_ex(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     if (t && t->n_trees != 1) return fail(KNN_EINVAL, "a forest is queried with knn_query_batch");
     return query_common(t, queries, m, k, self_ids, r2_max, nullptr, nullptr, p, out_idx,
                         out_dist2, stream);
+}
+
+int knn_query_noalloc(const knn_tree* t, const float* queries, int64_t m, int32_t k,
+                      const int32_t* self_ids, float r2_max, const knn_query_params* p,
+                      int32_t* out_idx, float* out_dist2, void* stream)
+{
+    if (t && t->n_trees != 1) return fail(KNN_EINVAL, "a forest is queried with knn_query_batch");
+    return query_common(t, queries, m, k, self_ids, r2_max, nullptr, nullptr, p, out_idx,
+                        out_dist2, stream, true);
 }
 
 int knn_query_batch(const knn_tree* t, const float* queries, const int32_t* tree_ids,

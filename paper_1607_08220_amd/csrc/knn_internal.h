@@ -150,12 +150,19 @@ struct QuerySpec {
     int32_t* out_idx = nullptr;
     float* out_d2 = nullptr;
     unsigned long long* stats = nullptr;
+    // caller-provided device workspace: when set the query allocates nothing
+    // and fails with KNN_EINVAL before launching if it needs more than ws_bytes
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
 };
 
 int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t stream);
 // Record that `stream` has enqueued work reading the tree (skipped while the
 // stream is being captured into a graph).
 int note_tree_use(const knn_tree* t, hipStream_t stream);
+// Device address and size of knn_query_noalloc's static workspace on the
+// current device.
+int noalloc_workspace(void** ptr, size_t* bytes);
 int merge_lists(const int32_t* ia, const float* da, int ka, const int32_t* ib, const float* db,
                 int kb, int64_t m, int k, int32_t* oi, float* od, hipStream_t stream);
 

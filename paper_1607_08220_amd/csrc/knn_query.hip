@@ -983,7 +983,34 @@ struct StreamBuf {
     }
 };
 
+// Workspace of knn_query_noalloc: a file-scope device array, so that those
+// calls allocate nothing.  Each device holds its own copy from the first call
+// there until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in): it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+constexpr size_t kNoAllocBytes = size_t(KNN_NOALLOC_WORKSPACE_BYTES);
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 }  // namespace
+
+int noalloc_workspace(void** ptr, size_t* bytes)
+{
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    KNN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(KNN_EDEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {  // the current device is the one the call runs on
+        void* p = nullptr;
+        KNN_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kNoAllocBytes;
+    return KNN_OK;
+}
 
 namespace {
 
@@ -1088,8 +1115,19 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     const size_t bytes = sizeof(uint32_t) * (size_t)(N + nsb) + sizeof(int32_t) * 3 * (size_t)mg;
     StreamBuf ws;
     ws.s = st;
-    if (bytes) KNN_HIP(hipMallocAsync(&ws.p, bytes, st));
-    uint32_t* cnt = static_cast<uint32_t*>(ws.p);
+    void* base = nullptr;
+    if (bytes && qs.ws) {
+        if (bytes > qs.ws_bytes)
+            return fail(KNN_EINVAL, "the query needs " + std::to_string(bytes) +
+                                        " bytes of workspace, the static workspace holds " +
+                                        std::to_string(qs.ws_bytes) +
+                                        " (order 1 needs none)");
+        base = qs.ws;
+    } else if (bytes) {
+        KNN_HIP(hipMallocAsync(&ws.p, bytes, st));
+        base = ws.p;
+    }
+    uint32_t* cnt = static_cast<uint32_t*>(base);
     uint32_t* bsum = cnt + N;
     int32_t* home = reinterpret_cast<int32_t*>(bsum + nsb);
     int32_t* ord = home + mg;
@@ -1152,7 +1190,8 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     }
     KNN_HIP(hipGetLastError());
     prof_mark(st, 8);
-    return note_tree_use(t, st);
+    // (a call on the static workspace creates no event: the caller waits)
+    return qs.ws ? KNN_OK : note_tree_use(t, st);
 }
 
 }  // namespace knn
