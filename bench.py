@@ -33,20 +33,27 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def query_bytes_per_query(d: int, k: int, enter: float, pts: float) -> float:
-    """Algorithmic bytes one query moves: query row + self id + its slot in
-    the grouped order (order + home leaf) + output row (index + distance) +
-    every node entered from above (16-byte record + 2d-float box) + every
-    scanned bucket row (d coordinates + index)."""
-    return 4 * d + 4 + 8 + 8 * k + enter * (16 + 8 * d) + pts * 4 * (d + 1)
+def query_bytes_per_query(d: int, k: int, nodes: float, pts: float) -> float:
+    """Algorithmic bytes of one query (the query term of the measurement
+    contract): the query row (4d), the output row (8k: index + distance),
+    every node Algorithm 1 visits (8 bytes of split + an 8d-byte box) and
+    every scanned bucket point (d coordinates + its index).  `nodes` and `pts`
+    are mean visit counts per query."""
+    return 4 * d + 8 * k + nodes * (8 + 8 * d) + pts * 4 * (d + 1)
 
 
 def build_bytes_per_point(d: int, levels: int) -> float:
     """Algorithmic bytes per point of the build: ingest (read AoS, write SoA +
-    index), per level pass (histogram key read, count key read, partition read
-    and write of d coordinates + index), subtree finish (read d + index, write
-    the packed row of d + 1 words)."""
-    return (4 * d + 4 * d + 4) + levels * (4 + 4 + 8 * (d + 1)) + (4 * (d + 1) + 4 * (d + 1))
+    index), per level pass (histogram key read, then partition read and write
+    of d coordinates + index), subtree finish (read d coordinates + index,
+    write the packed row)."""
+    return (4 * d + 4 * d + 4) + levels * (4 + 8 * (d + 1)) + 8 * (d + 1)
+
+
+def build_floor_bytes_per_point(d: int) -> float:
+    """The least any build can move: read the input once, write the packed
+    rows (d coordinates + index) once."""
+    return 4 * d + 4 * (d + 1)
 
 
 def partition_bytes_per_point(d: int) -> float:
@@ -69,26 +76,34 @@ def measured_traffic(kernel_file: str, profile: str):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(X: np.ndarray, k: int, log2n: int, m: int, threads: int) -> dict:
+def oracle_leg(w, threads: int, gpu_idx, gpu_d2) -> dict:
+    """The oracle on the host: its kd-tree over all points (the top levels'
+    subtrees on `threads` threads) and Algorithm 1 for every query, timed;
+    every GPU result compared with it bit for bit; and the oracle's mean visit
+    counts per query (nodes popped, points scanned) for the roofline."""
     import oracle
-    rng = np.random.default_rng(7)
-    n = min(len(X), 1 << log2n)
-    sub = np.sort(rng.choice(len(X), n, replace=False)) if n < len(X) else np.arange(len(X))
-    Xs = np.ascontiguousarray(X[sub])
-    ids = rng.choice(n, m, replace=False).astype(np.int32)
+    m = len(w.queries)
     t0 = time.perf_counter()
-    T = oracle.build(Xs, 32)
+    T = oracle.build(w.points, w.leaf, nthreads=threads)
     tb = time.perf_counter() - t0
     t0 = time.perf_counter()
-    T.query(Xs[ids], k, self_ids=ids, nthreads=threads)
+    oi, od, st = T.query(w.queries, w.k, self_ids=w.self_ids, nthreads=threads, stats=True)
     tq = time.perf_counter() - t0
     T.close()
-    return {"value": m / tq, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle kd-tree on a random {n}-point subset of the same points "
-                      f"(build single-threaded {tb:.2f} s = {n / tb / 1e6:.2f} Mpts/s), "
-                      f"{m} queries from that subset, self excluded, k={k}, "
-                      f"{threads} threads ({tq:.2f} s)",
-            "build_mpts_per_s": n / tb / 1e6}
+    same = bool(np.array_equal(oi, gpu_idx) and np.array_equal(od.view(np.uint32),
+                                                               gpu_d2.view(np.uint32)))
+    nodes, leaves, pts = st.astype(np.float64).mean(0).tolist()
+    n = len(w.points)
+    return {"cpu_baseline": {"value": m / tq, "unit": "queries/s", "cores": threads,
+                             "kind": "oracle",
+                             "sample": f"the whole workload: oracle kd-tree over all {n} points "
+                                       f"({tb:.1f} s = {n / tb / 1e6:.2f} Mpts/s, top-level "
+                                       f"subtrees on {threads} threads), Algorithm 1 for all "
+                                       f"{m} queries, self excluded, k={w.k}, {threads} threads "
+                                       f"({tq:.2f} s)",
+                             "build_mpts_per_s": n / tb / 1e6, "build_s": tb, "query_s": tq},
+            "verified_all": same,
+            "oracle_visits": {"nodes": nodes, "leaves": leaves, "points": pts}}
 
 
 def bench_forest(knn, torch, dev) -> dict:
@@ -204,6 +219,96 @@ def bench_forest(knn, torch, dev) -> dict:
             "identical_to_per_call": same}
 
 
+def build_levels(n: int, subtree_points: int) -> int:
+    """Level passes of the build: halvings until a node fits one subtree."""
+    levels, c = 0, n
+    while c > subtree_points:
+        c = (c + 1) // 2
+        levels += 1
+    return levels
+
+
+def bench_plasma(knn, torch, dev, threads: int) -> dict:
+    """The plasma-like 4-D workload: n = 2^28 points, 2^24 queries drawn from
+    the data (self excluded), k = 16.  The bucket size is swept over
+    {8, 16, 32, 64}: each build + query timed (median of 3 after a warm-up),
+    the fastest step reported; the results of every bucket size must be
+    identical (the answer does not depend on the tree), and 64 sampled
+    queries equal brute force over all points."""
+    import oracle
+    from paper_1607_08220_amd import inputs
+    t0 = time.perf_counter()
+    w = inputs.workload("plasma_4d")
+    n, d = w.points.shape
+    m, k = len(w.queries), w.k
+    log(f"plasma: n={n} d={d} m={m} k={k} (generated in {time.perf_counter() - t0:.1f} s)")
+    P = torch.from_numpy(w.points).to(dev)
+    Q = torch.from_numpy(w.queries).to(dev)
+    S = torch.from_numpy(w.self_ids).to(dev)
+    idx = torch.empty((m, k), dtype=torch.int32, device=dev)
+    d2 = torch.empty((m, k), dtype=torch.float32, device=dev)
+    ref = None
+    same = True
+    sweep = []
+    for leaf in (8, 16, 32, 64):
+        runs = []
+        for rep in range(4):
+            tr = knn.knn_build(P, leaf)
+            pb = knn.knn_get_profile()
+            knn.knn_query_ex(tr, Q, k, self_ids=S, out=(idx, d2))
+            pq = knn.knn_get_profile()
+            if rep:
+                runs.append((pb["build_total"], pq["query_total"], pq["query_traverse"]))
+            if rep < 3:
+                tr.free()
+        info = tr.info()
+        stats = torch.zeros(knn.KNN_QUERY_STATS, dtype=torch.int64, device=dev)
+        knn.knn_query_ex(tr, Q, k, self_ids=S, stats=stats)
+        torch.cuda.synchronize()
+        tr.free()
+        st = stats.cpu().numpy().astype(np.float64) / m
+        if ref is None:
+            ref = (idx.clone(), d2.clone())
+        else:
+            same &= bool(torch.equal(idx, ref[0]) and torch.equal(d2.view(torch.int32),
+                                                                  ref[1].view(torch.int32)))
+        bms, qms, tms = (float(np.median([r[j] for r in runs])) for j in range(3))
+        levels = build_levels(n, info["subtree_points"])
+        bpp = build_bytes_per_point(d, levels)
+        bpq = query_bytes_per_query(d, k, st[0], st[2])
+        sweep.append({"leaf_size": leaf, "build_ms": bms, "query_ms": qms, "traverse_ms": tms,
+                      "build_mpts_per_s": n / (bms * 1e-3) / 1e6,
+                      "queries_per_s": m / (qms * 1e-3), "depth": info["depth"],
+                      "level_passes": levels,
+                      "build_frac": bpp * n / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "query_bytes_per_query": bpq,
+                      "traverse_frac": bpq * m / (tms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "nodes_entered": st[0], "points_scanned": st[2]})
+        log(f"plasma: leaf {leaf}: build {bms:.1f} ms ({n / bms / 1e3:.0f} Mpts/s), query "
+            f"{qms:.1f} ms ({m / qms / 1e3:.0f} Mq/s), depth {info['depth']}")
+    best = min(sweep, key=lambda r: r["build_ms"] + r["query_ms"])
+    pick = np.random.default_rng(11).choice(m, 64, replace=False)
+    bi, bd = oracle.bf32(w.points, w.queries[pick], k, self_ids=w.self_ids[pick], nthreads=threads)
+    gi, gd = ref[0].cpu().numpy()[pick], ref[1].cpu().numpy()[pick]
+    verified = bool(np.array_equal(bi, gi) and np.array_equal(bd.view(np.uint32),
+                                                               gd.view(np.uint32)))
+    log(f"plasma: best leaf {best['leaf_size']}; identical across leaves={same}; 64 sampled "
+        f"queries vs brute force: {'bit-exact' if verified else 'MISMATCH'}")
+    del P, Q, S, idx, d2, ref
+    torch.cuda.empty_cache()
+    return {"workload": "plasma_4d", "n_points": n, "dim": d, "n_queries": m, "k": k,
+            "queries": "data points, self excluded", "best_leaf_size": best["leaf_size"],
+            "build_mpts_per_s": best["build_mpts_per_s"], "queries_per_s": best["queries_per_s"],
+            "build_roofline": {"bound": "hbm", "frac": best["build_frac"],
+                               "bytes_per_point": build_bytes_per_point(d, best["level_passes"]),
+                               "level_passes": best["level_passes"]},
+            "query_roofline": {"kernel": "traversal", "bound": "hbm",
+                               "frac": best["traverse_frac"],
+                               "bytes_per_query": best["query_bytes_per_query"],
+                               "visits": "the kernel's own counters"},
+            "sweep": sweep, "identical_across_leaf_sizes": same, "verified_sample": verified}
+
+
 def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float) -> dict:
     """Serving: the resident clustered 3-D tree plus a 10-D correlated-Gaussian
     tree (n = 2^24); a Poisson stream of requests with sizes floor(2^(16u)),
@@ -219,13 +324,16 @@ def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float) -> di
     tree10 = knn.knn_build(torch.from_numpy(X10).to(dev), 32)
     data = [X3, X10]
     trees = [tree3, tree10]
-    # per-call service time: fixed cost + per-query cost for each (tree, k)
+    # per-call service time for each (tree, k), measured at batch sizes on
+    # both sides of the switch between traversal forms and interpolated
+    # piecewise-linearly in b
     cal = np.random.default_rng(7)
+    cal_b = (1, 4096, 16384, 16385, 65535)
     cost = {}
     for t in (0, 1):
         for k in (1, 5, 16, 32):
             times = []
-            for b in (1, 4096):
+            for b in cal_b:
                 ids = cal.integers(0, len(data[t]), size=b).astype(np.int32)
                 Q = torch.from_numpy(data[t][ids]).to(dev)
                 S = torch.from_numpy(ids).to(dev)
@@ -235,9 +343,9 @@ def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float) -> di
                 knn.knn_query_ex(trees[t], Q, k, self_ids=S)
                 torch.cuda.synchronize()
                 times.append(time.perf_counter() - a)
-            cost[(t, k)] = (times[0], max(times[1] - times[0], 0.0) / 4095)
-    mean_b = (2 ** 16 - 1) / (16 * np.log(2))  # E[2^(16u)]
-    mean_s = float(np.mean([o + mean_b * c for o, c in cost.values()]))
+            cost[(t, k)] = times
+    draws = np.floor(2 ** (16 * np.random.default_rng(8).random(200_000)))
+    mean_s = float(np.mean([np.interp(draws, cal_b, c).mean() for c in cost.values()]))
     rate = load / mean_s
     n_req = max(64, int(rate * seconds))
     rng = np.random.default_rng(2005)
@@ -307,7 +415,9 @@ def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float) -> di
         f"{pc['p99_ms']:.2f} {pc['queries_per_s'] / 1e6:.1f} Mq/s; identical={same}")
     return {"workload": "serve_cosmo3d_plus_gauss10d", "requests": n_req, "queries": nq,
             "rate_per_s": rate, "per_call_load": load,
-            "per_call_cost_ms": {f"tree{t}_k{k}": [o * 1e3, c * 1e3] for (t, k), (o, c) in cost.items()},
+            "per_call_cost_ms": {"batch_sizes": list(cal_b),
+                                 **{f"tree{t}_k{k}": [x * 1e3 for x in c]
+                                    for (t, k), c in cost.items()}},
             "server": srv, "per_call": pc, "identical_to_per_call": same}
 
 
@@ -322,6 +432,8 @@ def main() -> int:
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--skip-next", action="store_true",
                     help="skip the batched-forest and serving measurements")
+    ap.add_argument("--skip-plasma", action="store_true",
+                    help="skip the plasma-like 4-D workload (2^28 points)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the per-call loop's capacity")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
@@ -408,15 +520,9 @@ def main() -> int:
     enter, leaves, pts, steps, ins = (st[:5] / m).tolist()
     waves = (m + 63) // 64
     w_steps, w_rows, w_rounds, w_ins = (st[5:9] / waves).tolist()
-    bpq = query_bytes_per_query(d, k, enter, pts)
-    achieved = bpq * m / (trav_ms * 1e-3) / 1e9
-
-    levels = 0
-    c = n
-    while c > info["subtree_points"]:
-        c = (c + 1) // 2
-        levels += 1
+    levels = build_levels(n, info["subtree_points"])
     bpp = build_bytes_per_point(d, levels)
+    threads = min(16, len(os.sched_getaffinity(0)))
 
     verified = None
     if not args.no_verify:
@@ -424,12 +530,28 @@ def main() -> int:
         rng = np.random.default_rng(3)
         pick = rng.choice(m, 64, replace=False)
         bi, bd = oracle.bf32(w.points, w.queries[pick], k, self_ids=w.self_ids[pick],
-                             nthreads=min(16, len(os.sched_getaffinity(0))))
+                             nthreads=threads)
         gi, gd = idx.cpu().numpy()[pick], d2.cpu().numpy()[pick]
         verified = bool(np.array_equal(bi, gi) and np.array_equal(bd.view(np.uint32),
                                                                    gd.view(np.uint32)))
         log(f"64 sampled queries vs brute force over all {n} points: "
             f"{'bit-exact' if verified else 'MISMATCH'}")
+    leg = None
+    if not args.no_cpu_baseline:
+        log(f"the oracle on the host ({threads} threads): tree over all points, every query")
+        leg = oracle_leg(w, threads, idx.cpu().numpy(), d2.cpu().numpy())
+        cb = leg["cpu_baseline"]
+        log(f"oracle: build {cb['build_s']:.1f} s, {m} queries in {cb['query_s']:.2f} s; "
+            f"all GPU results equal the oracle's: {leg['verified_all']}")
+    # algorithmic bytes per query with the oracle's Algorithm 1 visit counts on
+    # the same tree (and, beside them, with this kernel's own counts)
+    bpq_kernel = query_bytes_per_query(d, k, enter, pts)
+    if leg:
+        ov = leg["oracle_visits"]
+        bpq, visits = query_bytes_per_query(d, k, ov["nodes"], ov["points"]), "oracle"
+    else:
+        bpq, visits = bpq_kernel, "kernel"
+    achieved = bpq * m / (trav_ms * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -460,6 +582,9 @@ def main() -> int:
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("knn_query.hip", "traffic_k_traverse_cosmo_clustered.json"),
                      "bytes_per_launch": bpq * m, "bytes_per_query": bpq,
+                     "visit_counts": visits,
+                     "oracle_visits_per_query": leg["oracle_visits"] if leg else None,
+                     "frac_with_kernel_counts": bpq_kernel * m / (trav_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "avg_launch_ms": trav_ms},
         "build_roofline": {"kernel": "k_scatter", "bound": "hbm",
                            "achieved": part_bytes / (part_avg_ms * 1e-3) / 1e9,
@@ -469,8 +594,12 @@ def main() -> int:
                            "bytes_per_launch": part_bytes, "avg_launch_ms": part_avg_ms,
                            "launches": part_launches,
                            "whole_build_bytes_per_point": bpp, "level_passes": levels,
-                           "whole_build_frac": bpp * n / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                           "whole_build_frac": bpp * n / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "floor_bytes_per_point": build_floor_bytes_per_point(d),
+                           "floor_frac": build_floor_bytes_per_point(d) * n
+                           / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "verified_sample": verified,
+        "verified_all_vs_oracle": leg["verified_all"] if leg else None,
         "paper_context": "PANDA: 189e9 points built in 48 s and 19e9 queries in 12 s on "
                          "~50,000 Xeon cores (2048 nodes); single node (24 cores): "
                          "cosmo_thin 50 M points built in 1.1 s, 5 M queries in 1.1 s",
@@ -484,16 +613,17 @@ def main() -> int:
         out["serving_overload"] = bench_serving(knn, torch, dev, trees[-1], w.points, 2.0,
                                                 args.serve_seconds * 0.75)
         trees[-1].free()
-        del P, Q, S
+        del P, Q, S, idx, d2
         torch.cuda.empty_cache()
         out["batched"] = bench_forest(knn, torch, dev)
     else:
         trees[-1].free()
-    if not args.no_cpu_baseline:
-        threads = min(16, len(os.sched_getaffinity(0)))
-        log(f"timing the oracle on the host ({threads} threads)")
-        out["cpu_baseline"] = cpu_baseline(w.points, k, 23 if args.scale >= 1 else 16,
-                                           1 << 21 if args.scale >= 1 else 4096, threads)
+        del P, Q, S, idx, d2
+        torch.cuda.empty_cache()
+    if leg:
+        out["cpu_baseline"] = leg["cpu_baseline"]
+    if not args.skip_plasma and args.scale >= 1:
+        out["plasma_4d"] = bench_plasma(knn, torch, dev, threads)
     print(json.dumps(out), flush=True)
     return 0
 

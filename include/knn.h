@@ -253,12 +253,12 @@ int knn_merge(const int32_t* idx_a, const float* dist2_a, int32_t ka, const int3
  * Serving: resident trees answer a stream of query requests with continuous
  * batching (the query batching of Section III-B, step 2, applied to a request
  * stream).  A server keeps the given trees (which the caller keeps alive)
- * and runs one worker thread: pending requests for the same tree and k are
- * packed into one batch, admitted when a stream is free and the batch's
- * device memory fits in the budget beside the batches already in flight, so
- * requests that arrive while others run join the next batch and batches on
- * different streams overlap.  Each query is answered exactly as by
- * knn_query_ex, so results do not depend on the mix.
+ * and runs one worker thread: pending requests for the same tree, of any k,
+ * are packed into one batch (each query keeps its own k), admitted when a
+ * stream is free and the batch's device memory fits in the budget beside the
+ * batches already in flight, so requests that arrive while others run join
+ * the next batch and batches on different streams overlap.  Each query is
+ * answered exactly as by knn_query_ex, so results do not depend on the mix.
  */
 typedef struct knn_server knn_server;
 
@@ -282,9 +282,13 @@ int knn_server_submit(knn_server* s, int32_t tree, const float* queries, int64_t
  * seen by the worker.  Each ticket is waited for once. */
 int knn_server_wait(knn_server* s, int64_t ticket, double* latency_ms);
 
-/* Counters: requests submitted, batches launched, queries answered, peak
- * device bytes held by batches in flight. */
-int knn_server_stats(knn_server* s, int64_t* out /* [4] */);
+/* Counters, out[KNN_SERVER_STATS]: 0 requests submitted, 1 batches
+ * launched, 2 queries answered, 3 peak device bytes held by batches in
+ * flight, 4 most requests in one batch, 5 most batches in flight at once,
+ * 6 most distinct k in one batch, 7 requests launched while an earlier batch
+ * was still on the device. */
+#define KNN_SERVER_STATS 8
+int knn_server_stats(knn_server* s, int64_t* out);
 
 /* Finish every queued request, stop the worker and free the server (not the
  * trees).  NULL is OK. */

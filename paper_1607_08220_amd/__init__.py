@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libknn.so")
 
 KNN_OK, KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH, KNN_ENOTFINITE = 0, -1, -2, -3, -4, -5
-KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES, KNN_QUERY_STATS = 16, 64, 12, 9
+KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES, KNN_QUERY_STATS, KNN_SERVER_STATS = 16, 64, 12, 9, 8
 PHASES = ("build_ingest", "build_levels", "build_finish", "build_compact", "build_total",
           "query_locate", "query_group", "query_traverse", "query_total",
           "build_partition_ms", "build_partition_launches", "build_partition_mpts")
@@ -400,9 +400,11 @@ class Server:
         return idx, d2, lat.value
 
     def stats(self) -> dict:
-        buf = (ctypes.c_int64 * 4)()
+        buf = (ctypes.c_int64 * KNN_SERVER_STATS)()
         _check(load_library().knn_server_stats(self._h, buf))
-        return dict(zip(("requests", "batches", "queries", "peak_bytes"), list(buf)))
+        return dict(zip(("requests", "batches", "queries", "peak_bytes", "max_requests_per_batch",
+                         "peak_batches_in_flight", "max_k_per_batch", "joined_while_running"),
+                        list(buf)))
 
     def close(self):
         if self._h and self._h.value:

@@ -1,6 +1,6 @@
 """Compile libknn.so (HIP, gfx950) in-tree.
 
-    python -m paper_1607_08220_amd.build
+    python -m paper_1607_08220_amd.build [--incremental]
 
 Every source is compiled with ``-ffp-contract=off`` (no fused multiply-add:
 the FP32 distance is defined with a separate multiply and add) and without
@@ -31,8 +31,16 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _newest_dependency(src: str) -> float:
+    deps = [os.path.join(CSRC, src), os.path.join(CSRC, "knn_internal.h"),
+            os.path.join(INCLUDE, "knn.h"), os.path.abspath(__file__)]
+    return max(os.path.getmtime(p) for p in deps)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(OBJ, src.replace(".hip", ".o"))
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_dependency(src):
+        return obj
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -44,10 +52,12 @@ def _compile(src: str) -> str:
     return obj
 
 
-def compile_library(out: str = LIB) -> str:
+def compile_library(out: str = LIB, incremental: bool = False) -> str:
+    """Compile every source (``incremental``: only those whose object is
+    older than the source or a shared header) and link the library."""
     os.makedirs(OBJ, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, incremental), SOURCES))
     tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,4 +68,4 @@ def compile_library(out: str = LIB) -> str:
 
 
 if __name__ == "__main__":
-    print(compile_library())
+    print(compile_library(incremental="--incremental" in sys.argv))

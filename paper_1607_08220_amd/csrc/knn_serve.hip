@@ -3,8 +3,10 @@
 // Requests (a query batch of any size against one resident tree, with its
 // own k) are queued by knn_server_submit from any host thread.  One worker
 // thread per server admits them while the device works on earlier ones:
-// pending requests for the same (tree, k) are packed into one batch of up to
-// kMaxBatchReqs requests and kMaxBatchQueries queries, provided the batch's
+// pending requests for the same tree, whatever their k, are packed into one
+// batch of up to kMaxBatchReqs requests and kMaxBatchQueries queries (each
+// query carries its own k and output offset into the traversal, whose heap
+// holds the batch's largest k), provided the batch's
 // device memory fits in what the HBM budget leaves beside the batches in
 // flight; each batch runs on one of the server's streams (gather the
 // requests' queries, the traversal of Algorithm 1, scatter the results into
@@ -44,48 +46,54 @@ double now_ms()
 struct ReqTable {
     int32_t n;
     int32_t d;
-    int32_t k;
+    int32_t k[kMaxBatchReqs];          // neighbours asked for by request r
     int64_t start[kMaxBatchReqs + 1];  // first query of request r in the batch; start[n] = total
+    int64_t ostart[kMaxBatchReqs + 1]; // first output entry of request r; ostart[n] = total
     const float* q[kMaxBatchReqs];
     const int32_t* self[kMaxBatchReqs];
     int32_t* oi[kMaxBatchReqs];
     float* od[kMaxBatchReqs];
 };
 
-__device__ inline int req_of(const ReqTable& T, int64_t i)
+// Largest r with off[r] <= i (off ascending, off[0] = 0).
+__device__ inline int req_of(const int64_t* off, int n, int64_t i)
 {
-    int lo = 0, hi = T.n - 1;  // largest r with start[r] <= i
+    int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (T.start[mid] <= i) lo = mid;
+        if (off[mid] <= i) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
 
 // Copy every request's queries (and self ids, -1 where none) into the
-// batch's contiguous staging arrays.
+// batch's contiguous staging arrays, with each query's k and the first entry
+// of its row in the batch's packed output.
 __global__ __launch_bounds__(kBlockS) void k_gather(ReqTable T, float* __restrict__ q,
-                                                    int32_t* __restrict__ self)
+                                                    int32_t* __restrict__ self,
+                                                    int32_t* __restrict__ qk,
+                                                    int64_t* __restrict__ qout)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= T.start[T.n]) return;
-    const int r = req_of(T, i);
+    const int r = req_of(T.start, T.n, i);
     const int64_t j = i - T.start[r];
     for (int t = 0; t < T.d; ++t) q[i * T.d + t] = T.q[r][j * T.d + t];
     self[i] = T.self[r] ? T.self[r][j] : -1;
+    qk[i] = T.k[r];
+    qout[i] = T.ostart[r] + j * T.k[r];
 }
 
-// Copy the batch's results into each request's own output buffers.
+// Copy the batch's packed results into each request's own output buffers.
 __global__ __launch_bounds__(kBlockS) void k_scatter_results(ReqTable T,
                                                              const int32_t* __restrict__ oi,
                                                              const float* __restrict__ od)
 {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= T.start[T.n] * T.k) return;
-    const int64_t i = e / T.k;
-    const int r = req_of(T, i);
-    const int64_t o = (i - T.start[r]) * T.k + e % T.k;
+    if (e >= T.ostart[T.n]) return;
+    const int r = req_of(T.ostart, T.n, e);
+    const int64_t o = e - T.ostart[r];
     T.oi[r][o] = oi[e];
     T.od[r][o] = od[e];
 }
@@ -108,6 +116,9 @@ struct Batch {
     hipEvent_t done = nullptr;
     void* mem = nullptr;
     size_t bytes = 0;
+    int32_t kmax = 1;
+    int64_t queries = 0;
+    int64_t outputs = 0;  // sum over requests of m * k
     std::vector<Request*> reqs;
     int status = KNN_OK;
 };
@@ -129,19 +140,22 @@ struct knn_server {
     bool stop = false;
     std::vector<Batch> inflight;
     int64_t inflight_bytes = 0;
-    // counters
+    // counters (knn_server_stats)
     int64_t n_batches = 0, n_queries = 0, n_requests = 0;
     int64_t peak_bytes = 0;
+    int64_t max_reqs_per_batch = 0, peak_inflight = 0, max_k_kinds = 0;
+    int64_t joined_running = 0;  // requests launched while an earlier batch was on the device
 };
 
 namespace {
 
-// Device bytes a batch of `total` queries of dimension d and k needs:
-// staging for queries, self ids and results, plus the grouping workspace of
-// the query path when it runs.
-size_t batch_bytes(const knn_tree* t, int64_t total, int k)
+// Device bytes a batch needs: staging for its queries, self ids, per-query
+// k and output offsets, and results, plus the grouping workspace of the
+// query path when it runs.
+size_t batch_bytes(const knn_tree* t, int64_t total, int64_t outputs)
 {
-    size_t b = (size_t)total * (sizeof(float) * t->d + sizeof(int32_t) + (size_t)k * 8);
+    size_t b = (size_t)total * (sizeof(float) * t->d + sizeof(int32_t) * 2 + sizeof(int64_t)) +
+               (size_t)outputs * 8;
     if (total >= kGroupMin) {
         int shift = 0;
         while ((t->n >> shift) > (int64_t(1) << 22)) ++shift;
@@ -153,36 +167,46 @@ size_t batch_bytes(const knn_tree* t, int64_t total, int k)
 int launch_batch(knn_server* s, Batch& b)
 {
     const knn_tree* t = s->trees[b.reqs[0]->tree];
-    const int k = b.reqs[0]->k, d = t->d;
+    const int d = t->d;
     ReqTable T{};
     T.n = (int32_t)b.reqs.size();
     T.d = d;
-    T.k = k;
-    int64_t total = 0;
+    int64_t total = 0, outs = 0;
     for (int r = 0; r < T.n; ++r) {
         const Request* q = b.reqs[r];
         T.start[r] = total;
+        T.ostart[r] = outs;
+        T.k[r] = q->k;
         T.q[r] = q->q;
         T.self[r] = q->self;
         T.oi[r] = q->oi;
         T.od[r] = q->od;
         total += q->m;
+        outs += q->m * q->k;
     }
     T.start[T.n] = total;
-    const size_t qb = sizeof(float) * total * d, sb = sizeof(int32_t) * total;
-    const size_t ob = sizeof(int32_t) * total * k;
-    KNN_HIP(hipMallocAsync(&b.mem, qb + sb + 2 * ob, b.stream));
-    float* q = static_cast<float*>(b.mem);
-    int32_t* self = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(b.mem) + qb);
-    int32_t* oi = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(b.mem) + qb + sb);
-    float* od = reinterpret_cast<float*>(reinterpret_cast<char*>(b.mem) + qb + sb + ob);
+    T.ostart[T.n] = outs;
+    // staging: qout [total] int64, q [total][d], self [total], qk [total],
+    // oi [outs], od [outs] (8-byte array first)
+    const size_t b_qout = sizeof(int64_t) * total, b_q = sizeof(float) * total * d;
+    const size_t b_i = sizeof(int32_t) * total, b_o = sizeof(int32_t) * outs;
+    KNN_HIP(hipMallocAsync(&b.mem, b_qout + b_q + 2 * b_i + 2 * b_o, b.stream));
+    char* base = static_cast<char*>(b.mem);
+    int64_t* qout = reinterpret_cast<int64_t*>(base);
+    float* q = reinterpret_cast<float*>(base + b_qout);
+    int32_t* self = reinterpret_cast<int32_t*>(base + b_qout + b_q);
+    int32_t* qk = reinterpret_cast<int32_t*>(base + b_qout + b_q + b_i);
+    int32_t* oi = reinterpret_cast<int32_t*>(base + b_qout + b_q + 2 * b_i);
+    float* od = reinterpret_cast<float*>(base + b_qout + b_q + 2 * b_i + b_o);
     const unsigned g1 = (unsigned)((total + kBlockS - 1) / kBlockS);
-    k_gather<<<g1, kBlockS, 0, b.stream>>>(T, q, self);
+    k_gather<<<g1, kBlockS, 0, b.stream>>>(T, q, self, qk, qout);
     KNN_HIP(hipGetLastError());
     knn::QuerySpec qs;
     qs.queries = q;
     qs.m = total;
-    qs.k = k;
+    qs.k = b.kmax;
+    qs.qk = qk;
+    qs.qout = qout;
     qs.self_ids = self;
     qs.order = total >= kGroupMin ? 0 : 1;
     qs.batch = knn::kDefaultLeafBatch;
@@ -190,7 +214,7 @@ int launch_batch(knn_server* s, Batch& b)
     qs.out_d2 = od;
     const int rc = knn::query_tree(t, qs, b.stream);
     if (rc != KNN_OK) return rc;
-    const unsigned g2 = (unsigned)((total * k + kBlockS - 1) / kBlockS);
+    const unsigned g2 = (unsigned)((outs + kBlockS - 1) / kBlockS);
     k_scatter_results<<<g2, kBlockS, 0, b.stream>>>(T, oi, od);
     KNN_HIP(hipGetLastError());
     KNN_HIP(hipFreeAsync(b.mem, b.stream));
@@ -240,18 +264,22 @@ void worker_loop(knn_server* s)
             const knn_tree* t = s->trees[head->tree];
             Batch b;
             int64_t total = 0;
+            uint64_t kinds = 0;  // bit k-1: some request asks for k neighbours
             for (auto it = s->pending.begin(); it != s->pending.end() && (int)b.reqs.size() < kMaxBatchReqs;) {
                 Request* r = *it;
-                if (r->tree == head->tree && r->k == head->k &&
-                    (b.reqs.empty() || total + r->m <= kMaxBatchQueries)) {
+                if (r->tree == head->tree && (b.reqs.empty() || total + r->m <= kMaxBatchQueries)) {
                     b.reqs.push_back(r);
                     total += r->m;
+                    b.outputs += r->m * r->k;
+                    b.kmax = std::max(b.kmax, r->k);
+                    kinds |= uint64_t(1) << (r->k - 1);
                     it = s->pending.erase(it);
                 } else {
                     ++it;
                 }
             }
-            b.bytes = batch_bytes(t, total, head->k);
+            b.queries = total;
+            b.bytes = batch_bytes(t, total, b.outputs);
             if (!s->inflight.empty() && s->inflight_bytes + (int64_t)b.bytes > s->budget) {
                 // not enough memory beside the batches in flight: wait for one to retire
                 for (auto it = b.reqs.rbegin(); it != b.reqs.rend(); ++it) s->pending.push_front(*it);
@@ -266,7 +294,11 @@ void worker_loop(knn_server* s)
             s->peak_bytes = std::max(s->peak_bytes, s->inflight_bytes);
             ++s->n_batches;
             s->n_queries += total;
+            s->max_reqs_per_batch = std::max<int64_t>(s->max_reqs_per_batch, (int64_t)b.reqs.size());
+            s->max_k_kinds = std::max<int64_t>(s->max_k_kinds, __builtin_popcountll(kinds));
+            if (!s->inflight.empty()) s->joined_running += (int64_t)b.reqs.size();
             s->inflight.push_back(std::move(b));
+            s->peak_inflight = std::max<int64_t>(s->peak_inflight, (int64_t)s->inflight.size());
         }
         if (s->stop && s->pending.empty() && s->inflight.empty()) break;
         if (s->inflight.empty()) {
@@ -370,7 +402,7 @@ int knn_server_wait(knn_server* s, int64_t ticket, double* latency_ms)
     return st == KNN_OK ? KNN_OK : knn::fail(st, "the request's batch failed on the device");
 }
 
-int knn_server_stats(knn_server* s, int64_t* out /* [4] */)
+int knn_server_stats(knn_server* s, int64_t* out /* [KNN_SERVER_STATS] */)
 {
     if (!s || !out) return knn::fail(KNN_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
@@ -378,6 +410,10 @@ int knn_server_stats(knn_server* s, int64_t* out /* [4] */)
     out[1] = s->n_batches;
     out[2] = s->n_queries;
     out[3] = s->peak_bytes;
+    out[4] = s->max_reqs_per_batch;
+    out[5] = s->peak_inflight;
+    out[6] = s->max_k_kinds;
+    out[7] = s->joined_running;
     return KNN_OK;
 }
 
