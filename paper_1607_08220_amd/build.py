@@ -19,7 +19,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libknn.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["knn_api.hip", "knn_build.hip", "knn_query.hip", "knn_serve.hip", "knn_classify.hip"]
+SOURCES = ["knn_api.hip", "knn_build.hip", "knn_query.hip", "knn_trav_lane1.hip",
+           "knn_trav_lane2.hip", "knn_trav_stack1.hip", "knn_trav_stack2.hip", "knn_serve.hip",
+           "knn_classify.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KNN_OFFLOAD_ARCH", "gfx950")
@@ -34,6 +36,8 @@ FLAGS = [
 def _newest_dependency(src: str) -> float:
     deps = [os.path.join(CSRC, src), os.path.join(CSRC, "knn_internal.h"),
             os.path.join(INCLUDE, "knn.h"), os.path.abspath(__file__)]
+    if '#include "knn_traverse.h"' in open(deps[0]).read():
+        deps.append(os.path.join(CSRC, "knn_traverse.h"))
     return max(os.path.getmtime(p) for p in deps)
 
 

@@ -1974,11 +1974,16 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
 {
     prof_mark(st, 0);
     prof_part_begin();
-    {   // let the pool keep build scratch between builds (up to 64 GiB)
+    {   // let the pool keep build scratch between builds, up to half the
+        // device's memory: a 2^28-point 4-D build touches about 40 GiB, and
+        // memory handed back at every synchronisation has to be mapped again
+        // by the next build
         int dev = 0;
         hipMemPool_t pool;
-        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t keep = uint64_t(64) << 30;
+        size_t free_b = 0, total_b = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess &&
+            hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+            uint64_t keep = std::max<uint64_t>(uint64_t(total_b) / 2, uint64_t(64) << 30);
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
         }
     }
