@@ -1,5 +1,7 @@
 """CPU tests of the oracle against its pins, and proof that the pins catch
 plausible mistakes planted in the oracle (compiled variants, CPU only)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -83,3 +85,25 @@ def test_vote_regress_merge_hand_examples():
     ib = np.array([[5, 7]], np.int32); db = np.array([[2.0, 2.0]], np.float32)
     oi, od = oracle.merge(ia, da, ib, db, 4)
     assert oi.tolist() == [[3, 5, 7, -1]] and od[0, :3].tolist() == [1.0, 2.0, 2.0]
+
+
+def test_oracle_under_address_and_undefined_sanitizers(tmp_path):
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc, host code only) runs every entry point on small random, integer and
+    constant inputs without a report, and its answers still check out."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "oracle_sanitize")
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-pthread",
+           os.path.join(here, "oracle_sanitize_main.c"),
+           os.path.join(os.path.dirname(here), "oracle", "oracle.c"), "-o", exe, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ok: 0 failing cases" in r.stdout and "runtime error" not in r.stderr, r.stderr
