@@ -130,19 +130,20 @@ def bench_forest(knn, torch, dev) -> dict:
     a = time.perf_counter()
     tuned = autotune.tune(P[:int(f.offsets[ns])], Q[sel].contiguous(), f.k,
                           self_ids=S[sel].contiguous(), offsets=f.offsets[:ns + 1],
-                          tree_ids=T[sel].contiguous(), traversals=(1, 2), reps=2)
+                          tree_ids=T[sel].contiguous(), traversals=(1, 2, (4, 16), (4, 32)),
+                          reps=2)
     log(f"forest: autotuned on {ns} trees in {time.perf_counter() - a:.1f} s: leaf "
         f"{tuned['leaf_size']}, leaf batch {tuned['leaf_batch']}, order {tuned['order']}, "
-        f"traversal {tuned['traversal']}")
-    leaf, lb, order, trav = (tuned["leaf_size"], tuned["leaf_batch"], tuned["order"],
-                             tuned["traversal"])
+        f"traversal {tuned['traversal']} (team {tuned['team_lanes']})")
+    leaf, lb, order, trav, team = (tuned["leaf_size"], tuned["leaf_batch"], tuned["order"],
+                                   tuned["traversal"], tuned["team_lanes"])
 
     def batched():
         a = time.perf_counter()
         forest = knn.knn_build_batch(P, f.offsets, leaf_size=leaf)
         b = time.perf_counter()
         idx, d2 = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
-                                      traversal=trav)
+                                      traversal=trav, team_lanes=team)
         torch.cuda.synchronize()
         c = time.perf_counter()
         forest.free()
@@ -162,13 +163,13 @@ def bench_forest(knn, torch, dev) -> dict:
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
-                            traversal=trav, out=(gi_t, gd_t))
+                            traversal=trav, team_lanes=team, out=(gi_t, gd_t))
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
-                            traversal=trav, out=(gi_t, gd_t))
+                            traversal=trav, team_lanes=team, out=(gi_t, gd_t))
     reps = []
     graph_same = True
     for _ in range(5):
@@ -195,7 +196,7 @@ def bench_forest(knn, torch, dev) -> dict:
     for t in range(len(f.offsets) - 1):
         tr = knn.knn_build(P[int(f.offsets[t]):int(f.offsets[t + 1])], leaf)
         outs.append(knn.knn_query_ex(tr, Qt[t], f.k, self_ids=St[t], order=order, leaf_batch=lb,
-                                     traversal=trav))
+                                     traversal=trav, team_lanes=team))
         tr.free()
     torch.cuda.synchronize()
     per_call = (time.perf_counter() - a) * 1e3
@@ -211,7 +212,7 @@ def bench_forest(knn, torch, dev) -> dict:
         f"identical={graph_same}); per call {per_call:.0f} ms; identical={same}")
     return {"workload": "forest512_6d", "trees": len(f.offsets) - 1, "points": n, "queries": m,
             "k": f.k, "autotuned": {"leaf_size": leaf, "leaf_batch": lb, "order": order,
-                                    "traversal": trav},
+                                    "traversal": trav, "team_lanes": team},
             "batched_build_ms": bb, "batched_query_ms": bq, "graph_replay_query_ms": bqg,
             "graph_replay_identical": graph_same,
             "batched_ms": bb + bq, "per_call_ms": per_call, "speedup": per_call / (bb + bq),
@@ -258,7 +259,9 @@ def bench_plasma(knn, torch, dev, threads: int) -> dict:
             knn.knn_query_ex(tr, Q, k, self_ids=S, out=(idx, d2))
             pq = knn.knn_get_profile()
             if rep:
-                runs.append((pb["build_total"], pq["query_total"], pq["query_traverse"]))
+                runs.append((pb["build_total"], pq["query_total"], pq["query_traverse"],
+                             pb["build_ingest"], pb["build_levels"], pb["build_finish"],
+                             pb["build_compact"]))
             if rep < 3:
                 tr.free()
         info = tr.info()
@@ -272,7 +275,8 @@ def bench_plasma(knn, torch, dev, threads: int) -> dict:
         else:
             same &= bool(torch.equal(idx, ref[0]) and torch.equal(d2.view(torch.int32),
                                                                   ref[1].view(torch.int32)))
-        bms, qms, tms = (float(np.median([r[j] for r in runs])) for j in range(3))
+        bms, qms, tms, b_in, b_lv, b_fi, b_co = (float(np.median([r[j] for r in runs]))
+                                                 for j in range(7))
         levels = build_levels(n, info["subtree_points"])
         bpp = build_bytes_per_point(d, levels)
         bpq = query_bytes_per_query(d, k, st[0], st[2])
@@ -283,8 +287,11 @@ def bench_plasma(knn, torch, dev, threads: int) -> dict:
                       "build_frac": bpp * n / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                       "query_bytes_per_query": bpq,
                       "traverse_frac": bpq * m / (tms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                      "nodes_entered": st[0], "points_scanned": st[2]})
-        log(f"plasma: leaf {leaf}: build {bms:.1f} ms ({n / bms / 1e3:.0f} Mpts/s), query "
+                      "nodes_entered": st[0], "points_scanned": st[2],
+                      "build_phases_ms": {"ingest": b_in, "levels": b_lv, "finish": b_fi,
+                                          "compact": b_co}})
+        log(f"plasma: leaf {leaf}: build {bms:.1f} ms ({n / bms / 1e3:.0f} Mpts/s; ingest "
+            f"{b_in:.1f}, levels {b_lv:.1f}, finish {b_fi:.1f}, compact {b_co:.1f}), query "
             f"{qms:.1f} ms ({m / qms / 1e3:.0f} Mq/s), depth {info['depth']}")
     best = min(sweep, key=lambda r: r["build_ms"] + r["query_ms"])
     pick = np.random.default_rng(11).choice(m, 64, replace=False)
@@ -309,7 +316,8 @@ def bench_plasma(knn, torch, dev, threads: int) -> dict:
             "sweep": sweep, "identical_across_leaf_sizes": same, "verified_sample": verified}
 
 
-def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float) -> dict:
+def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float,
+                  slot_kwargs=None, legs=("slots", "batches", "per_call")) -> dict:
     """Serving: the resident clustered 3-D tree plus a 10-D correlated-Gaussian
     tree (n = 2^24); a Poisson stream of requests with sizes floor(2^(16u)),
     k from {1, 5, 16, 32}, a tree chosen uniformly and queries drawn from that
@@ -365,34 +373,45 @@ def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float) -> di
     log(f"serving: {n_req} requests, {nq} queries, rate {rate:.1f}/s for per-call load {load} "
         f"(prepared in {time.perf_counter() - t0:.1f} s)")
 
-    # continuous batching server
-    server = knn.Server(trees)
-    lat = np.zeros(n_req)
-    lag = np.zeros(n_req)
-    tickets = [0] * n_req
-    start = time.perf_counter() + 0.05
+    def serve(slot_max):
+        """The server on the stream: slot kernels for the requests of at most
+        slot_max queries (0: batches only, the default)."""
+        server = knn.Server(trees, slot_max_queries=slot_max, **(slot_kwargs or {}))
+        lat = np.zeros(n_req)
+        lag = np.zeros(n_req)
+        tickets = [0] * n_req
+        start = time.perf_counter() + 0.05
 
-    def submitter():
-        for i, (t, Q, S, k, oi, od) in enumerate(reqs):
-            due = start + arrivals[i]
-            while time.perf_counter() < due:
-                pass
-            lag[i] = time.perf_counter() - due
-            tickets[i] = server.submit(t, Q, k, self_ids=S, out=(oi, od))
+        def submitter():
+            for i, (t, Q, S, k, oi, od) in enumerate(reqs):
+                due = start + arrivals[i]
+                while time.perf_counter() < due:
+                    pass
+                lag[i] = time.perf_counter() - due
+                tickets[i] = server.submit(t, Q, k, self_ids=S, out=(oi, od))
 
-    th = threading.Thread(target=submitter)
-    th.start()
-    th.join()
-    for i in range(n_req):
-        _, _, ms = server.wait(tickets[i])
-        lat[i] = lag[i] * 1e3 + ms
-    end = max(start + arrivals[i] + lat[i] * 1e-3 for i in range(n_req))
-    st = server.stats()
-    server.close()
-    served = [(r[4].clone(), r[5].clone()) for r in reqs]
-    srv = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-           "queries_per_s": nq / (end - start), "batches": st["batches"],
-           "peak_batch_bytes": st["peak_bytes"]}
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        for i in range(n_req):
+            _, _, ms = server.wait(tickets[i])
+            lat[i] = lag[i] * 1e3 + ms
+        end = max(start + arrivals[i] + lat[i] * 1e-3 for i in range(n_req))
+        st = server.stats()
+        server.close()
+        served = [(r[4].clone(), r[5].clone()) for r in reqs]
+        small = lat[[r[1].shape[0] <= 4096 for r in reqs]]
+        return served, {"p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99)),
+                        "p50_ms_requests_to_4096": float(np.percentile(small, 50)),
+                        "p99_ms_requests_to_4096": float(np.percentile(small, 99)),
+                        "queries_per_s": nq / (end - start), "stats": st}
+
+    served, srv = serve(0) if "batches" in legs else (None, None)
+    served_s, srv_s = serve(4096) if "slots" in legs else (None, None)
+    if "per_call" not in legs:
+        tree10.free()
+        return {"server": srv, "server_slot_kernels": srv_s}
 
     # per-call baseline on the same arrivals
     lat_pc = np.zeros(n_req)
@@ -406,15 +425,21 @@ def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float) -> di
         lat_pc[i] = (time.perf_counter() - due) * 1e3
     end = max(start + arrivals[i] + lat_pc[i] * 1e-3 for i in range(n_req))
     same = all(torch.equal(a[0], r[4]) and torch.equal(a[1].view(torch.int32), r[5].view(torch.int32))
-               for a, r in zip(served, reqs))
+               and torch.equal(b[0], r[4]) and torch.equal(b[1].view(torch.int32), r[5].view(torch.int32))
+               for a, b, r in zip(served, served_s, reqs))
     tree10.free()
+    small = lat_pc[[r[1].shape[0] <= 4096 for r in reqs]]
     pc = {"p50_ms": float(np.percentile(lat_pc, 50)), "p99_ms": float(np.percentile(lat_pc, 99)),
+          "p50_ms_requests_to_4096": float(np.percentile(small, 50)),
+          "p99_ms_requests_to_4096": float(np.percentile(small, 99)),
           "queries_per_s": nq / (end - start)}
-    log(f"serving: server p50 {srv['p50_ms']:.2f} ms p99 {srv['p99_ms']:.2f} ms "
-        f"{srv['queries_per_s'] / 1e6:.1f} Mq/s; per call p50 {pc['p50_ms']:.2f} p99 "
-        f"{pc['p99_ms']:.2f} {pc['queries_per_s'] / 1e6:.1f} Mq/s; identical={same}")
+    log(f"serving: batches p50 {srv['p50_ms']:.2f} ms p99 {srv['p99_ms']:.2f} ms "
+        f"{srv['queries_per_s'] / 1e6:.1f} Mq/s; slot kernels p50 {srv_s['p50_ms']:.2f} p99 "
+        f"{srv_s['p99_ms']:.2f} {srv_s['queries_per_s'] / 1e6:.1f} Mq/s; per call p50 "
+        f"{pc['p50_ms']:.2f} p99 {pc['p99_ms']:.2f} {pc['queries_per_s'] / 1e6:.1f} Mq/s; "
+        f"identical={same}")
     return {"workload": "serve_cosmo3d_plus_gauss10d", "requests": n_req, "queries": nq,
-            "rate_per_s": rate, "per_call_load": load,
+            "rate_per_s": rate, "per_call_load": load, "server_slot_kernels": srv_s,
             "per_call_cost_ms": {"batch_sizes": list(cal_b),
                                  **{f"tree{t}_k{k}": [x * 1e3 for x in c]
                                     for (t, k), c in cost.items()}},

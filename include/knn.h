@@ -71,15 +71,20 @@ typedef struct {
                        steps, 4 heap inserts; summed over wavefronts (64 queries):
                        5 traversal-loop iterations, 6 bucket-row batches, 7 leaf
                        rounds, 8 heap-insert executions */
-    int32_t traversal; /* 0 (default): form 3 for batches of at most 16,384 queries, else
-                          1 below 5 dimensions and 2 from 5; 1: stack-free walk from the
+    int32_t traversal; /* 0 (default): below 5 dimensions form 3 for batches of at most
+                          16,384 queries, else 1; from 5 dimensions form 3 up to 4,096
+                          queries, form 4 with 32 lanes up to 32,768 (where k and the
+                          depth fit), else 2; 1: stack-free walk from the
                           query's home leaf (each node keeps its parent); 2: Algorithm 1's
                           explicit stack, kept in LDS (used when the tree's depth fits);
                           3: Algorithm 1's explicit stack with one wavefront per query
                           (used when the tree is at most 63 levels deep and stats is
                           NULL; for deep searches answered with few queries);
+                          4: the same with a team of team_lanes lanes per query (used
+                          when k <= team_lanes, the tree is at most team_lanes - 1
+                          levels deep and stats is NULL, else as 0);
                           a scheduling knob, the result does not depend on it */
-    int32_t pad2_;
+    int32_t team_lanes; /* traversal 4: lanes per query, 8, 16 or 32 (0 = 32) */
 } knn_query_params;
 
 typedef struct {
@@ -262,10 +267,32 @@ int knn_merge(const int32_t* idx_a, const float* dist2_a, int32_t ka, const int3
  */
 typedef struct knn_server knn_server;
 
-/* trees: host array of ntrees (>= 1) single trees on one device;
- * hbm_budget_bytes: device memory the batches in flight may hold (0 = 4 GiB;
- * a batch larger than the budget still runs when nothing else is in
- * flight); streams: concurrent batches, 1..64 (0 = 4). */
+/* Server parameters; zero selects the default. */
+typedef struct {
+    int64_t hbm_budget_bytes; /* device memory the batches in flight may hold (0 = 4 GiB; a
+                                 batch larger than the budget still runs when nothing else is
+                                 in flight) */
+    int32_t streams;          /* concurrent batches, 1..64 (0 = 4) */
+    int32_t slot_max_queries; /* 0 (default): every request forms batches; n > 0: requests
+                                 of at most min(n, 16384) queries are answered by the tree's
+                                 slot kernel instead -- a persistent launch whose wavefronts
+                                 take each new request over while it runs and answer its
+                                 queries one wavefront per query, the request with the fewest
+                                 queries left first; a launch stops admitting after 20 ms and
+                                 ends when idle (the worker relaunches it), so it never holds
+                                 a hardware queue long */
+    int32_t slot_workgroups_per_cu; /* a slot kernel's workgroups of four wavefronts per
+                                       compute unit, 1..8 (0 = 1) */
+    int32_t slot_idle_us;     /* a slot kernel with nothing to do ends after this many
+                                 microseconds (0 = 2000) */
+} knn_server_params;
+
+/* trees: host array of ntrees (>= 1) single trees on one device (each at
+ * most 63 levels deep); p may be NULL for the defaults. */
+int knn_server_create_ex(const knn_tree* const* trees, int32_t ntrees, const knn_server_params* p,
+                         knn_server** out);
+
+/* knn_server_create_ex with the given budget and stream count (batches only). */
 int knn_server_create(const knn_tree* const* trees, int32_t ntrees, int64_t hbm_budget_bytes,
                       int32_t streams, knn_server** out);
 
@@ -285,9 +312,11 @@ int knn_server_wait(knn_server* s, int64_t ticket, double* latency_ms);
 /* Counters, out[KNN_SERVER_STATS]: 0 requests submitted, 1 batches
  * launched, 2 queries answered, 3 peak device bytes held by batches in
  * flight, 4 most requests in one batch, 5 most batches in flight at once,
- * 6 most distinct k in one batch, 7 requests launched while an earlier batch
- * was still on the device. */
-#define KNN_SERVER_STATS 8
+ * 6 most distinct k in one batch, 7 requests admitted while earlier work was
+ * on the device (a batch launched beside another, or a request posted to a
+ * running slot kernel), 8 requests answered by slot kernels, 9 slot-kernel
+ * launches. */
+#define KNN_SERVER_STATS 10
 int knn_server_stats(knn_server* s, int64_t* out);
 
 /* Finish every queued request, stop the worker and free the server (not the
@@ -339,6 +368,14 @@ int knn_tree_info(const knn_tree* t, knn_tree_info_t* info);
 
 /* Copy the tree to host arrays (synchronous); used to check its invariants. */
 int knn_tree_export(const knn_tree* t, knn_tree_host* h);
+
+/* Builds take their scratch and the trees' memory from a cache of device
+ * blocks kept by the library (per device), which gives memory a build or a
+ * freed tree handed back to later builds instead of mapping fresh memory;
+ * at most 96 GiB of unused blocks are kept.  This call waits for the current
+ * device and frees every unused block (and trims the device's stream-ordered
+ * pool, which query workspaces come from). */
+int knn_release_memory(void);
 
 /* Message describing the last failure of the calling thread. */
 const char* knn_last_error(void);

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libknn.so")
 
 KNN_OK, KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EDEPTH, KNN_ENOTFINITE = 0, -1, -2, -3, -4, -5
-KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES, KNN_QUERY_STATS, KNN_SERVER_STATS = 16, 64, 12, 9, 8
+KNN_MAX_DIM, KNN_MAX_K, KNN_PHASES, KNN_QUERY_STATS, KNN_SERVER_STATS = 16, 64, 12, 9, 10
 PHASES = ("build_ingest", "build_levels", "build_finish", "build_compact", "build_total",
           "query_locate", "query_group", "query_traverse", "query_total",
           "build_partition_ms", "build_partition_launches", "build_partition_mpts")
@@ -41,7 +41,13 @@ class _BuildParams(ctypes.Structure):
 class _QueryParams(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("leaf_batch", ctypes.c_int32),
                 ("stats", ctypes.c_void_p), ("traversal", ctypes.c_int32),
-                ("pad2_", ctypes.c_int32)]
+                ("team_lanes", ctypes.c_int32)]
+
+
+class _ServerParams(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("slot_max_queries", ctypes.c_int32), ("slot_workgroups_per_cu", ctypes.c_int32),
+                ("slot_idle_us", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -61,10 +67,11 @@ class _Host(ctypes.Structure):
 _lib = None
 EXPORTED = ("knn_build", "knn_build_ex", "knn_build_batch", "knn_query", "knn_query_ex",
             "knn_query_noalloc", "knn_query_batch", "knn_query_radius", "knn_merge", "knn_classify", "knn_regress",
-            "knn_server_create",
+            "knn_server_create", "knn_server_create_ex",
             "knn_server_submit", "knn_server_wait", "knn_server_stats", "knn_server_destroy",
             "knn_tree_free", "knn_tree_errors", "knn_tree_info", "knn_tree_export",
-            "knn_last_error", "knn_strerror", "knn_set_profiling", "knn_get_profile")
+            "knn_last_error", "knn_strerror", "knn_release_memory", "knn_set_profiling",
+            "knn_get_profile")
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -93,6 +100,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                      vp, vp]
     lib.knn_merge.argtypes = [vp, vp, i32, vp, vp, i32, i64, i32, vp, vp, vp]
     lib.knn_server_create.argtypes = [ctypes.POINTER(vp), i32, i64, i32, ctypes.POINTER(vp)]
+    lib.knn_server_create_ex.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(_ServerParams),
+                                         ctypes.POINTER(vp)]
     lib.knn_server_submit.argtypes = [vp, i32, vp, i64, i32, vp, vp, vp,
                                       ctypes.POINTER(ctypes.c_int64)]
     lib.knn_server_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
@@ -108,6 +117,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.knn_last_error.restype = ctypes.c_char_p
     lib.knn_strerror.argtypes = [ctypes.c_int]
     lib.knn_strerror.restype = ctypes.c_char_p
+    lib.knn_release_memory.argtypes = []
     lib.knn_set_profiling.argtypes = [i32]
     lib.knn_get_profile.argtypes = [ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTED:
@@ -240,7 +250,8 @@ def knn_query(tree: Tree, queries, k: int, out=None):
 
 
 def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = math.inf,
-                 order: int = 0, out=None, stats=None, leaf_batch: int = 0, traversal: int = 0):
+                 order: int = 0, out=None, stats=None, leaf_batch: int = 0, traversal: int = 0,
+                 team_lanes: int = 0):
     """knn_query with self exclusion (int32 [m], -1 = none), radius and order.
     ``stats``: optional CUDA int64 [KNN_QUERY_STATS] tensor the traversal adds
     its counters to (see knn_query_params in knn.h)."""
@@ -262,7 +273,7 @@ def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = mat
             raise TypeError(f"stats must be a contiguous CUDA int64 tensor of "
                             f"{KNN_QUERY_STATS} counters")
         st = stats.data_ptr()
-    p = _QueryParams(order, leaf_batch, st, traversal)
+    p = _QueryParams(order, leaf_batch, st, traversal, team_lanes)
     _check(lib.knn_query_ex(tree.handle, ctypes.c_void_p(queries.data_ptr()), queries.shape[0],
                             k, sp, ctypes.c_float(r2_max), ctypes.byref(p),
                             ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
@@ -271,7 +282,8 @@ def knn_query_ex(tree: Tree, queries, k: int, self_ids=None, r2_max: float = mat
 
 
 def knn_query_noalloc(tree: Tree, queries, k: int, self_ids=None, r2_max: float = math.inf,
-                      order: int = 0, out=None, leaf_batch: int = 0, traversal: int = 0):
+                      order: int = 0, out=None, leaf_batch: int = 0, traversal: int = 0,
+                      team_lanes: int = 0):
     """knn_query_ex on the library's static device workspace (the call
     allocates no device memory; calls that overlap on one device race).
     ``out`` (the result tensors) must be given: allocating them here would
@@ -283,7 +295,7 @@ def knn_query_noalloc(tree: Tree, queries, k: int, self_ids=None, r2_max: float 
     idx, d2 = _outputs(queries, k, out)
     m = queries.shape[0]
     sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
-    p = _QueryParams(order, leaf_batch, None, traversal)
+    p = _QueryParams(order, leaf_batch, None, traversal, team_lanes)
     _check(lib.knn_query_noalloc(tree.handle, ctypes.c_void_p(queries.data_ptr()), m, k, sp,
                                  ctypes.c_float(r2_max), ctypes.byref(p),
                                  ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
@@ -301,7 +313,7 @@ def _dev_i32_vec(t, name, m):
 
 def knn_query_batch(forest: Tree, queries, tree_ids, k: int, self_ids=None,
                     r2_max: float = math.inf, order: int = 0, out=None, leaf_batch: int = 0,
-                    traversal: int = 0):
+                    traversal: int = 0, team_lanes: int = 0):
     """k nearest neighbours of each query within its own tree of a forest
     (``tree_ids``: CUDA int32 [m])."""
     lib = load_library()
@@ -310,7 +322,7 @@ def knn_query_batch(forest: Tree, queries, tree_ids, k: int, self_ids=None,
     idx, d2 = _outputs(queries, k, out)
     tp = _dev_i32_vec(tree_ids, "tree_ids", m)
     sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
-    p = _QueryParams(order, leaf_batch, None, traversal)
+    p = _QueryParams(order, leaf_batch, None, traversal, team_lanes)
     _check(lib.knn_query_batch(forest.handle, ctypes.c_void_p(queries.data_ptr()), tp, m, k, sp,
                                ctypes.c_float(r2_max), ctypes.byref(p),
                                ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
@@ -319,7 +331,7 @@ def knn_query_batch(forest: Tree, queries, tree_ids, k: int, self_ids=None,
 
 
 def knn_query_radius(tree: Tree, queries, k: int, r2, self_ids=None, order: int = 0, out=None,
-                     leaf_batch: int = 0, traversal: int = 0):
+                     leaf_batch: int = 0, traversal: int = 0, team_lanes: int = 0):
     """k nearest neighbours with one squared radius per query (CUDA float32 [m])."""
     import torch
     lib = load_library()
@@ -330,7 +342,7 @@ def knn_query_radius(tree: Tree, queries, k: int, r2, self_ids=None, order: int 
         raise TypeError("r2 must be a contiguous CUDA float32 [m] tensor")
     idx, d2 = _outputs(queries, k, out)
     sp = _dev_i32_vec(self_ids, "self_ids", m) if self_ids is not None else None
-    p = _QueryParams(order, leaf_batch, None, traversal)
+    p = _QueryParams(order, leaf_batch, None, traversal, team_lanes)
     _check(lib.knn_query_radius(tree.handle, ctypes.c_void_p(queries.data_ptr()), m, k, sp,
                                 ctypes.c_void_p(r2.data_ptr()), ctypes.byref(p),
                                 ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
@@ -366,13 +378,19 @@ class Server:
     """Serving loop over resident trees (knn_server_* in knn.h).  Keep the
     trees, and every submitted request's tensors, alive until waited for."""
 
-    def __init__(self, trees, hbm_budget_bytes: int = 0, streams: int = 0):
+    def __init__(self, trees, hbm_budget_bytes: int = 0, streams: int = 0,
+                 slot_max_queries: int = 0, slot_workgroups_per_cu: int = 0,
+                 slot_idle_us: int = 0):
+        """``slot_max_queries``: 0 (default), every request forms batches;
+        n > 0, requests of at most n queries go to the trees' slot kernels
+        (persistent launches that take requests over while they run)."""
         lib = load_library()
         self._trees = list(trees)
         arr = (ctypes.c_void_p * len(self._trees))(*[t.handle.value for t in self._trees])
         h = ctypes.c_void_p()
-        _check(lib.knn_server_create(arr, len(self._trees), hbm_budget_bytes, streams,
-                                     ctypes.byref(h)))
+        p = _ServerParams(hbm_budget_bytes, streams, slot_max_queries, slot_workgroups_per_cu,
+                          slot_idle_us)
+        _check(lib.knn_server_create_ex(arr, len(self._trees), ctypes.byref(p), ctypes.byref(h)))
         self._h = h
         self._keep = {}
 
@@ -403,8 +421,8 @@ class Server:
         buf = (ctypes.c_int64 * KNN_SERVER_STATS)()
         _check(load_library().knn_server_stats(self._h, buf))
         return dict(zip(("requests", "batches", "queries", "peak_bytes", "max_requests_per_batch",
-                         "peak_batches_in_flight", "max_k_per_batch", "joined_while_running"),
-                        list(buf)))
+                         "peak_batches_in_flight", "max_k_per_batch", "joined_while_running",
+                         "slot_requests", "slot_launches"), list(buf)))
 
     def close(self):
         if self._h and self._h.value:
@@ -420,6 +438,13 @@ class Server:
 
 def knn_server_create(trees, hbm_budget_bytes: int = 0, streams: int = 0) -> Server:
     return Server(trees, hbm_budget_bytes, streams)
+
+
+def knn_server_create_ex(trees, hbm_budget_bytes: int = 0, streams: int = 0,
+                         slot_max_queries: int = 0, slot_workgroups_per_cu: int = 0,
+                         slot_idle_us: int = 0) -> Server:
+    return Server(trees, hbm_budget_bytes, streams, slot_max_queries, slot_workgroups_per_cu,
+                  slot_idle_us)
 
 
 def knn_server_submit(server: Server, tree: int, queries, k: int, self_ids=None, out=None) -> int:
@@ -513,6 +538,11 @@ def knn_tree_errors(tree: Tree, stream=None) -> int:
     _check(load_library().knn_tree_errors(tree.handle, ctypes.c_void_p(s.cuda_stream),
                                           ctypes.byref(c)))
     return c.value
+
+
+def knn_release_memory():
+    """Wait for the device and return the build pool's unused memory to it."""
+    _check(load_library().knn_release_memory())
 
 
 def knn_strerror(code: int) -> str:

@@ -36,12 +36,15 @@ def _time(fn, reps: int) -> float:
 
 def tune(points, queries, k: int, self_ids=None, offsets=None, tree_ids=None,
          leaf_sizes=(16, 32, 64), leaf_batches=(32, 48, 64), orders=(0, 1),
-         traversals=(1, 2, 3), reps: int = 3, build_weight: float = 1.0) -> dict:
-    """Return {"leaf_size", "leaf_batch", "order", "traversal", "ms", "table"}: the knobs
-    minimising build_weight * build time + query time on this sample.  The
-    best traversal form depends on the batch size (one wavefront per query pays
-    off for small batches), so tune on batches of the size the knobs will
-    serve, or leave form 3 out of ``traversals`` when the sample is smaller.
+         traversals=(1, 2, 3, (4, 16), (4, 32)), reps: int = 3,
+         build_weight: float = 1.0) -> dict:
+    """Return {"leaf_size", "leaf_batch", "order", "traversal", "team_lanes", "ms",
+    "table"}: the knobs minimising build_weight * build time + query time on
+    this sample.  A traversal entry is a form (1, 2, 3) or (4, lanes) for a
+    team of lanes per query.  The best form depends on the batch size (one
+    wavefront or a team per query pays off for small batches), so tune on
+    batches of the size the knobs will serve, or leave forms 3 and 4 out of
+    ``traversals`` when the sample is smaller.
     ``points``/``queries`` are CUDA float32 tensors; for a forest pass the host
     ``offsets`` and the CUDA int32 ``tree_ids`` of the queries."""
     table = []
@@ -52,19 +55,23 @@ def tune(points, queries, k: int, self_ids=None, offsets=None, tree_ids=None,
             build = lambda: knn.knn_build_ex(points, leaf_size=leaf)  # noqa: E731
         t_build = _time(lambda: build().free(), reps)
         tree = build()
-        for lb, order, trav in itertools.product(leaf_batches, orders, traversals):
+        for lb, order, form in itertools.product(leaf_batches, orders, traversals):
+            trav, team = form if isinstance(form, tuple) else (form, 0)
             if offsets is not None:
                 q = lambda: knn.knn_query_batch(tree, queries, tree_ids, k,  # noqa: E731
                                                 self_ids=self_ids, order=order, leaf_batch=lb,
-                                                traversal=trav)
+                                                traversal=trav, team_lanes=team)
             else:
                 q = lambda: knn.knn_query_ex(tree, queries, k, self_ids=self_ids,  # noqa: E731
-                                             order=order, leaf_batch=lb, traversal=trav)
+                                             order=order, leaf_batch=lb, traversal=trav,
+                                             team_lanes=team)
             t_query = _time(q, reps)
             table.append({"leaf_size": leaf, "leaf_batch": lb, "order": order, "traversal": trav,
-                          "build_ms": t_build * 1e3, "query_ms": t_query * 1e3,
+                          "team_lanes": team, "build_ms": t_build * 1e3,
+                          "query_ms": t_query * 1e3,
                           "ms": (build_weight * t_build + t_query) * 1e3})
         tree.free()
     best = min(table, key=lambda r: r["ms"])
-    return {**{key: best[key] for key in ("leaf_size", "leaf_batch", "order", "traversal", "ms")},
+    return {**{key: best[key] for key in ("leaf_size", "leaf_batch", "order", "traversal",
+                                          "team_lanes", "ms")},
             "table": table}

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libknn.so")
 OBJ = os.path.join(ROOT, "_build")
 SOURCES = ["knn_api.hip", "knn_build.hip", "knn_query.hip", "knn_trav_lane1.hip",
-           "knn_trav_lane2.hip", "knn_trav_stack1.hip", "knn_trav_stack2.hip", "knn_serve.hip",
+           "knn_trav_lane2.hip", "knn_trav_stack1.hip", "knn_trav_stack2.hip", "knn_trav_team.hip",
+           "knn_serve.hip",
            "knn_classify.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

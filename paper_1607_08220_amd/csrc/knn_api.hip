@@ -48,6 +48,86 @@ int hip_fail(hipError_t e, const char* what)
 
 Profiler& profiler() { return g_prof; }
 
+namespace {
+std::mutex g_cache_mu;
+std::multimap<std::pair<int, size_t>, void*> g_cache_free;     // (device, bytes) -> block
+std::unordered_map<void*, std::pair<int, size_t>> g_cache_all;  // every block the cache made
+size_t g_cache_free_bytes = 0;
+constexpr size_t kCacheRound = size_t(2) << 20;
+constexpr size_t kCacheKeepMax = size_t(96) << 30;  // free blocks kept beyond this are freed
+
+// Free kept blocks of `dev` (all of them when dev < 0), largest first,
+// until at most `keep` bytes stay.  The caller holds g_cache_mu.
+hipError_t cache_shrink(int dev, size_t keep)
+{
+    hipError_t err = hipSuccess;
+    for (auto it = g_cache_free.end(); it != g_cache_free.begin() && g_cache_free_bytes > keep;) {
+        --it;
+        if (dev >= 0 && it->first.first != dev) continue;
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        if (prev != it->first.first) (void)hipSetDevice(it->first.first);
+        const hipError_t e = hipFree(it->second);
+        if (prev != it->first.first) (void)hipSetDevice(prev);
+        if (e != hipSuccess) err = e;
+        g_cache_free_bytes -= it->first.second;
+        g_cache_all.erase(it->second);
+        it = g_cache_free.erase(it);
+    }
+    return err;
+}
+}  // namespace
+
+hipError_t cache_alloc(void** out, size_t bytes)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t want = (std::max<size_t>(bytes, 1) + kCacheRound - 1) / kCacheRound * kCacheRound;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        auto it = g_cache_free.lower_bound({dev, want});
+        // a kept block of this device at most a quarter larger than asked for
+        if (it != g_cache_free.end() && it->first.first == dev &&
+            it->first.second <= want + want / 4 + kCacheRound) {
+            *out = it->second;
+            g_cache_free_bytes -= it->first.second;
+            g_cache_free.erase(it);
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(out, want);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {  // hand kept blocks back, retry
+        {
+            std::lock_guard<std::mutex> g(g_cache_mu);
+            (void)cache_shrink(dev, 0);
+        }
+        (void)hipGetLastError();
+        e = hipMalloc(out, want);
+    }
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    g_cache_all[*out] = {dev, want};
+    return hipSuccess;
+}
+
+void cache_free(void* p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    auto it = g_cache_all.find(p);
+    if (it == g_cache_all.end()) return;  // not a cache block
+    g_cache_free.emplace(it->second, p);
+    g_cache_free_bytes += it->second.second;
+    if (g_cache_free_bytes > kCacheKeepMax) (void)cache_shrink(-1, kCacheKeepMax);
+}
+
+hipError_t cache_trim()
+{
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    return cache_shrink(-1, 0);
+}
+
 void prof_mark(hipStream_t s, int slot)
 {
     if (!g_prof.on) return;
@@ -188,7 +268,10 @@ int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     const int32_t batch = p && p->leaf_batch ? p->leaf_batch : kDefaultLeafBatch;
     if (batch < 1 || batch > 64) return fail(KNN_EINVAL, "leaf_batch must be in [0, 64]");
     const int32_t traversal = p ? p->traversal : 0;
-    if (traversal < 0 || traversal > 3) return fail(KNN_EINVAL, "traversal must be 0, 1, 2 or 3");
+    if (traversal < 0 || traversal > 4) return fail(KNN_EINVAL, "traversal must be 0 .. 4");
+    const int32_t team = p ? p->team_lanes : 0;
+    if (team != 0 && team != 8 && team != 16 && team != 32)
+        return fail(KNN_EINVAL, "team_lanes must be 0, 8, 16 or 32");
     DeviceGuard g(t->device);
     QuerySpec qs;
     qs.queries = queries;
@@ -201,6 +284,7 @@ int query_common(const knn_tree* t, const float* queries, int64_t m, int32_t k,
     qs.order = order;
     qs.batch = batch;
     qs.traversal = traversal;
+    qs.team = team;
     qs.out_idx = out_idx;
     qs.out_d2 = out_dist2;
     qs.stats = p ? reinterpret_cast<unsigned long long*>(p->stats) : nullptr;
@@ -285,12 +369,12 @@ int knn_tree_free(knn_tree* t)
         }
         t->uses.clear();
     }
-    // stream-ordered pool allocations of the build: no work reads them any
-    // more, so they go back to the pool without waiting for the device
-    if (t->pts) (void)hipFreeAsync(t->pts, nullptr);
-    if (t->nodes) (void)hipFreeAsync(t->nodes, nullptr);
-    if (t->bbox) (void)hipFreeAsync(t->bbox, nullptr);
-    if (t->bad) (void)hipFreeAsync(t->bad, nullptr);
+    // no work reads the tree's blocks any more: back to the cache for the
+    // next build
+    cache_free(t->pts);
+    cache_free(t->nodes);
+    cache_free(t->bbox);
+    cache_free(t->bad);
     delete t;
     return rc;
 }
@@ -375,6 +459,18 @@ int knn_tree_export(const knn_tree* t, knn_tree_host* h)
         if (h->packed)
             for (int j = 0; j < d; ++j) h->packed[i * d + j] = row[j];
     }
+    return KNN_OK;
+}
+
+int knn_release_memory(void)
+{
+    int dev = 0;
+    KNN_HIP(hipGetDevice(&dev));
+    KNN_HIP(hipDeviceSynchronize());
+    KNN_HIP(cache_trim());
+    hipMemPool_t pool;
+    KNN_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    KNN_HIP(hipMemPoolTrimTo(pool, 0));
     return KNN_OK;
 }
 

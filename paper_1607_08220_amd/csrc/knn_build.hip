@@ -1974,23 +1974,10 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
 {
     prof_mark(st, 0);
     prof_part_begin();
-    {   // let the pool keep build scratch between builds, up to half the
-        // device's memory: a 2^28-point 4-D build touches about 40 GiB, and
-        // memory handed back at every synchronisation has to be mapped again
-        // by the next build
-        int dev = 0;
-        hipMemPool_t pool;
-        size_t free_b = 0, total_b = 0;
-        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess &&
-            hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-            uint64_t keep = std::max<uint64_t>(uint64_t(total_b) / 2, uint64_t(64) << 30);
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-        }
-    }
     const int64_t nd = n * d;
-    // the tree's own buffers (pts, nodes, bbox) come from the stream-ordered
-    // pool too: a build that follows a freed tree reuses its memory instead of
-    // mapping fresh pages while the device waits
+    // scratch and the tree's own buffers (pts, nodes, bbox) come from the
+    // library's block cache: a build that follows another, or a freed tree,
+    // reuses that memory instead of mapping fresh pages while the device waits
     DevBuf colsA(st), colsB(st), idxA(st), idxB(st), pts(st), gbuf(st);
     // padded by one finish tile of rows: the finish reads whole rows of 64
     // points, up to 64 * kGlobalRows - 1 elements past a node's last point

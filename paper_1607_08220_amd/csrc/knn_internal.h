@@ -5,7 +5,9 @@
 
 #include <cmath>
 #include <cstdint>
+#include <map>
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -74,16 +76,26 @@ int hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::knn::hip_fail(e_, #expr);   \
     } while (0)
 
-// Device buffer owned by a scope.  With a stream it is scratch taken from
-// the device's stream-ordered pool (freed in stream order, kept by the pool
-// for the next build); without one it is a plain allocation.
+// Device memory of builds and trees.  Blocks handed back here are kept per
+// device and given out again to later requests of about the same size:
+// mapping fresh device memory (tens of GiB for the largest builds) costs more
+// than a build, and the stream-ordered pool returns its memory to the device
+// at synchronisations.  A block is handed back only when no work on it
+// remains.  cache_trim frees every kept block.
+hipError_t cache_alloc(void** p, size_t bytes);
+void cache_free(void* p);
+hipError_t cache_trim();
+
+// Device buffer owned by a scope.  With a stream it comes from the cache
+// above and goes back there once that stream has finished with it; without
+// one it is a plain allocation.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
-    bool pooled = false;
+    bool cached = false;
     DevBuf() = default;
-    explicit DevBuf(hipStream_t s) : stream(s), pooled(true) {}
+    explicit DevBuf(hipStream_t s) : stream(s), cached(true) {}
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { reset(); }
@@ -91,10 +103,17 @@ struct DevBuf {
         reset();
         bytes = b;
         if (!b) return hipSuccess;
-        return pooled ? hipMallocAsync(&p, b, stream) : hipMalloc(&p, b);
+        return cached ? cache_alloc(&p, b) : hipMalloc(&p, b);
     }
     void reset() {
-        if (p) (void)(pooled ? hipFreeAsync(p, stream) : hipFree(p));
+        if (p) {
+            if (cached) {
+                (void)hipStreamSynchronize(stream);  // nothing in flight may still use it
+                cache_free(p);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -146,7 +165,9 @@ struct QuerySpec {
     const int32_t* qroot = nullptr;  // per-query root node (forests)
     int32_t order = 0;
     int32_t batch = 48;
-    int32_t traversal = 0;           // 0 auto, 1 stack-free walk from the home leaf, 2 explicit stack
+    int32_t traversal = 0;           // 0 auto, 1 stack-free walk from the home leaf, 2 explicit
+                                     // stack, 3 a wavefront per query, 4 a team per query
+    int32_t team = 0;                // lanes per query of traversal 4 (0 = 32)
     int32_t* out_idx = nullptr;
     float* out_d2 = nullptr;
     unsigned long long* stats = nullptr;

@@ -326,9 +326,18 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     // asked for, or by default for batches too small to fill the device with
     // one lane per query; it runs in input order (grouping by home leaf costs
     // more than the coherence it buys a wavefront that walks one query)
+    // a team of lanes per query: asked for, or by default for mid-size batches
+    // of deep (high-dimensional) searches; k and the tree's depth must fit
+    const bool high = d >= kStackMinDim;
+    const bool team_default = qs.traversal == 0 && high && m > kWaveQueriesMaxHigh &&
+                              m <= kTeamQueriesMax;
+    const int team = qs.team ? qs.team : kTeamDefault;
+    const bool use_team = (qs.traversal == 4 || team_default) && qs.stats == nullptr &&
+                          qs.k <= team && t->depth + 1 <= team;
+    const int trav = qs.traversal == 4 && !use_team ? 0 : qs.traversal;
     const bool wave_ok = t->depth + 1 <= kWave && qs.stats == nullptr;
-    const bool use_wave =
-        wave_ok && (qs.traversal == 3 || (qs.traversal == 0 && m <= kWaveQueriesMax));
+    const int64_t wave_max = high ? kWaveQueriesMaxHigh : kWaveQueriesMax;
+    const bool use_wave = !use_team && wave_ok && (trav == 3 || (trav == 0 && m <= wave_max));
     const bool grouped = qs.order != 1 && !use_wave;
     // key range: packed positions >> shift, at most 2^22 buckets
     int shift = 0;
@@ -398,8 +407,15 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     // the explicit stack needs (depth + 1) entries of 8 bytes per lane in LDS
     const size_t stk_bytes = sizeof(int2) * (size_t)(t->depth + 1) * kBlock;
     const bool use_stack = stk_bytes <= kMaxStackLds &&
-                           (qs.traversal == 2 || (qs.traversal == 0 && d >= kStackMinDim));
-    if (use_wave) {
+                           (trav == 2 || (trav == 0 && d >= kStackMinDim));
+    if (use_team) {  // grouped order (when asked) for locality; each team starts at its root
+        TraverseFn ft = team_for(d, team);
+        if (!ft) return fail(KNN_EINVAL, "unsupported dimension or team size");
+        A.home = nullptr;
+        const int64_t per_block = (int64_t)kWavesPerBlock * (kWave / team);
+        hipLaunchKernelGGL(ft, dim3((unsigned)((m + per_block - 1) / per_block)), dim3(kBlock), 0,
+                           st, A);
+    } else if (use_wave) {
         WaveFn wf = wave_for(d);
         const unsigned wgrid = (unsigned)((m + kWavesPerBlock - 1) / kWavesPerBlock);
         hipLaunchKernelGGL(wf, dim3(wgrid), dim3(kBlock), 0, st, A);

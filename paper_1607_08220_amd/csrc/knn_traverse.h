@@ -48,6 +48,11 @@ constexpr int kXcds = 8;                      // accelerator complex dies of an 
 constexpr size_t kMaxStackLds = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr int kStackMinDim = 5;               // default: explicit stack from 5 dimensions
 constexpr int64_t kWaveQueriesMax = 16384;    // default: one wavefront per query up to this batch
+// default from kStackMinDim dimensions: batches above kWaveQueriesMaxHigh and
+// up to kTeamQueriesMax queries take a team of kTeamDefault lanes per query
+constexpr int64_t kWaveQueriesMaxHigh = 4096;
+constexpr int64_t kTeamQueriesMax = 32768;
+constexpr int kTeamDefault = 32;
 
 // q[dim] as a chain of selects.  The empty asm keeps the compiler from
 // turning the chain back into a dynamically indexed array (which it would
@@ -624,34 +629,23 @@ __device__ inline uint64_t readlane_u64(uint64_t v, int lane)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The k nearest neighbours of one query, computed by the whole (active,
+// uniform) wavefront: q is the query, self the index it excludes (-1: none),
+// r2 the squared radius, root the node to start at (-1: none, padding rows),
+// k the neighbour count; lane j < k writes entry j to out_idx / out_d2.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
+__device__ inline void wave_answer(const NodeRec* __restrict__ nodes,
+                                   const float* __restrict__ bbox, const float* __restrict__ pts,
+                                   const float (&q)[D], int32_t self, int k, float r2, int root,
+                                   int32_t* __restrict__ out_idx, float* __restrict__ out_d2)
 {
-    const NodeRec* __restrict__ nodes = A.nodes;
-    const float* __restrict__ bbox = A.bbox;
-    const float* __restrict__ pts = A.pts;
     const int lane = threadIdx.x & 63;
-    const int64_t slot =
-        (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (slot >= A.m) return;  // the whole wavefront
-    const int64_t qid = A.order ? A.order[slot] : slot;
-    float q[D];
-#pragma unroll
-    for (int t = 0; t < D; ++t) q[t] = A.queries[qid * D + t];
-    const int32_t self = A.self_ids ? A.self_ids[qid] : -1;
-    const int k = __builtin_amdgcn_readfirstlane(A.qk ? A.qk[qid] : A.k);
-    const float r2 = A.r2s ? A.r2s[qid] : A.r2;
     const uint64_t empty = r2 > 0.0f ? make_key(r2, 0) : 0;
     uint64_t h = empty;  // lane j < k: the (j + 1)-th smallest key so far
     int s_node = 0;      // pending far child of stack entry `lane`
     float s_bound = 0.0f;
     int sp = 0;
-    int cur = 0;
-    if (A.root) {  // one lane validates (and counts) the tree id for the wavefront
-        int r0 = 0;
-        if (lane == 0) r0 = query_root(A, qid);
-        cur = __builtin_amdgcn_readfirstlane(r0);
-    }
+    int cur = root;
     // record and box of the stack's top entry, loaded while a bucket is
     // scanned: the node the next pop most likely returns
     int pf = -1;
@@ -734,11 +728,176 @@ __global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
         cur = -1;
     }
     if (lane < k) {
-        const int64_t o = (A.qout ? A.qout[qid] : qid * k) + lane;
         const bool none = h == empty;
-        A.out_idx[o] = none ? -1 : (int)(uint32_t)h;
-        A.out_d2[o] = none ? INFINITY : key_dist(h);
+        out_idx[lane] = none ? -1 : (int)(uint32_t)h;
+        out_d2[lane] = none ? INFINITY : key_dist(h);
     }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t slot =
+        (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (slot >= A.m) return;  // the whole wavefront
+    const int64_t qid = A.order ? A.order[slot] : slot;
+    float q[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) q[t] = A.queries[qid * D + t];
+    const int32_t self = A.self_ids ? A.self_ids[qid] : -1;
+    const int k = __builtin_amdgcn_readfirstlane(A.qk ? A.qk[qid] : A.k);
+    const float r2 = A.r2s ? A.r2s[qid] : A.r2;
+    int cur = 0;
+    if (A.root) {  // one lane validates (and counts) the tree id for the wavefront
+        int r0 = 0;
+        if (lane == 0) r0 = query_root(A, qid);
+        cur = __builtin_amdgcn_readfirstlane(r0);
+    }
+    const int64_t o = A.qout ? A.qout[qid] : qid * k;
+    wave_answer<D>(A.nodes, A.bbox, A.pts, q, self, k, r2, cur, A.out_idx + o, A.out_d2 + o);
+}
+
+// A team of T lanes (T divides 64) per query: the one-wavefront-per-query
+// search above with the wavefront split into 64 / T independent teams, for
+// batches large enough to fill the device with teams.  Team lane i holds
+// stack entry i and, for i < k, heap entry i; a bucket is scanned T rows at
+// a time; every exchange stays inside the team (shuffles of width T, the
+// team's bits of a ballot).  Needs k <= T and depth + 1 <= T.  Control flow
+// is uniform within a team only.
+__device__ inline uint64_t team_read_u64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int D, int T>
+__device__ inline void team_answer(const NodeRec* __restrict__ nodes,
+                                   const float* __restrict__ bbox, const float* __restrict__ pts,
+                                   const float (&q)[D], int32_t self, int k, float r2, int root,
+                                   int32_t* __restrict__ out_idx, float* __restrict__ out_d2)
+{
+    static_assert(T >= 2 && T <= kWave && (kWave % T) == 0, "a team divides the wavefront");
+    const int lane = threadIdx.x & 63;
+    const int tl = lane & (T - 1);  // lane within the team
+    const int tb = lane - tl;       // the team's first lane
+    constexpr uint64_t kTeamBits = T == 64 ? ~0ull : ((1ull << T) - 1);
+    const uint64_t empty = r2 > 0.0f ? make_key(r2, 0) : 0;
+    uint64_t h = empty;  // team lane j < k: the (j + 1)-th smallest key so far
+    int s_node = 0;      // pending far child of stack entry tl
+    float s_bound = 0.0f;
+    int sp = 0;
+    int cur = root;
+    int pf = -1;  // the stack top's node, loaded while a bucket is scanned
+    NodeRec pr{};
+    float pbb[2 * D];
+    while (true) {
+        uint64_t top = team_read_u64(h, tb + k - 1);
+        const float thr = key_dist(top);
+        if (cur < 0) {  // the next pending far child whose bound does not exceed thr
+            while (sp > 0) {
+                --sp;
+                const float b = __shfl(s_bound, tb + sp);
+                if (b <= thr) {
+                    cur = __shfl(s_node, tb + sp);
+                    break;
+                }
+            }
+            if (cur < 0) break;
+        }
+        NodeRec r;
+        float bb[2 * D];
+        if (cur == pf) {
+            r = pr;
+#pragma unroll
+            for (int t = 0; t < 2 * D; ++t) bb[t] = pbb[t];
+        } else {
+            r = nodes[cur];
+            load_box<D>(bbox + (int64_t)cur * (2 * D), bb);
+        }
+        pf = -1;
+        if (box_bound<D>(q, bb) > thr) {  // no point of this node can enter H
+            cur = -1;
+            continue;
+        }
+        if (r.dim >= 0) {
+            const float qd = select_dim<D>(q, r.dim);
+            const bool left_near = qd < r.split;
+            const float o = left_near ? r.split - qd : qd - r.split;
+            if (sp < T) {  // always: a path holds at most depth pending entries
+                if (tl == sp) {
+                    s_node = left_near ? r.a + 1 : r.a;
+                    s_bound = o * o;
+                }
+                ++sp;
+            }
+            cur = left_near ? r.a : r.a + 1;  // near child first
+            continue;
+        }
+        const int cnt = -r.dim;
+        if (sp > 0) {
+            pf = __shfl(s_node, tb + sp - 1);
+            pr = nodes[pf];
+            load_box<D>(bbox + (int64_t)pf * (2 * D), pbb);
+        }
+        for (int j0 = 0; j0 < cnt; j0 += T) {
+            const int j = j0 + tl;
+            uint64_t key = ~0ull;
+            bool cand = false;
+            if (j < cnt) {
+                float x[D + 1];
+                load_row<D>(pts + (int64_t)(r.a + j) * (D + 1), x);
+                const int id = __float_as_int(x[D]);
+                key = make_key(distance<D>(q, x), id);
+                cand = key < top && id != self;
+            }
+            uint64_t cm = (__ballot(cand) >> tb) & kTeamBits;
+            while (cm) {
+                const int src = __builtin_ctzll(cm);
+                cm &= cm - 1;
+                const uint64_t kk = team_read_u64(key, tb + src);
+                if (kk < top) {  // insert into the sorted list, dropping entry k - 1
+                    const uint32_t plo = (uint32_t)__shfl_up((int)(uint32_t)h, 1, T);
+                    const uint32_t phi = (uint32_t)__shfl_up((int)(uint32_t)(h >> 32), 1, T);
+                    const uint64_t prev = ((uint64_t)phi << 32) | plo;
+                    if (tl < k && kk < h) h = (tl > 0 && kk < prev) ? prev : kk;
+                    top = team_read_u64(h, tb + k - 1);
+                }
+            }
+        }
+        cur = -1;
+    }
+    if (tl < k) {
+        const bool none = h == empty;
+        out_idx[tl] = none ? -1 : (int)(uint32_t)h;
+        out_d2[tl] = none ? INFINITY : key_dist(h);
+    }
+}
+
+template <int D, int T>
+__global__ __launch_bounds__(kBlock) void k_traverse_team(TravArgs A)
+{
+    constexpr int kQpw = kWave / T;  // queries per wavefront
+    const int lane = threadIdx.x & 63;
+    const int tb = lane & ~(T - 1);
+    const int64_t slot = ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * kQpw + lane / T;
+    if (slot >= A.m) return;  // the whole team
+    const int64_t qid = A.order ? A.order[slot] : slot;
+    float q[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) q[t] = A.queries[qid * D + t];
+    const int32_t self = A.self_ids ? A.self_ids[qid] : -1;
+    const int k = A.qk ? A.qk[qid] : A.k;
+    const float r2 = A.r2s ? A.r2s[qid] : A.r2;
+    int cur = 0;
+    if (A.root) {  // the team's first lane validates (and counts) the tree id
+        int r0 = 0;
+        if (lane == tb) r0 = query_root(A, qid);
+        cur = __shfl(r0, tb);
+    }
+    const int64_t o = A.qout ? A.qout[qid] : qid * k;
+    team_answer<D, T>(A.nodes, A.bbox, A.pts, q, self, k, r2, cur, A.out_idx + o, A.out_d2 + o);
 }
 
 }  // namespace
@@ -753,5 +912,8 @@ TraverseFn traverse_for_high(int d, int k, bool stats);
 // The explicit-stack kernel likewise: knn_trav_stack1.hip, knn_trav_stack2.hip.
 StackFn stack_for_low(int d, int k, bool stats);
 StackFn stack_for_high(int d, int k, bool stats);
+// The team form for dimension d and team size t in {8, 16, 32}:
+// knn_trav_team.hip.
+TraverseFn team_for(int d, int t);
 
 }  // namespace knn

@@ -22,7 +22,7 @@ def dev(a, dtype=None):
 
 
 def gpu_knn(points, queries, k, leaf=32, self_ids=None, r2=np.inf, order=0, tree=None,
-            subtree_points=0, split_block_nodes=0, traversal=0):
+            subtree_points=0, split_block_nodes=0, traversal=0, team_lanes=0):
     """Build (unless a tree is given) and query through the C-ABI; host arrays out."""
     import torch
     import paper_1607_08220_amd as knn
@@ -34,7 +34,7 @@ def gpu_knn(points, queries, k, leaf=32, self_ids=None, r2=np.inf, order=0, tree
     Q = dev(np.asarray(queries, np.float32))
     S = dev(np.asarray(self_ids, np.int32)) if self_ids is not None else None
     idx, d2 = knn.knn_query_ex(tree, Q, k, self_ids=S, r2_max=r2, order=order,
-                               traversal=traversal)
+                               traversal=traversal, team_lanes=team_lanes)
     torch.cuda.synchronize()
     return idx.cpu().numpy(), d2.cpu().numpy(), tree
 

@@ -30,7 +30,8 @@ def _local_self(ids_global, members):
 
 
 @pytest.mark.parametrize("k,trav,order", [(1, 0, 0), (8, 0, 0), (33, 0, 0), (8, 1, 0),
-                                           (8, 1, 1), (33, 2, 0), (8, 2, 1), (33, 3, 0)])
+                                           (8, 1, 1), (33, 2, 0), (8, 2, 1), (33, 3, 0),
+                                           (8, 4, 0), (1, 4, 1)])
 def test_two_owner_query_with_radius_and_merge(knn, k, trav, order):
     import torch
     w = inputs.workload("cosmo_clustered", scale=1 / 512)
@@ -84,7 +85,8 @@ def test_merge_edges(knn):
         knn.knn_merge((dev(ia), dev(da)), (dev(ib), dev(db)), 65)
 
 
-@pytest.mark.parametrize("trav,order", [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (3, 0)])
+@pytest.mark.parametrize("trav,order", [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (3, 0), (4, 0),
+                                        (4, 1)])
 def test_radius_per_query_matches_scalar(knn, trav, order):
     """A per-query radius equal for all queries gives the scalar-radius result."""
     import torch

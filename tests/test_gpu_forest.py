@@ -47,13 +47,13 @@ def test_forest_matches_oracle_and_single_trees(knn, d, lo, hi, ntrees):
     # every traversal form in both orders: the lane-per-query forms start at
     # the home leaf of each query's own tree (grouped across trees) or at its
     # root; the wavefront form takes input order
-    for trav in (1, 2, 3):
+    for trav, team in ((1, 0), (2, 0), (3, 0), (4, 8), (4, 32)):
         for order in (0, 1):
             ti, td = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order,
-                                         traversal=trav)
+                                         traversal=trav, team_lanes=team)
             torch.cuda.synchronize()
             assert_same(ti.cpu().numpy(), td.cpu().numpy(), fi, fd,
-                        f"traversal {trav} order {order} vs default")
+                        f"traversal {trav} (team {team}) order {order} vs default")
     assert knn.knn_tree_errors(forest) == 0
     for t in range(ntrees):
         a, b = int(f.offsets[t]), int(f.offsets[t + 1])
@@ -93,12 +93,13 @@ def test_autotune_picks_a_listed_config(knn):
                       leaf_batches=(48, 64), orders=(0, 1), reps=1)
     assert (r["leaf_size"], r["leaf_batch"], r["order"]) in {
         (a["leaf_size"], a["leaf_batch"], a["order"]) for a in r["table"]}
-    # 2 leaf sizes x 2 leaf batches x 2 orders x 3 traversal forms
-    assert len(r["table"]) == 24 and r["ms"] == min(a["ms"] for a in r["table"])
-    assert {a["traversal"] for a in r["table"]} == {1, 2, 3}
+    # 2 leaf sizes x 2 leaf batches x 2 orders x 5 traversal forms (two team sizes)
+    assert len(r["table"]) == 40 and r["ms"] == min(a["ms"] for a in r["table"])
+    assert {(a["traversal"], a["team_lanes"]) for a in r["table"]} == {
+        (1, 0), (2, 0), (3, 0), (4, 16), (4, 32)}
 
 
-@pytest.mark.parametrize("trav", [1, 2, 3])
+@pytest.mark.parametrize("trav", [1, 2, 3, 4])
 def test_forest_query_graph_replay(knn, trav):
     """The batched query captured once in a graph and replayed, with eager
     work and synchronization between replays, gives the eager result every
@@ -161,10 +162,10 @@ def test_out_of_range_tree_ids(knn):
         ii, dd = oracle.bf32(f.points[a:b], f.queries[sel], f.k, self_ids=f.self_ids[sel] - a)
         ref[t] = (sel, np.where(ii >= 0, ii + a, ii), dd)
     Q, T, S = dev(f.queries), dev(ids), dev(f.self_ids)
-    for trav in (1, 2, 3):
+    for trav in (1, 2, 3, 4):
         for order in (0, 1):
             gi, gd = knn.knn_query_batch(forest, Q, T, f.k, self_ids=S, order=order,
-                                         traversal=trav)
+                                         traversal=trav, team_lanes=16)
             torch.cuda.synchronize()
             gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
             assert (gi[bad] == -1).all() and np.isinf(gd[bad]).all(), (trav, order)

@@ -51,6 +51,10 @@ def _full_check(knn, X, Q, k, leaf, self_ids=None, r2=np.inf, what="", subtree_p
             gi2, gd2, _ = gpu_knn(X, Q, k, self_ids=self_ids, r2=r2, tree=tree, traversal=trav,
                                   order=order)
             assert_same(gi2, gd2, oi, od, what + f" (traversal {trav}, order {order})")
+    for team in (8, 16, 32):  # a team of lanes per query (where k and the depth fit)
+        gi3, gd3, _ = gpu_knn(X, Q, k, self_ids=self_ids, r2=r2, tree=tree, traversal=4,
+                              team_lanes=team)
+        assert_same(gi3, gd3, oi, od, what + f" (team of {team})")
     tree.free()
 
 
@@ -329,12 +333,13 @@ def test_both_traversals_match_oracle(knn, d):
     log(f"[case] traversals d={d}")
     t = knn.knn_build(dev(X), 32)
     bi, bd = oracle.bf32(X, X[ids], 9, self_ids=ids)
-    for trav in (1, 2, 3):
+    for trav, team in ((1, 0), (2, 0), (3, 0), (4, 16), (4, 32)):
         for order in (0, 1):
             gi, gd = knn.knn_query_ex(t, dev(X[ids]), 9, self_ids=dev(ids), traversal=trav,
-                                      order=order)
+                                      order=order, team_lanes=team)
             torch.cuda.synchronize()
-            assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"traversal {trav} order {order}")
+            assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd,
+                        f"traversal {trav} (team {team}) order {order}")
     t.free()
 
 
@@ -352,15 +357,23 @@ def test_wavefront_per_query_edge_cases(knn, d):
     ids = rng.choice(n, 300, replace=False).astype(np.int32)
     log(f"[case] wavefront per query d={d}")
     t = knn.knn_build(dev(X), 16)
-    for k in (1, 7, 64):
+    for k in (1, 7, 16, 32, 64):
         bi, bd = oracle.bf32(X, X[ids], k, self_ids=ids)
         gi, gd = knn.knn_query_ex(t, dev(X[ids]), k, self_ids=dev(ids), traversal=3)
         torch.cuda.synchronize()
         assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"wave k={k}")
+        for team in (8, 16, 32):  # teams with k at and above their size (the latter fall back)
+            gi, gd = knn.knn_query_ex(t, dev(X[ids]), k, self_ids=dev(ids), traversal=4,
+                                      team_lanes=team)
+            torch.cuda.synchronize()
+            assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"team {team} k={k}")
     for r2 in (0.0, -1.0, 0.5):
         bi, bd = oracle.bf32(X, X[ids[:1]], 5, self_ids=ids[:1], r2=r2)
-        gi, gd = knn.knn_query_ex(t, dev(X[ids[:1]]), 5, self_ids=dev(ids[:1]), r2_max=r2,
-                                  traversal=3)
-        torch.cuda.synchronize()
-        assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"wave r2={r2}")
+        for trav in (3, 4):
+            gi, gd = knn.knn_query_ex(t, dev(X[ids[:1]]), 5, self_ids=dev(ids[:1]), r2_max=r2,
+                                      traversal=trav, team_lanes=8)
+            torch.cuda.synchronize()
+            assert_same(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd, f"form {trav} r2={r2}")
+    with pytest.raises(knn.KnnError):
+        knn.knn_query_ex(t, dev(X[ids]), 5, traversal=4, team_lanes=12)
     t.free()
