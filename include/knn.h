@@ -41,6 +41,7 @@ extern "C" {
 #define KNN_MAX_K 64    /* neighbours per query: 1..KNN_MAX_K */
 
 typedef struct knn_tree knn_tree; /* opaque; owns all device memory of one tree */
+typedef struct knn_build_plan knn_build_plan; /* opaque; see knn_build_plan_create */
 
 /* Construction parameters (Section III-A1).  Zero selects the default. */
 typedef struct {
@@ -160,6 +161,52 @@ int knn_build_ex(const float* points, int64_t n, int32_t dim, const knn_build_pa
  */
 int knn_build_batch(const float* points, const int64_t* offsets, int32_t trees, int32_t dim,
                     const knn_build_params* p, void* stream, knn_tree** out);
+
+/*
+ * Build plans -- the build of Section III-A (as knn_build_batch) for a fixed
+ * point count and forest layout, split into a set-up call that allocates and
+ * uploads everything once, and runs that only enqueue kernels.  A run
+ * allocates nothing, copies nothing between host and device and never waits,
+ * so a HIP graph can capture it (queries on the plan's tree may follow it in
+ * the same graph) and replay it over new point values.  A successful run
+ * builds exactly the tree knn_build_batch builds from the same points.
+ *
+ * knn_build_plan_create(n, dim, offsets, trees, p, stream, out)
+ *   n, dim     as knn_build_ex
+ *   offsets    HOST pointer [trees + 1] as knn_build_batch, with offsets[trees]
+ *              = n; or NULL with trees = 1 (one tree over all n points).
+ *              Read during the call only.
+ *   p          as knn_build_ex, except max_depth 0 = the largest tree's balanced
+ *              depth + 8.  max_depth bounds every run and is the depth the
+ *              plan's tree reports (query kernels size their stacks by it).
+ *   stream     carries the one-time uploads; the call waits for them
+ *   out        receives the plan.  Errors: KNN_EINVAL, KNN_ENOMEM.
+ * knn_build_plan_run(plan, points, stream)
+ *   points     device pointer [n, dim] FP32 (same layout as knn_build_batch)
+ *   Enqueued on stream and not waited for.  Runs of one plan must not
+ *   overlap.  Input errors found on the device (a non-finite coordinate, a
+ *   tree deeper than max_depth, more level passes than the plan holds) are
+ *   recorded there; the tree then answers every query with index -1 in all
+ *   k places until a run succeeds.
+ * knn_build_plan_finish(plan, stream, tree)
+ *   Waits for stream and returns the status of the latest run it carried:
+ *   KNN_OK, KNN_ENOTFINITE, KNN_EDEPTH or KNN_EDEVICE.  *tree (if tree is not
+ *   NULL) receives the plan's tree, with its node count updated.
+ * knn_build_plan_tree(plan)
+ *   The plan's tree, without waiting (to capture queries after a run).  It
+ *   belongs to the plan (knn_tree_free refuses it), is the same handle for the
+ *   plan's whole life, and holds the latest completed run's tree.
+ * knn_build_plan_destroy(plan)
+ *   Waits for the queries on the plan's tree and the latest run enqueued
+ *   outside a capture, then frees all of the plan's device memory.  Graph
+ *   launches are the caller's to wait for.  NULL is a no-op.
+ */
+int knn_build_plan_create(int64_t n, int32_t dim, const int64_t* offsets, int32_t trees,
+                          const knn_build_params* p, void* stream, knn_build_plan** out);
+int knn_build_plan_run(knn_build_plan* plan, const float* points, void* stream);
+int knn_build_plan_finish(knn_build_plan* plan, void* stream, knn_tree** tree);
+knn_tree* knn_build_plan_tree(knn_build_plan* plan);
+int knn_build_plan_destroy(knn_build_plan* plan);
 
 /*
  * knn_query -- the k nearest neighbours of m queries (Algorithm 1).

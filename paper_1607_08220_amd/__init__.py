@@ -69,6 +69,8 @@ EXPORTED = ("knn_build", "knn_build_ex", "knn_build_batch", "knn_query", "knn_qu
             "knn_query_noalloc", "knn_query_batch", "knn_query_radius", "knn_merge", "knn_classify", "knn_regress",
             "knn_server_create", "knn_server_create_ex",
             "knn_server_submit", "knn_server_wait", "knn_server_stats", "knn_server_destroy",
+            "knn_build_plan_create", "knn_build_plan_run", "knn_build_plan_finish",
+            "knn_build_plan_tree", "knn_build_plan_destroy",
             "knn_tree_free", "knn_tree_errors", "knn_tree_info", "knn_tree_export",
             "knn_last_error", "knn_strerror", "knn_release_memory", "knn_set_profiling",
             "knn_get_profile")
@@ -89,6 +91,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(vp)]
     lib.knn_build_batch.argtypes = [vp, vp, i32, i32, ctypes.POINTER(_BuildParams), vp,
                                     ctypes.POINTER(vp)]
+    lib.knn_build_plan_create.argtypes = [i64, i32, vp, i32, ctypes.POINTER(_BuildParams), vp,
+                                          ctypes.POINTER(vp)]
+    lib.knn_build_plan_run.argtypes = [vp, vp, vp]
+    lib.knn_build_plan_finish.argtypes = [vp, vp, ctypes.POINTER(vp)]
+    lib.knn_build_plan_tree.argtypes = [vp]
+    lib.knn_build_plan_destroy.argtypes = [vp]
     lib.knn_query.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     lib.knn_query_batch.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.c_float,
                                     ctypes.POINTER(_QueryParams), vp, vp, vp]
@@ -121,8 +129,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.knn_set_profiling.argtypes = [i32]
     lib.knn_get_profile.argtypes = [ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTED:
-        if name not in ("knn_last_error", "knn_strerror"):
+        if name not in ("knn_last_error", "knn_strerror", "knn_build_plan_tree"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.knn_build_plan_tree.restype = vp
     _lib = lib
     return lib
 
@@ -152,10 +161,11 @@ def _dev_f32(t, name, cols=None):
 class Tree:
     """A kd-tree resident in device memory (owns it until free())."""
 
-    def __init__(self, handle: int, dim: int, device):
+    def __init__(self, handle: int, dim: int, device, owned: bool = True):
         self._h = ctypes.c_void_p(handle)
         self.dim = dim
         self.device = device
+        self._owned = owned  # False: a build plan's tree, freed with the plan
 
     @property
     def handle(self):
@@ -175,7 +185,8 @@ class Tree:
 
     def free(self):
         if self._h.value:
-            _check(load_library().knn_tree_free(self._h))
+            if self._owned:
+                _check(load_library().knn_tree_free(self._h))
             self._h = ctypes.c_void_p(0)
 
     def __del__(self):
@@ -223,6 +234,93 @@ def knn_build_batch(points, offsets, leaf_size: int = 0, max_depth: int = 0,
                                points.shape[1], ctypes.byref(p), _stream(points),
                                ctypes.byref(out)))
     return Tree(out.value, points.shape[1], points.device)
+
+
+class BuildPlan:
+    """A build plan (knn_build_plan_*): the kd-tree build for a fixed point
+    count, dimension and forest layout (``offsets``, host sequence, or None
+    for one tree), with all device memory taken at creation.  ``run(points)``
+    only enqueues kernels on the current stream (no allocation, copy or wait),
+    so it can be captured in a ``torch.cuda.CUDAGraph`` and replayed over new
+    point values; ``finish()`` waits and raises the latest run's error.
+    ``tree`` is the plan's tree (the same handle for the plan's life)."""
+
+    def __init__(self, n: int, dim: int, offsets=None, leaf_size: int = 0, max_depth: int = 0,
+                 subtree_points: int = 0, split_block_nodes: int = 0, device=None):
+        import torch
+        lib = load_library()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.n, self.dim = int(n), int(dim)
+        off_ptr, trees = None, 1
+        if offsets is not None:
+            off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+            if off.ndim != 1 or len(off) < 2 or off[-1] != n:
+                raise ValueError("offsets must be trees + 1 values ending at n")
+            self._off = off
+            off_ptr, trees = off.ctypes.data_as(ctypes.c_void_p), len(off) - 1
+        p = _BuildParams(leaf_size, max_depth, subtree_points, split_block_nodes)
+        out = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            _check(lib.knn_build_plan_create(self.n, self.dim, off_ptr, trees, ctypes.byref(p), st,
+                                             ctypes.byref(out)))
+        self._h = out
+        self.tree = Tree(lib.knn_build_plan_tree(self._h), self.dim, self.device, owned=False)
+
+    @property
+    def handle(self):
+        if not self._h.value:
+            raise ValueError("plan already destroyed")
+        return self._h
+
+    def run(self, points):
+        _dev_f32(points, "points", self.dim)
+        if points.shape[0] != self.n:
+            raise ValueError(f"points has {points.shape[0]} rows, the plan {self.n}")
+        _check(load_library().knn_build_plan_run(self.handle, ctypes.c_void_p(points.data_ptr()),
+                                                 _stream(points)))
+
+    def finish(self) -> Tree:
+        import torch
+        out = ctypes.c_void_p()
+        st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        _check(load_library().knn_build_plan_finish(self.handle, st, ctypes.byref(out)))
+        return self.tree
+
+    def destroy(self):
+        if self._h.value:
+            self.tree._h = ctypes.c_void_p(0)
+            _check(load_library().knn_build_plan_destroy(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def knn_build_plan_create(n: int, dim: int, offsets=None, leaf_size: int = 0,
+                          max_depth: int = 0, subtree_points: int = 0,
+                          split_block_nodes: int = 0) -> BuildPlan:
+    return BuildPlan(n, dim, offsets=offsets, leaf_size=leaf_size, max_depth=max_depth,
+                     subtree_points=subtree_points, split_block_nodes=split_block_nodes)
+
+
+def knn_build_plan_run(plan: BuildPlan, points) -> None:
+    plan.run(points)
+
+
+def knn_build_plan_finish(plan: BuildPlan) -> Tree:
+    return plan.finish()
+
+
+def knn_build_plan_tree(plan: BuildPlan) -> Tree:
+    return plan.tree
+
+
+def knn_build_plan_destroy(plan: BuildPlan) -> None:
+    plan.destroy()
 
 
 def _outputs(queries, k, out):

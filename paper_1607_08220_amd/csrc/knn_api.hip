@@ -199,6 +199,38 @@ const char* knn_strerror(int code)
 
 namespace {
 
+// Build parameters with defaults filled in (max_depth stays 0 if unset).
+struct BuildArgs {
+    int32_t leaf, max_depth, W;
+    int64_t sbn;
+};
+
+int build_args(int32_t dim, const knn_build_params* p, BuildArgs* a)
+{
+    if (dim < 1 || dim > KNN_MAX_DIM) return fail(KNN_EINVAL, "dim must be in [1, 16]");
+    knn_build_params q = p ? *p : knn_build_params{0, 0, 0, 0};
+    if (q.leaf_size < 0 || q.max_depth < 0 || q.subtree_points < 0 || q.split_block_nodes < -1)
+        return fail(KNN_EINVAL, "negative build parameter");
+    if (q.max_depth > 4096) return fail(KNN_EINVAL, "max_depth too large");
+    a->leaf = q.leaf_size ? q.leaf_size : kDefaultLeaf;
+    a->max_depth = q.max_depth;
+    a->W = subtree_points_for(dim, q.subtree_points);
+    a->sbn = q.split_block_nodes ? std::max(q.split_block_nodes, 0) : kDefaultSplitBlockNodes;
+    return KNN_OK;
+}
+
+// offsets[0 .. trees]: 0, strictly increasing (every tree holds a point), at most 2^30.
+int check_offsets(const int64_t* offsets, int32_t trees)
+{
+    if (!offsets) return fail(KNN_EINVAL, "offsets is NULL");
+    if (trees < 1) return fail(KNN_EINVAL, "trees must be >= 1");
+    if (offsets[0] != 0) return fail(KNN_EINVAL, "offsets[0] must be 0");
+    for (int32_t t = 0; t < trees; ++t)
+        if (offsets[t + 1] <= offsets[t]) return fail(KNN_EINVAL, "every tree needs >= 1 point");
+    if (offsets[trees] > kMaxPoints) return fail(KNN_EINVAL, "more than 2^30 points in all");
+    return KNN_OK;
+}
+
 int build_common(const float* points, int64_t n, int32_t dim, const int64_t* offsets,
                  int32_t trees, const knn_build_params* p, void* stream, knn_tree** out)
 {
@@ -206,17 +238,10 @@ int build_common(const float* points, int64_t n, int32_t dim, const int64_t* off
     *out = nullptr;
     if (!points) return fail(KNN_EINVAL, "points is NULL");
     if (n < 1 || n > kMaxPoints) return fail(KNN_EINVAL, "n must be in [1, 2^30]");
-    if (dim < 1 || dim > KNN_MAX_DIM) return fail(KNN_EINVAL, "dim must be in [1, 16]");
-    knn_build_params q = p ? *p : knn_build_params{0, 0, 0, 0};
-    if (q.leaf_size < 0 || q.max_depth < 0 || q.subtree_points < 0 || q.split_block_nodes < -1)
-        return fail(KNN_EINVAL, "negative build parameter");
-    const int32_t leaf = q.leaf_size ? q.leaf_size : kDefaultLeaf;
-    const int32_t max_depth = q.max_depth ? q.max_depth : kDefaultMaxDepth;
-    if (max_depth > 4096) return fail(KNN_EINVAL, "max_depth too large");
-    const int32_t W = subtree_points_for(dim, q.subtree_points);
-    const int64_t sbn = q.split_block_nodes ? std::max(q.split_block_nodes, 0) : kDefaultSplitBlockNodes;
-    return build_tree(points, n, dim, leaf, max_depth, W, sbn, offsets, trees,
-                      static_cast<hipStream_t>(stream), out);
+    BuildArgs a{};
+    if (int rc = build_args(dim, p, &a)) return rc;
+    return build_tree(points, n, dim, a.leaf, a.max_depth ? a.max_depth : kDefaultMaxDepth, a.W,
+                      a.sbn, offsets, trees, static_cast<hipStream_t>(stream), out);
 }
 
 }  // namespace
@@ -232,13 +257,54 @@ int knn_build_batch(const float* points, const int64_t* offsets, int32_t trees, 
                     const knn_build_params* p, void* stream, knn_tree** out)
 {
     if (out) *out = nullptr;
-    if (!offsets) return fail(KNN_EINVAL, "offsets is NULL");
-    if (trees < 1) return fail(KNN_EINVAL, "trees must be >= 1");
-    if (offsets[0] != 0) return fail(KNN_EINVAL, "offsets[0] must be 0");
-    for (int32_t t = 0; t < trees; ++t)
-        if (offsets[t + 1] <= offsets[t]) return fail(KNN_EINVAL, "every tree needs >= 1 point");
-    if (offsets[trees] > kMaxPoints) return fail(KNN_EINVAL, "more than 2^30 points in all");
+    if (int rc = check_offsets(offsets, trees)) return rc;
     return build_common(points, offsets[trees], dim, offsets, trees, p, stream, out);
+}
+
+int knn_build_plan_create(int64_t n, int32_t dim, const int64_t* offsets, int32_t trees,
+                          const knn_build_params* p, void* stream, knn_build_plan** out)
+{
+    if (!out) return fail(KNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > kMaxPoints) return fail(KNN_EINVAL, "n must be in [1, 2^30]");
+    const int64_t one[2] = {0, n};
+    if (!offsets) {
+        if (trees != 1) return fail(KNN_EINVAL, "offsets is NULL with trees != 1");
+        offsets = one;
+    }
+    if (int rc = check_offsets(offsets, trees)) return rc;
+    if (offsets[trees] != n) return fail(KNN_EINVAL, "offsets[trees] must equal n");
+    BuildArgs a{};
+    if (int rc = build_args(dim, p, &a)) return rc;
+    return plan_create(n, dim, offsets, trees, a.leaf, a.max_depth, a.W, a.sbn,
+                       static_cast<hipStream_t>(stream), out);
+}
+
+int knn_build_plan_run(knn_build_plan* plan, const float* points, void* stream)
+{
+    if (!plan) return fail(KNN_EINVAL, "plan is NULL");
+    if (!points) return fail(KNN_EINVAL, "points is NULL");
+    DeviceGuard g(plan_device(plan));
+    return plan_run(plan, points, static_cast<hipStream_t>(stream));
+}
+
+int knn_build_plan_finish(knn_build_plan* plan, void* stream, knn_tree** tree)
+{
+    if (tree) *tree = nullptr;
+    if (!plan) return fail(KNN_EINVAL, "plan is NULL");
+    DeviceGuard g(plan_device(plan));
+    const int rc = plan_finish(plan, static_cast<hipStream_t>(stream));
+    if (tree) *tree = plan_tree(plan);
+    return rc;
+}
+
+knn_tree* knn_build_plan_tree(knn_build_plan* plan) { return plan ? plan_tree(plan) : nullptr; }
+
+int knn_build_plan_destroy(knn_build_plan* plan)
+{
+    if (!plan) return KNN_OK;
+    DeviceGuard g(plan_device(plan));
+    return plan_destroy(plan);
 }
 
 int knn_build(const float* points, int64_t n, int32_t dim, int32_t leaf_size, void* stream,
@@ -357,6 +423,7 @@ int knn_query(const knn_tree* t, const float* queries, int64_t m, int32_t k, int
 int knn_tree_free(knn_tree* t)
 {
     if (!t) return KNN_OK;
+    if (t->plan_owned) return fail(KNN_EINVAL, "the tree belongs to a build plan");
     DeviceGuard g(t->device);
     int rc = KNN_OK;
     {   // wait for the latest query on every stream that queried the tree; the

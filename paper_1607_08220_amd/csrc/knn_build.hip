@@ -35,7 +35,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
+#include <vector>
 
 #include "knn_internal.h"
 
@@ -738,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_count(Level L, const int32_t* __rest
 
 // Children of a split node that need another level pass: more than W
 // points and more than the bucket size.
-__device__ inline bool needs_level_pass(int c, int W, int leaf) { return c > W && c > leaf; }
+__host__ __device__ inline bool needs_level_pass(int c, int W, int leaf) { return c > W && c > leaf; }
 
 // Per-node exclusive scan of the block counts (the left count before each
 // block), the node's left count, and the node's plan counters: split (0/1),
@@ -1513,18 +1515,15 @@ __device__ int finish_global(const FinishCtx& cx, const float* __restrict__ scol
 // the index permutation ping-pongs between two arrays, and each bucket's
 // packed rows are written as soon as the bucket is final.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_finish(
-    const SubEntry* __restrict__ subs, int32_t n_sub, float* colsA, int32_t* idxA, float* colsB,
-    int32_t* idxB, int64_t n, int leaf, int W, int max_depth,
+__device__ inline void finish_subtree(
+    int sub, unsigned char* smem, const SubEntry* __restrict__ subs, float* colsA, int32_t* idxA,
+    float* colsB, int32_t* idxB, int64_t n, int leaf, int W, int max_depth,
     size_t per_wave, float* __restrict__ pts, NodeRec* __restrict__ tnodes,
     float* __restrict__ tbox, int32_t* __restrict__ sub_nodes, int32_t* __restrict__ err,
     int32_t* __restrict__ depth_seen)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     constexpr int D2 = 2 * D;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int sub = blockIdx.x * kWavesPerBlock + w;
-    if (sub >= n_sub) return;  // only wavefront-level synchronization below
     const SubEntry e = subs[sub];
     const float* cols = e.buf ? colsB : colsA;
     const int32_t* gidx = e.buf ? idxB : idxA;
@@ -1655,10 +1654,31 @@ __global__ __launch_bounds__(kBlock) void k_finish(
     }
 }
 
+// One wavefront per subtree; subtrees beyond the grid are taken in strides
+// (the count comes from n_sub, or from *n_sub_dev when that is set, for
+// launches whose grid is fixed before the count is known).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_finish(
+    const SubEntry* __restrict__ subs, int32_t n_sub, const int32_t* __restrict__ n_sub_dev,
+    float* colsA, int32_t* idxA, float* colsB, int32_t* idxB, int64_t n, int leaf, int W,
+    int max_depth, size_t per_wave, float* __restrict__ pts, NodeRec* __restrict__ tnodes,
+    float* __restrict__ tbox, int32_t* __restrict__ sub_nodes, int32_t* __restrict__ err,
+    int32_t* __restrict__ depth_seen)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int total = n_sub_dev ? __builtin_amdgcn_readfirstlane(*n_sub_dev) : n_sub;
+    // only wavefront-level synchronization below
+    for (int sub = blockIdx.x * kWavesPerBlock + w; sub < total; sub += gridDim.x * kWavesPerBlock)
+        finish_subtree<D>(sub, smem, subs, colsA, idxA, colsB, idxB, n, leaf, W, max_depth,
+                          per_wave, pts, tnodes, tbox, sub_nodes, err, depth_seen);
+}
+
 // Final ids: subtree root keeps its level-pass id, local node j >= 1 becomes
 // sub_base + j - 1.
 __global__ __launch_bounds__(kBlock) void k_compact(const SubEntry* __restrict__ subs,
                                                     int32_t n_sub,
+                                                    const int32_t* __restrict__ n_sub_dev,
                                                     const int32_t* __restrict__ sub_nodes,
                                                     const int32_t* __restrict__ sub_base,
                                                     const NodeRec* __restrict__ tnodes,
@@ -1667,8 +1687,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(const SubEntry* __restrict__
                                                     float* __restrict__ bbox)
 {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int sub = blockIdx.x * kWavesPerBlock + w;
-    if (sub >= n_sub) return;
+    const int total = n_sub_dev ? __builtin_amdgcn_readfirstlane(*n_sub_dev) : n_sub;
+    for (int sub = blockIdx.x * kWavesPerBlock + w; sub < total; sub += gridDim.x * kWavesPerBlock) {
     const SubEntry e = subs[sub];
     const int cnt = sub_nodes[sub];
     const int base = sub_base[sub];
@@ -1685,6 +1705,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const SubEntry* __restrict__
         const int g = gid(j);
         nodes[g] = o;
         for (int t = 0; t < D2; ++t) bbox[(int64_t)g * D2 + t] = tbox[(2 * gs + j) * D2 + t];
+    }
     }
 }
 
@@ -1898,6 +1919,32 @@ __global__ __launch_bounds__(kBlock) void k_plan_fill(Level nxt)
     }
 }
 
+// Int32 words of one Level with the given capacities.
+inline size_t level_words(int64_t nn_cap, int64_t nb_cap, int64_t nbh_cap)
+{
+    return 8 * (size_t)nn_cap + 2 * (size_t)nb_cap + 2 * (size_t)nbh_cap + 4;
+}
+
+// The arrays of one Level laid out in level_words() words at p.
+inline Level carve_level(int32_t* p, int64_t nn_cap, int64_t nb_cap, int64_t nbh_cap)
+{
+    Level L{};
+    L.start = p; p += nn_cap;
+    L.count = p; p += nn_cap;
+    L.id = p; p += nn_cap;
+    L.parent = p; p += nn_cap;
+    L.depth = p; p += nn_cap;
+    L.blk0 = p; p += nn_cap;
+    L.nblk = p; p += nn_cap;
+    L.bnode = p; p += nb_cap;
+    L.bbeg = p; p += nb_cap;
+    L.hnode = p; p += nbh_cap;
+    L.hbeg = p; p += nbh_cap;
+    L.hblk0 = p; p += nn_cap;
+    L.cnt = p;
+    return L;
+}
+
 // Device buffers of one Level with the given capacities.
 struct LevelMem {
     DevBuf mem;
@@ -1905,29 +1952,15 @@ struct LevelMem {
     explicit LevelMem(hipStream_t s) : mem(s) {}
     hipError_t alloc(int64_t nn_cap, int64_t nb_cap, int64_t nbh_cap)
     {
-        const size_t ints = 8 * (size_t)nn_cap + 2 * (size_t)nb_cap + 2 * (size_t)nbh_cap + 4;
-        hipError_t e = mem.alloc(sizeof(int32_t) * ints);
+        hipError_t e = mem.alloc(sizeof(int32_t) * level_words(nn_cap, nb_cap, nbh_cap));
         if (e != hipSuccess) return e;
-        int32_t* p = mem.as<int32_t>();
-        L.start = p; p += nn_cap;
-        L.count = p; p += nn_cap;
-        L.id = p; p += nn_cap;
-        L.parent = p; p += nn_cap;
-        L.depth = p; p += nn_cap;
-        L.blk0 = p; p += nn_cap;
-        L.nblk = p; p += nn_cap;
-        L.bnode = p; p += nb_cap;
-        L.bbeg = p; p += nb_cap;
-        L.hnode = p; p += nbh_cap;
-        L.hbeg = p; p += nbh_cap;
-        L.hblk0 = p; p += nn_cap;
-        L.cnt = p;
+        L = carve_level(mem.as<int32_t>(), nn_cap, nb_cap, nbh_cap);
         return hipSuccess;
     }
 };
 
-using FinishFn = void (*)(const SubEntry*, int32_t, float*, int32_t*, float*, int32_t*,
-                          int64_t, int, int, int, size_t, float*, NodeRec*,
+using FinishFn = void (*)(const SubEntry*, int32_t, const int32_t*, float*, int32_t*, float*,
+                          int32_t*, int64_t, int, int, int, size_t, float*, NodeRec*,
                           float*, int32_t*, int32_t*, int32_t*);
 
 FinishFn finish_for(int d)
@@ -1947,6 +1980,122 @@ FinishFn finish_for(int d)
 }
 
 inline unsigned blocks_for(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
+
+// The host side of level 0.  Tree t has root node t.  Roots of at most W
+// points (or at most a bucket) go straight to the subtree finish; the
+// others form level 0, with their block tables.
+struct Level0Host {
+    std::vector<int32_t> f[8];  // per large root: start, count, id, parent, depth, blk0, nblk, hblk0
+    std::vector<int32_t> bnode, bbeg, hnode, hbeg;
+    std::vector<SubEntry> small;
+    std::vector<int32_t> big_roots;
+    int64_t largest = 0;
+};
+
+Level0Host level0_tables(const int64_t* offsets, int32_t T, int32_t W, int32_t leaf)
+{
+    Level0Host h;
+    for (int32_t r = 0; r < T; ++r) {
+        const int64_t c = offsets[r + 1] - offsets[r];
+        if (!needs_level_pass((int)c, W, leaf)) {
+            h.small.push_back(SubEntry{(int32_t)offsets[r], (int32_t)c, r, -1, 0, 0, 0, 0});
+            continue;
+        }
+        const int32_t i = (int32_t)h.big_roots.size();
+        h.big_roots.push_back(r);
+        h.largest = std::max(h.largest, c);
+        const int32_t nb = (int32_t)((c + kChunk - 1) / kChunk);
+        const int32_t nbh = (int32_t)((c + kHistChunk - 1) / kHistChunk);
+        const int32_t vals[8] = {(int32_t)offsets[r], (int32_t)c, r, -1, 0,
+                                 (int32_t)h.bnode.size(), nb, (int32_t)h.hnode.size()};
+        for (int k = 0; k < 8; ++k) h.f[k].push_back(vals[k]);
+        for (int32_t j = 0; j < nb; ++j) {
+            h.bnode.push_back(i);
+            h.bbeg.push_back(j * kChunk);
+        }
+        for (int32_t j = 0; j < nbh; ++j) {
+            h.hnode.push_back(i);
+            h.hbeg.push_back(j * kHistChunk);
+        }
+    }
+    return h;
+}
+
+// Level passes a tree of `largest` points needs when every split halves.
+int expected_levels(int64_t largest, int32_t W, int32_t leaf)
+{
+    int e = 1;
+    for (int64_t c = largest; c > W && c > leaf; c = (c + 1) / 2) ++e;
+    return e;
+}
+
+// Buffers and sizes shared by every level pass of one build.
+struct LevelWork {
+    float* cols[2];       // SoA coordinates: the pass reads cols[buf], writes cols[buf ^ 1]
+    int32_t* idx[2];      // original indices, likewise
+    int32_t* dimv;
+    float* splitv;
+    int32_t* nleft;
+    float* samples;
+    uint32_t* hist;
+    uint32_t* wave_left;
+    uint32_t* blk_off;
+    int32_t* planv;
+    int32_t* planx;
+    int32_t* pblk;
+    NodeRec* big;         // level-pass node records by id
+    SubEntry* subs;       // subtree list
+    int32_t* rng;         // id range of each depth's level-pass nodes
+    int32_t* g;           // build counters
+    int64_t n;
+    int d, leaf, W, max_depth;
+    int64_t split_block_nodes;
+    int64_t nn0;          // nodes of level 0
+    int64_t nn_cap, nb_cap, nbh_cap, big_cap, sub_cap;
+};
+
+// Enqueues one level pass (B1-B7) over the nodes of `cur`, writing the next
+// level into `nxt`.  Grids are sized for the largest level possible at this
+// depth; the kernels read the actual counts from cur.cnt on the device.
+void enqueue_level(const LevelWork& w, const Level& cur, const Level& nxt, int level, int buf,
+                   bool prof, hipStream_t st)
+{
+    const int64_t n = w.n;
+    const int64_t nn_l = std::min<int64_t>(level < 40 ? w.nn0 << std::min(level, 40) : w.nn_cap,
+                                           w.nn_cap);
+    const unsigned g_nn = (unsigned)nn_l;
+    const unsigned g_nb = (unsigned)std::min<int64_t>(n / kChunk + nn_l + 1, w.nb_cap);
+    const unsigned g_nbh = (unsigned)std::min<int64_t>(n / kHistChunk + nn_l + 1, w.nbh_cap);
+    const float* src = w.cols[buf];
+    const int32_t* srci = w.idx[buf];
+    float* dst = w.cols[buf ^ 1];
+    int32_t* dsti = w.idx[buf ^ 1];
+    const unsigned g_nw = (g_nn + kWavesPerBlock - 1) / kWavesPerBlock;
+    k_sample<<<g_nw, kBlock, 0, st>>>(cur, src, n, w.d, w.samples, w.dimv, w.hist);
+    k_hist<<<g_nbh, kBlock, 0, st>>>(cur, w.dimv, w.samples, src, n, w.hist);
+    if (nn_l <= w.split_block_nodes)  // few large nodes: a block each
+        k_choose<<<g_nn, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, src, n, w.d, w.splitv);
+    else
+        k_choose_wave<<<g_nw, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, src, n, w.d,
+                                               w.splitv);
+    k_count<<<g_nb, kBlock, 0, st>>>(cur, w.dimv, w.splitv, src, n, w.wave_left);
+    k_blkscan<<<g_nn, kBlock, 0, st>>>(cur, w.wave_left, w.dimv, w.W, w.leaf, w.blk_off, w.nleft,
+                                       w.planv);
+    if (prof) prof_part_mark(st);
+    k_scatter<<<g_nb, kBlock, 0, st>>>(cur, w.dimv, w.splitv, w.blk_off, w.nleft, src, srci, dst,
+                                       dsti, n, w.d);
+    if (prof) prof_part_mark(st);
+    k_plan_local<<<blocks_for(nn_l, kPlanBlock), kPlanBlock, 0, st>>>(cur, w.planv, w.planx,
+                                                                       w.pblk, w.g);
+    k_plan_top<<<1, kPlanBlock, 0, st>>>(cur, nxt, w.pblk, w.g, w.rng, level, w.big_cap,
+                                         w.sub_cap, w.nn_cap, w.nb_cap, w.nbh_cap);
+    k_plan_write<<<blocks_for(nn_l, kBlock), kBlock, 0, st>>>(
+        cur, nxt, w.dimv, w.splitv, w.nleft, w.planx, w.pblk, w.leaf, w.W, w.max_depth, buf ^ 1,
+        w.big, w.subs, w.g);
+    const int64_t nn_next = std::min<int64_t>(2 * nn_l, w.nn_cap);
+    const int64_t fill = std::min<int64_t>(n / kChunk + nn_next + 1, w.nb_cap);
+    k_plan_fill<<<blocks_for(fill, kBlock), kBlock, 0, st>>>(nxt);
+}
 
 }  // namespace
 
@@ -2006,7 +2155,6 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     prof_mark(st, 1);
 
     // ---- level passes: nodes above W points (and above the bucket size) -------
-    auto needs_level = [&](int64_t c) { return c > W && c > leaf; };
     // a level's nodes hold more than W points each and are disjoint
     const int64_t nn_cap = n / (W + 1) + 1;
     const int64_t nb_cap = n / kChunk + nn_cap + 1;
@@ -2020,20 +2168,10 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         d_big(st), d_subs(st), d_rng(st), planv(st), planx(st), pblk(st);
     int32_t n_sub = 0, n_big = T, n_levels = 1;
     std::vector<int32_t> h_g(G_COUNT, 0);
-    // Tree t has root node t.  Roots of at most W points (or at most a bucket)
-    // go straight to the subtree finish; the others form level 0.
-    std::vector<SubEntry> small;
-    std::vector<int32_t> big_roots;
-    int64_t largest = 0;
-    for (int32_t r = 0; r < T; ++r) {
-        const int64_t c = offsets[r + 1] - offsets[r];
-        if (needs_level(c)) {
-            big_roots.push_back(r);
-            largest = std::max(largest, c);
-        } else {
-            small.push_back(SubEntry{(int32_t)offsets[r], (int32_t)c, r, -1, 0, 0, 0, 0});
-        }
-    }
+    const Level0Host h0 = level0_tables(offsets, T, W, leaf);
+    const std::vector<SubEntry>& small = h0.small;
+    const std::vector<int32_t>& big_roots = h0.big_roots;
+    const int64_t largest = h0.largest;
     const int32_t r0[2] = {0, T};
     if (big_roots.empty()) {
         n_sub = (int32_t)small.size();
@@ -2062,25 +2200,8 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2 * (lv_cap + 1)));
         {   // level 0: the large roots and their block tables
             const int32_t nn0 = (int32_t)big_roots.size();
-            std::vector<int32_t> f[8];  // start, count, id, parent, depth, blk0, nblk, hblk0
-            std::vector<int32_t> bnode, bbeg, hnode, hbeg;
-            for (int32_t i = 0; i < nn0; ++i) {
-                const int32_t r = big_roots[i];
-                const int64_t c = offsets[r + 1] - offsets[r];
-                const int32_t nb = (int32_t)((c + kChunk - 1) / kChunk);
-                const int32_t nbh = (int32_t)((c + kHistChunk - 1) / kHistChunk);
-                const int32_t vals[8] = {(int32_t)offsets[r], (int32_t)c, r, -1, 0,
-                                         (int32_t)bnode.size(), nb, (int32_t)hnode.size()};
-                for (int k = 0; k < 8; ++k) f[k].push_back(vals[k]);
-                for (int32_t j = 0; j < nb; ++j) {
-                    bnode.push_back(i);
-                    bbeg.push_back(j * kChunk);
-                }
-                for (int32_t j = 0; j < nbh; ++j) {
-                    hnode.push_back(i);
-                    hbeg.push_back(j * kHistChunk);
-                }
-            }
+            const auto& f = h0.f;
+            const auto &bnode = h0.bnode, &bbeg = h0.bbeg, &hnode = h0.hnode, &hbeg = h0.hbeg;
             const Level& L0 = lvA.L;
             int32_t* dst[8] = {L0.start, L0.count, L0.id, L0.parent, L0.depth, L0.blk0, L0.nblk,
                                L0.hblk0};
@@ -2106,56 +2227,43 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
             KNN_HIP(hipStreamSynchronize(st));  // the host staging vectors die here
         }
         // levels expected for balanced splits; the host checks for more after that
-        int expected = 1;
-        for (int64_t c = largest; needs_level(c); c = (c + 1) / 2) ++expected;
+        const int expected = expected_levels(largest, W, leaf);
+        LevelWork lw{};
+        lw.cols[0] = colsA.as<float>();
+        lw.cols[1] = colsB.as<float>();
+        lw.idx[0] = idxA.as<int32_t>();
+        lw.idx[1] = idxB.as<int32_t>();
+        lw.dimv = dimv.as<int32_t>();
+        lw.splitv = splitv.as<float>();
+        lw.nleft = nleft.as<int32_t>();
+        lw.samples = samples.as<float>();
+        lw.hist = hist.as<uint32_t>();
+        lw.wave_left = wave_left.as<uint32_t>();
+        lw.blk_off = blk_off.as<uint32_t>();
+        lw.planv = planv.as<int32_t>();
+        lw.planx = planx.as<int32_t>();
+        lw.pblk = pblk.as<int32_t>();
+        lw.big = d_big.as<NodeRec>();
+        lw.subs = d_subs.as<SubEntry>();
+        lw.rng = d_rng.as<int32_t>();
+        lw.g = g;
+        lw.n = n;
+        lw.d = d;
+        lw.leaf = leaf;
+        lw.W = W;
+        lw.max_depth = max_depth;
+        lw.split_block_nodes = split_block_nodes;
+        lw.nn0 = (int64_t)big_roots.size();
+        lw.nn_cap = nn_cap;
+        lw.nb_cap = nb_cap;
+        lw.nbh_cap = nbh_cap;
+        lw.big_cap = big_cap;
+        lw.sub_cap = sub_cap;
         Level cur = lvA.L, nxt = lvB.L;
         int buf = 0;
         for (int level = 0;; ++level) {
             if (level >= lv_cap) return fail(KNN_EDEPTH, "tree deeper than max_depth");
-            const int64_t nn_l = std::min<int64_t>(
-                level < 40 ? (int64_t)big_roots.size() << std::min(level, 40) : nn_cap, nn_cap);
-            const unsigned g_nn = (unsigned)nn_l;
-            const unsigned g_nb = (unsigned)std::min<int64_t>(n / kChunk + nn_l + 1, nb_cap);
-            const unsigned g_nbh = (unsigned)std::min<int64_t>(n / kHistChunk + nn_l + 1, nbh_cap);
-            const float* src = (buf ? colsB : colsA).as<float>();
-            const int32_t* srci = (buf ? idxB : idxA).as<int32_t>();
-            float* dst = (buf ? colsA : colsB).as<float>();
-            int32_t* dsti = (buf ? idxA : idxB).as<int32_t>();
-            k_sample<<<(g_nn + kWavesPerBlock - 1) / kWavesPerBlock, kBlock, 0, st>>>(cur, src, n, d, samples.as<float>(),
-                                              dimv.as<int32_t>(), hist.as<uint32_t>());
-            k_hist<<<g_nbh, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), samples.as<float>(), src, n,
-                                             hist.as<uint32_t>());
-            if (nn_l <= split_block_nodes)  // few large nodes: a block each
-                k_choose<<<g_nn, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), samples.as<float>(),
-                                                  hist.as<uint32_t>(), src, n, d, splitv.as<float>());
-            else
-                k_choose_wave<<<(g_nn + kWavesPerBlock - 1) / kWavesPerBlock, kBlock, 0, st>>>(
-                    cur, dimv.as<int32_t>(), samples.as<float>(), hist.as<uint32_t>(), src, n, d,
-                    splitv.as<float>());
-            k_count<<<g_nb, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), splitv.as<float>(), src, n,
-                                             wave_left.as<uint32_t>());
-            k_blkscan<<<g_nn, kBlock, 0, st>>>(cur, wave_left.as<uint32_t>(), dimv.as<int32_t>(), W,
-                                               leaf, blk_off.as<uint32_t>(), nleft.as<int32_t>(),
-                                               planv.as<int32_t>());
-            prof_part_mark(st);
-            k_scatter<<<g_nb, kBlock, 0, st>>>(cur, dimv.as<int32_t>(), splitv.as<float>(),
-                                               blk_off.as<uint32_t>(), nleft.as<int32_t>(), src,
-                                               srci, dst, dsti, n, d);
-            prof_part_mark(st);
-            k_plan_local<<<blocks_for(nn_l, kPlanBlock), kPlanBlock, 0, st>>>(
-                cur, planv.as<int32_t>(), planx.as<int32_t>(), pblk.as<int32_t>(), g);
-            k_plan_top<<<1, kPlanBlock, 0, st>>>(cur, nxt, pblk.as<int32_t>(), g,
-                                                 d_rng.as<int32_t>(), level, big_cap, sub_cap,
-                                                 nn_cap, nb_cap, nbh_cap);
-            k_plan_write<<<blocks_for(nn_l, kBlock), kBlock, 0, st>>>(
-                cur, nxt, dimv.as<int32_t>(), splitv.as<float>(), nleft.as<int32_t>(),
-                planx.as<int32_t>(), pblk.as<int32_t>(), leaf, W, max_depth, buf ^ 1,
-                d_big.as<NodeRec>(), d_subs.as<SubEntry>(), g);
-            {
-                const int64_t nn_next = std::min<int64_t>(2 * nn_l, nn_cap);
-                const int64_t fill = std::min<int64_t>(n / kChunk + nn_next + 1, nb_cap);
-                k_plan_fill<<<blocks_for(fill, kBlock), kBlock, 0, st>>>(nxt);
-            }
+            enqueue_level(lw, cur, nxt, level, buf, true, st);
             KNN_HIP(hipGetLastError());
             n_levels = level + 2;  // depth ranges 0 .. level + 1 are recorded
             std::swap(cur, nxt);
@@ -2201,7 +2309,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ff),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(ff, dim3(fblocks), dim3(kBlock), lds, st, d_subs.as<SubEntry>(), n_sub,
-                       colsA.as<float>(), idxA.as<int32_t>(), colsB.as<float>(),
+                       nullptr, colsA.as<float>(), idxA.as<int32_t>(), colsB.as<float>(),
                        idxB.as<int32_t>(), n, leaf, Wt, max_depth, per_wave, pts.as<float>(),
                        tnodes.as<NodeRec>(), tbox.as<float>(), subn.as<int32_t>(),
                        flags.as<int32_t>(), flags.as<int32_t>() + 1);
@@ -2231,7 +2339,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     if (n_big > 1)
         KNN_HIP(hipMemcpyAsync(nodes.p, d_big.p, sizeof(NodeRec) * n_big, hipMemcpyDeviceToDevice, st));
     KNN_HIP(hipMemcpyAsync(d_base.p, h_base.data(), sizeof(int32_t) * n_sub, hipMemcpyHostToDevice, st));
-    k_compact<<<fblocks, kBlock, 0, st>>>(d_subs.as<SubEntry>(), n_sub, subn.as<int32_t>(),
+    k_compact<<<fblocks, kBlock, 0, st>>>(d_subs.as<SubEntry>(), n_sub, nullptr, subn.as<int32_t>(),
                                           d_base.as<int32_t>(), tnodes.as<NodeRec>(),
                                           tbox.as<float>(), d, nodes.as<NodeRec>(),
                                           bbox.as<float>());
@@ -2266,5 +2374,450 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     *out = t;
     return KNN_OK;
 }
+
+
+// ---------------------------------------------------------------------------
+// Build plans: the build above for a fixed point count and forest layout,
+// with every buffer sized once at creation and no host round trip between
+// kernels.  A run is a fixed sequence of kernel launches (no allocation,
+// copy, fill or wait), so a HIP graph can capture it; results come back
+// through device status words that knn_build_plan_finish reads.
+// ---------------------------------------------------------------------------
+
+// Status words of a plan run.
+enum { PS_ERR = 0, PS_NSUB = 1, PS_NSUB_COMPACT = 2, PS_TOTAL = 3, PS_DEPTH = 4, PS_COUNT = 8 };
+
+// Level 0 as uploaded at plan creation.
+struct PlanLevel0 {
+    const int32_t* f;        // [8][nn0]: start, count, id, parent, depth, blk0, nblk, hblk0
+    const int32_t* bnode;    // [nb0]
+    const int32_t* bbeg;     // [nb0]
+    const int32_t* hnode;    // [nbh0]
+    const int32_t* hbeg;     // [nbh0]
+    const SubEntry* small;   // [n_small]: roots that go straight to the subtree finish
+    int32_t nn0, nb0, nbh0, n_small, T;
+};
+
+// Start of a run: counters, status and the tree's query error count to zero.
+__global__ void k_run_init(int32_t* __restrict__ g, int32_t* __restrict__ status,
+                           int32_t* __restrict__ flags, unsigned long long* __restrict__ bad)
+{
+    const int t = threadIdx.x;
+    if (t < G_COUNT) g[t] = 0;
+    if (t < PS_COUNT) status[t] = 0;
+    if (t < 2) flags[t] = 0;
+    if (t == 0) *bad = 0;
+}
+
+// Level 0 from its uploaded copy; after the ingest, so that a non-finite
+// coordinate empties the level and the subtree list (nothing is split).
+__global__ void k_run_level0(PlanLevel0 P, Level L0, SubEntry* __restrict__ subs,
+                             int32_t* __restrict__ g, int32_t* __restrict__ rng,
+                             int32_t* __restrict__ status)
+{
+    const bool bad = g[G_NONFINITE] != 0;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t* const dst[8] = {L0.start, L0.count, L0.id, L0.parent, L0.depth, L0.blk0, L0.nblk,
+                             L0.hblk0};
+    for (int64_t i = i0; i < 8 * (int64_t)P.nn0; i += stride)
+        dst[i / P.nn0][i % P.nn0] = P.f[i];
+    for (int64_t i = i0; i < P.nb0; i += stride) {
+        L0.bnode[i] = P.bnode[i];
+        L0.bbeg[i] = P.bbeg[i];
+    }
+    for (int64_t i = i0; i < P.nbh0; i += stride) {
+        L0.hnode[i] = P.hnode[i];
+        L0.hbeg[i] = P.hbeg[i];
+    }
+    for (int64_t i = i0; i < P.n_small; i += stride) subs[i] = P.small[i];
+    if (i0 == 0) {
+        if (P.nn0) {
+            L0.cnt[0] = bad ? 0 : P.nn0;
+            L0.cnt[1] = bad ? 0 : P.nb0;
+            L0.cnt[2] = bad ? 0 : P.nbh0;
+        }
+        g[G_NEXT_ID] = P.T;
+        g[G_NSUB] = bad ? 0 : P.n_small;
+        rng[0] = 0;
+        rng[1] = bad ? 0 : P.T;
+        if (bad) status[PS_ERR] = KNN_ENOTFINITE;
+    }
+}
+
+// After the level passes: an error, or nodes left over once the planned
+// passes ran out, stops the run; the subtree passes then see no subtrees and
+// the box pass sees empty depth ranges.
+__global__ void k_run_levels_done(const int32_t* __restrict__ left, const int32_t* __restrict__ g,
+                                  int32_t* __restrict__ rng, int n_rng,
+                                  int32_t* __restrict__ status)
+{
+    if (threadIdx.x != 0) return;
+    int err = status[PS_ERR];
+    if (!err && g[G_ERR]) err = g[G_ERR] == KNN_EDEPTH ? KNN_EDEPTH : KNN_EDEVICE;
+    if (!err && left && *left != 0) err = KNN_EDEPTH;
+    status[PS_ERR] = err;
+    status[PS_NSUB] = err ? 0 : g[G_NSUB];
+    if (err)
+        for (int j = 0; j < 2 * n_rng; ++j) rng[j] = 0;
+}
+
+// Final ids of the subtree nodes: subtree i's nodes other than its root get
+// ids base[i] .. base[i] + sub_nodes[i] - 2, after the level-pass ids, in
+// subtree order (the eager build's host prefix sum).  One block of
+// kPlanBlock threads, each over a contiguous run of subtrees.  A finish error
+// (or too many nodes) stops the run as k_run_levels_done does.
+__global__ __launch_bounds__(kPlanBlock) void k_run_bases(
+    const int32_t* __restrict__ sub_nodes, const int32_t* __restrict__ g,
+    const int32_t* __restrict__ flags, int32_t* __restrict__ base,
+    int32_t* __restrict__ status, int64_t node_cap, int32_t* __restrict__ rng, int n_rng)
+{
+    __shared__ long long wsum[kPlanBlock / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int ns = status[PS_NSUB];
+    const int64_t n_big = g[G_NEXT_ID];
+    const int seg = (ns + kPlanBlock - 1) / kPlanBlock;
+    const int lo = min(t * seg, ns), hi = min(lo + seg, ns);
+    long long mine = 0;
+    for (int i = lo; i < hi; ++i) mine += sub_nodes[i] - 1;
+    long long x = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    long long before = 0, all = 0;
+    for (int j = 0; j < kPlanBlock / 64; ++j) {
+        if (j < w) before += wsum[j];
+        all += wsum[j];
+    }
+    long long run = n_big + before + x - mine;
+    for (int i = lo; i < hi; ++i) {
+        base[i] = (int32_t)run;
+        run += sub_nodes[i] - 1;
+    }
+    if (t == 0) {
+        const long long total = n_big + all;
+        int err = status[PS_ERR];
+        if (!err && flags[0]) err = flags[0] == KNN_EDEPTH ? KNN_EDEPTH : KNN_EDEVICE;
+        if (!err && total > node_cap) err = KNN_EDEVICE;
+        status[PS_ERR] = err;
+        status[PS_NSUB_COMPACT] = err ? 0 : ns;
+        status[PS_TOTAL] = err ? 0 : (int32_t)total;
+        status[PS_DEPTH] = flags[1];
+        if (err)  // subtree roots stay unwritten: no box pass may read below them
+            for (int j = 0; j < 2 * n_rng; ++j) rng[j] = 0;
+    }
+}
+
+// End of a run.  After an error every root becomes a bucket holding only the
+// pad row past the last point, whose index word is -1: the tree stays safe to
+// query (results are padding-like rows), and knn_build_plan_finish reports the
+// error.  Without an error that index word goes back to 0.
+__global__ void k_run_done(const int32_t* __restrict__ status, NodeRec* __restrict__ nodes,
+                           float* __restrict__ bbox, float* __restrict__ pts, int64_t n, int d,
+                           int T)
+{
+    const bool err = status[PS_ERR] != 0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) pts[n * (d + 1) + d] = __int_as_float(err ? -1 : 0);
+    if (!err || i >= T) return;
+    nodes[i] = NodeRec{(int32_t)n, -1, 0.0f, -1};
+    for (int t = 0; t < 2 * d; ++t) bbox[(int64_t)i * 2 * d + t] = 0.0f;
+}
+
+}  // namespace knn
+
+struct knn_build_plan {
+    int32_t device = 0;
+    int64_t n = 0;
+    int32_t d = 0, leaf = 0, W = 0, max_depth = 0, T = 0, levels = 0;
+    int64_t split_block_nodes = 0;
+    int64_t nn_cap = 0, nb_cap = 0, nbh_cap = 0, big_cap = 0, sub_cap = 0, node_cap = 0;
+    int32_t Wt = 0;
+    size_t per_wave = 0, lds = 0;
+    unsigned fgrid = 0;
+    knn::FinishFn ff = nullptr;
+    std::vector<void*> blocks;  // every device block the plan holds (block cache)
+    knn::LevelWork lw{};
+    knn::Level lv[2]{};
+    knn::PlanLevel0 l0{};
+    float* pts = nullptr;
+    knn::NodeRec* tnodes = nullptr;
+    float* tbox = nullptr;
+    int32_t* subn = nullptr;
+    int32_t* flags = nullptr;
+    int32_t* base = nullptr;
+    int32_t* status = nullptr;
+    knn::NodeRec* nodes = nullptr;
+    float* bbox = nullptr;
+    knn_tree* tree = nullptr;
+    hipEvent_t last = nullptr;  // recorded after the latest run enqueued outside a capture
+    bool ran = false;
+};
+
+namespace knn {
+
+namespace {
+
+template <class T>
+hipError_t plan_alloc(knn_build_plan* P, T** p, size_t count)
+{
+    void* q = nullptr;
+    const hipError_t e = cache_alloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    P->blocks.push_back(q);
+    *p = static_cast<T*>(q);
+    return hipSuccess;
+}
+
+void plan_release(knn_build_plan* P)
+{
+    for (void* q : P->blocks) cache_free(q);
+    P->blocks.clear();
+    if (P->last) (void)hipEventDestroy(P->last);
+    delete P->tree;
+    delete P;
+}
+
+}  // namespace
+
+int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t T, int32_t leaf,
+                int32_t max_depth, int32_t W, int64_t split_block_nodes, hipStream_t st,
+                knn_build_plan** out)
+{
+    FinishFn ff = finish_for(d);
+    if (!ff) return fail(KNN_EINVAL, "unsupported dimension");
+    const Level0Host h0 = level0_tables(offsets, T, W, leaf);
+    int64_t biggest = 0;
+    for (int32_t r = 0; r < T; ++r) biggest = std::max(biggest, offsets[r + 1] - offsets[r]);
+    if (max_depth == 0) {  // balanced depth of the largest tree, with room for uneven splits
+        int dep = 0;
+        for (int64_t c = biggest; c > leaf; c = (c + 1) / 2) ++dep;
+        max_depth = dep + 8;
+    }
+    std::unique_ptr<knn_build_plan, void (*)(knn_build_plan*)> P(new knn_build_plan(),
+                                                                  plan_release);
+    (void)hipGetDevice(&P->device);
+    P->n = n;
+    P->d = d;
+    P->leaf = leaf;
+    P->W = W;
+    P->max_depth = max_depth;
+    P->T = T;
+    P->split_block_nodes = split_block_nodes;
+    const int nn0 = (int)h0.big_roots.size();
+    P->levels = nn0 ? std::min(expected_levels(h0.largest, W, leaf) + 4, max_depth + 1) : 0;
+    // capacities as in the eager build, with the planned passes as the depth
+    const int64_t lv_cap = (int64_t)P->levels + 1;
+    P->nn_cap = n / (W + 1) + 1;
+    P->nb_cap = n / kChunk + P->nn_cap + 1;
+    P->nbh_cap = n / kHistChunk + P->nn_cap + 1;
+    P->big_cap = T + 2 * P->nn_cap * lv_cap + 2;
+    P->sub_cap = std::min<int64_t>(n, P->big_cap);
+    P->node_cap = std::max<int64_t>(2 * n + T, P->big_cap);
+    if (P->node_cap > INT32_MAX) return fail(KNN_EINVAL, "too many nodes for int32 ids");
+    const int64_t nd = n * d, tail = (int64_t)kWave * kGlobalRows;
+    LevelWork& w = P->lw;
+    int32_t* g = nullptr;
+    int32_t* lvbuf[2] = {nullptr, nullptr};
+    int32_t* rng = nullptr;
+    int32_t* l0buf = nullptr;
+    SubEntry* small = nullptr;
+    KNN_HIP(plan_alloc(P.get(), &w.cols[0], nd + tail));
+    KNN_HIP(plan_alloc(P.get(), &w.cols[1], nd + tail));
+    KNN_HIP(plan_alloc(P.get(), &w.idx[0], n + tail));
+    KNN_HIP(plan_alloc(P.get(), &w.idx[1], n + tail));
+    KNN_HIP(plan_alloc(P.get(), &P->pts, (n + kRowPad) * (d + 1)));
+    KNN_HIP(plan_alloc(P.get(), &g, G_COUNT));
+    KNN_HIP(plan_alloc(P.get(), &rng, 2 * (lv_cap + 1)));
+    KNN_HIP(plan_alloc(P.get(), &w.subs, P->sub_cap));
+    KNN_HIP(plan_alloc(P.get(), &P->tnodes, 2 * n));
+    KNN_HIP(plan_alloc(P.get(), &P->tbox, 2 * n * 2 * d));
+    KNN_HIP(plan_alloc(P.get(), &P->subn, P->sub_cap));
+    KNN_HIP(plan_alloc(P.get(), &P->base, P->sub_cap));
+    KNN_HIP(plan_alloc(P.get(), &P->flags, 2));
+    KNN_HIP(plan_alloc(P.get(), &P->status, PS_COUNT));
+    KNN_HIP(plan_alloc(P.get(), &P->nodes, P->node_cap));
+    KNN_HIP(plan_alloc(P.get(), &P->bbox, P->node_cap * 2 * d));
+    unsigned long long* bad = nullptr;
+    KNN_HIP(plan_alloc(P.get(), &bad, 1));
+    if (nn0) {
+        for (int k = 0; k < 2; ++k) {
+            KNN_HIP(plan_alloc(P.get(), &lvbuf[k], level_words(P->nn_cap, P->nb_cap, P->nbh_cap)));
+            P->lv[k] = carve_level(lvbuf[k], P->nn_cap, P->nb_cap, P->nbh_cap);
+        }
+        KNN_HIP(plan_alloc(P.get(), &w.dimv, P->nn_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.splitv, P->nn_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.nleft, P->nn_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.samples, (size_t)kWinStride * P->nn_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.hist, (size_t)kWinRow * P->nn_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.wave_left, (size_t)kWavesPerBlock * P->nb_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.blk_off, P->nb_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.planv, (size_t)kPlanStride * P->nn_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.planx, (size_t)kPlanStride * P->nn_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.pblk,
+                           (size_t)kPlanStride * ((P->nn_cap + kPlanBlock - 1) / kPlanBlock)));
+    }
+    // level 0 and the small roots, uploaded once
+    const size_t nb0 = h0.bnode.size(), nbh0 = h0.hbeg.size();
+    const size_t l0_words = 8 * (size_t)nn0 + 2 * nb0 + 2 * nbh0;
+    KNN_HIP(plan_alloc(P.get(), &l0buf, l0_words));
+    KNN_HIP(plan_alloc(P.get(), &small, h0.small.size()));
+    {
+        std::vector<int32_t> host;
+        host.reserve(l0_words);
+        for (int k = 0; k < 8; ++k) host.insert(host.end(), h0.f[k].begin(), h0.f[k].end());
+        for (auto* v : {&h0.bnode, &h0.bbeg, &h0.hnode, &h0.hbeg})
+            host.insert(host.end(), v->begin(), v->end());
+        if (!host.empty())
+            KNN_HIP(hipMemcpyAsync(l0buf, host.data(), sizeof(int32_t) * host.size(),
+                                   hipMemcpyHostToDevice, st));
+        if (!h0.small.empty())
+            KNN_HIP(hipMemcpyAsync(small, h0.small.data(), sizeof(SubEntry) * h0.small.size(),
+                                   hipMemcpyHostToDevice, st));
+        // the pad rows past the last point read as zeros
+        KNN_HIP(hipMemsetAsync(P->pts + n * (d + 1), 0, sizeof(float) * kRowPad * (d + 1), st));
+        KNN_HIP(hipStreamSynchronize(st));  // the host copies die here
+    }
+    P->l0 = PlanLevel0{l0buf, l0buf + 8 * (size_t)nn0, l0buf + 8 * (size_t)nn0 + nb0,
+                       l0buf + 8 * (size_t)nn0 + 2 * nb0, l0buf + 8 * (size_t)nn0 + 2 * nb0 + nbh0,
+                       small, nn0, (int32_t)nb0, (int32_t)nbh0, (int32_t)h0.small.size(), T};
+    w.big = P->nodes;  // level-pass records go straight to their final ids
+    w.rng = rng;
+    w.g = g;
+    w.n = n;
+    w.d = d;
+    w.leaf = leaf;
+    w.W = W;
+    w.max_depth = max_depth;
+    w.split_block_nodes = split_block_nodes;
+    w.nn0 = nn0;
+    w.nn_cap = P->nn_cap;
+    w.nb_cap = P->nb_cap;
+    w.nbh_cap = P->nbh_cap;
+    w.big_cap = P->big_cap;
+    w.sub_cap = P->sub_cap;
+    P->ff = ff;
+    P->Wt = finish_tile_points(d, W);
+    P->per_wave = finish_lds_bytes_per_wave(d, P->Wt);
+    P->lds = P->per_wave * kWavesPerBlock;
+    if (P->lds > 64 * 1024)
+        KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ff),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P->lds));
+    // one wavefront per subtree for the usual count (subtrees hold more than
+    // W / 2 points when splits are near even); more are taken in strides
+    const int64_t usual = std::min<int64_t>(P->sub_cap, 3 * n / W + 2 * (int64_t)T + 256);
+    P->fgrid = (unsigned)((usual + kWavesPerBlock - 1) / kWavesPerBlock);
+
+    knn_tree* t = new knn_tree();
+    t->n = n;
+    t->d = d;
+    t->leaf = leaf;
+    t->n_trees = T;
+    t->depth = max_depth;  // a bound that holds for every successful run
+    t->sub_pts = W;
+    t->n_nodes = 0;
+    t->device = P->device;
+    t->bytes = (int64_t)(sizeof(float) * (n + kRowPad) * (d + 1) +
+                         (sizeof(NodeRec) + sizeof(float) * 2 * d) * P->node_cap);
+    t->pts = P->pts;
+    t->nodes = P->nodes;
+    t->bbox = P->bbox;
+    t->bad = bad;
+    t->plan_owned = true;
+    P->tree = t;
+    KNN_HIP(hipEventCreateWithFlags(&P->last, hipEventDisableTiming));
+    *out = P.release();
+    return KNN_OK;
+}
+
+int plan_run(knn_build_plan* P, const float* points, hipStream_t st)
+{
+    const int64_t n = P->n;
+    const int d = P->d, T = P->T;
+    const LevelWork& w = P->lw;
+    k_run_init<<<1, 64, 0, st>>>(w.g, P->status, P->flags, P->tree->bad);
+    {
+        const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
+        k_ingest<<<(unsigned)blocks, kBlock, 0, st>>>(points, n, d, w.cols[0], w.idx[0], w.g);
+    }
+    {
+        const PlanLevel0& l0 = P->l0;
+        const int64_t items = std::max<int64_t>({8 * (int64_t)l0.nn0, l0.nb0, l0.nbh0,
+                                                 l0.n_small, 1});
+        k_run_level0<<<(unsigned)std::min<int64_t>(blocks_for(items, kBlock), 4096), kBlock, 0,
+                       st>>>(l0, P->lv[0], w.subs, w.g, w.rng, P->status);
+    }
+    int buf = 0;
+    for (int level = 0; level < P->levels; ++level) {
+        enqueue_level(w, P->lv[buf], P->lv[buf ^ 1], level, buf, false, st);
+        buf ^= 1;
+    }
+    k_run_levels_done<<<1, 64, 0, st>>>(P->levels ? P->lv[buf].cnt : nullptr, w.g, w.rng,
+                                        P->levels + 1, P->status);
+    hipLaunchKernelGGL(P->ff, dim3(P->fgrid), dim3(kBlock), P->lds, st, w.subs, 0,
+                       P->status + PS_NSUB, w.cols[0], w.idx[0], w.cols[1], w.idx[1], n, P->leaf,
+                       P->Wt, P->max_depth, P->per_wave, P->pts, P->tnodes, P->tbox, P->subn,
+                       P->flags, P->flags + 1);
+    k_run_bases<<<1, kPlanBlock, 0, st>>>(P->subn, w.g, P->flags, P->base, P->status,
+                                          P->node_cap, w.rng, P->levels + 1);
+    k_compact<<<P->fgrid, kBlock, 0, st>>>(w.subs, 0, P->status + PS_NSUB_COMPACT, P->subn,
+                                           P->base, P->tnodes, P->tbox, d, P->nodes, P->bbox);
+    for (int dep = P->levels; dep >= 0; --dep) {
+        const int64_t cap = std::min<int64_t>(dep < 40 ? (int64_t)T << dep : P->node_cap,
+                                              P->node_cap);
+        k_bbox_up<<<blocks_for(cap, kBlock), kBlock, 0, st>>>(w.rng + 2 * dep, P->nodes, P->bbox,
+                                                             d);
+    }
+    k_run_done<<<blocks_for(T, kBlock), kBlock, 0, st>>>(P->status, P->nodes, P->bbox, P->pts, n,
+                                                          d, T);
+    KNN_HIP(hipGetLastError());
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    KNN_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusNone) KNN_HIP(hipEventRecord(P->last, st));
+    P->ran = true;
+    return KNN_OK;
+}
+
+int plan_finish(knn_build_plan* P, hipStream_t st)
+{
+    if (!P->ran) return fail(KNN_EINVAL, "the plan has not run");
+    int32_t h[PS_COUNT] = {};
+    KNN_HIP(hipMemcpyAsync(h, P->status, sizeof(h), hipMemcpyDeviceToHost, st));
+    KNN_HIP(hipStreamSynchronize(st));
+    knn_tree* t = P->tree;
+    t->n_nodes = h[PS_ERR] ? P->T : h[PS_TOTAL];
+    switch (h[PS_ERR]) {
+    case KNN_OK: return KNN_OK;
+    case KNN_ENOTFINITE: return fail(KNN_ENOTFINITE, "an input coordinate is NaN or infinite");
+    case KNN_EDEPTH: return fail(KNN_EDEPTH, "tree deeper than the plan's max_depth");
+    default: return fail(KNN_EDEVICE, "the build overflowed the plan's buffers");
+    }
+}
+
+int plan_destroy(knn_build_plan* P)
+{
+    int rc = KNN_OK;
+    {   // queries on the plan's tree, then the latest run outside a capture
+        std::lock_guard<std::mutex> lk(P->tree->use_mu);
+        for (auto& u : P->tree->uses) {
+            hipError_t e = hipEventSynchronize(u.second);
+            if (e != hipSuccess && rc == KNN_OK) rc = hip_fail(e, "hipEventSynchronize");
+            (void)hipEventDestroy(u.second);
+        }
+        P->tree->uses.clear();
+    }
+    if (P->ran) {
+        hipError_t e = hipEventSynchronize(P->last);
+        if (e != hipSuccess && rc == KNN_OK) rc = hip_fail(e, "hipEventSynchronize");
+    }
+    plan_release(P);
+    return rc;
+}
+
+knn_tree* plan_tree(knn_build_plan* P) { return P->tree; }
+int32_t plan_device(const knn_build_plan* P) { return P->device; }
 
 }  // namespace knn

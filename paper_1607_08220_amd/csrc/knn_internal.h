@@ -62,6 +62,8 @@ struct knn_tree {
     // latest query there: knn_tree_free waits for these and nothing else.
     mutable std::mutex use_mu;
     mutable std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+    // held by a build plan, whose runs rewrite it in place: freed with the plan
+    bool plan_owned = false;
 };
 
 namespace knn {
@@ -151,6 +153,16 @@ size_t finish_lds_bytes_per_wave(int32_t d, int32_t w);
 int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
                int32_t W, int64_t split_block_nodes, const int64_t* offsets, int32_t trees,
                hipStream_t stream, knn_tree** out);
+// Build plans (knn_build_plan_*): max_depth 0 picks a bound from the largest
+// tree's balanced depth.
+int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t trees, int32_t leaf,
+                int32_t max_depth, int32_t W, int64_t split_block_nodes, hipStream_t stream,
+                knn_build_plan** out);
+int plan_run(knn_build_plan* plan, const float* points, hipStream_t stream);
+int plan_finish(knn_build_plan* plan, hipStream_t stream);
+int plan_destroy(knn_build_plan* plan);
+knn_tree* plan_tree(knn_build_plan* plan);
+int32_t plan_device(const knn_build_plan* plan);
 // One batch of queries against a tree (or forest).  Per-query arrays are
 // device pointers indexed by query; NULL selects the scalar.
 struct QuerySpec {

@@ -67,3 +67,26 @@ def test_strerror_and_tree_errors_without_device():
                      -4: "KNN_EDEPTH", -5: "KNN_ENOTFINITE"}
     assert knn.knn_strerror(7) == "unknown"
     assert lib.knn_tree_errors(None, None, None) == knn.KNN_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libknn.so not built")
+def test_build_plan_argument_errors_need_no_device():
+    import paper_1607_08220_amd as knn
+    lib = knn.load_library()
+    out = ctypes.c_void_p()
+    I64 = ctypes.c_int64 * 3
+    assert lib.knn_build_plan_create(0, 3, None, 1, None, None, ctypes.byref(out)) == knn.KNN_EINVAL
+    assert lib.knn_build_plan_create(10, 17, None, 1, None, None, ctypes.byref(out)) == knn.KNN_EINVAL
+    assert lib.knn_build_plan_create(10, 3, None, 2, None, None, ctypes.byref(out)) == knn.KNN_EINVAL
+    bad_end = I64(0, 4, 9)  # offsets[trees] != n
+    assert lib.knn_build_plan_create(10, 3, bad_end, 2, None, None,
+                                     ctypes.byref(out)) == knn.KNN_EINVAL
+    empty_tree = I64(0, 4, 4)
+    assert lib.knn_build_plan_create(4, 3, empty_tree, 2, None, None,
+                                     ctypes.byref(out)) == knn.KNN_EINVAL
+    assert lib.knn_build_plan_create(10, 3, None, 1, None, None, None) == knn.KNN_EINVAL
+    assert not out.value
+    assert lib.knn_build_plan_run(None, ctypes.c_void_p(16), None) == knn.KNN_EINVAL
+    assert lib.knn_build_plan_finish(None, None, None) == knn.KNN_EINVAL
+    assert lib.knn_build_plan_tree(None) is None
+    assert lib.knn_build_plan_destroy(None) == knn.KNN_OK
