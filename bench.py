@@ -109,7 +109,9 @@ def oracle_leg(w, threads: int, gpu_idx, gpu_d2) -> dict:
 def bench_forest(knn, torch, dev) -> dict:
     """Batched build + query of 512 independent 6-D trees (sizes log-uniform in
     [2^10, 2^20], each queried by 1,024 of its own points, k = 5) against the
-    same work as 512 per-call builds and queries; identical results required."""
+    same work as 512 per-call builds and queries; identical results required.
+    Also timed: the query alone replayed from a graph, and a build plan's
+    build with the query captured together in one graph and replayed."""
     from paper_1607_08220_amd import inputs
     t0 = time.perf_counter()
     f = inputs.forest(512)
@@ -185,6 +187,37 @@ def bench_forest(knn, torch, dev) -> dict:
     forest.free()
     bqg = float(np.median(reps))
 
+    # build (a build plan) and query captured together in one graph and replayed
+    plan = knn.BuildPlan(len(f.points), f.points.shape[1], offsets=f.offsets, leaf_size=leaf)
+    with torch.cuda.stream(side):
+        plan.run(P)
+        knn.knn_query_batch(plan.tree, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
+                            traversal=trav, team_lanes=team, out=(gi_t, gd_t))
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    plan.finish()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(P)
+        knn.knn_query_batch(plan.tree, Q, T, f.k, self_ids=S, order=order, leaf_batch=lb,
+                            traversal=trav, team_lanes=team, out=(gi_t, gd_t))
+    reps = []
+    plan_same = True
+    for _ in range(5):
+        gi_t.fill_(-1)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - a) * 1e3)
+        plan.finish()
+        plan_same &= bool(torch.equal(gi_t, idx) and torch.equal(gd_t.view(torch.int32),
+                                                                  d2.view(torch.int32)))
+    del graph
+    torch.cuda.synchronize()
+    plan.destroy()
+    bpg = float(np.median(reps))
+
     # the same work as one call per tree
     qsel = [np.flatnonzero(f.tree_ids == t) for t in range(len(f.offsets) - 1)]
     Qt = [Q[torch.from_numpy(s).to(dev)].contiguous() for s in qsel]
@@ -209,12 +242,14 @@ def bench_forest(knn, torch, dev) -> dict:
                                                                   od.view(np.uint32)))
     n, m = len(f.points), len(f.queries)
     log(f"forest: batched build {bb:.1f} ms + query {bq:.2f} ms (graph replay {bqg:.2f} ms, "
-        f"identical={graph_same}); per call {per_call:.0f} ms; identical={same}")
+        f"identical={graph_same}); build plan + query in one graph {bpg:.1f} ms "
+        f"(identical={plan_same}); per call {per_call:.0f} ms; identical={same}")
     return {"workload": "forest512_6d", "trees": len(f.offsets) - 1, "points": n, "queries": m,
             "k": f.k, "autotuned": {"leaf_size": leaf, "leaf_batch": lb, "order": order,
                                     "traversal": trav, "team_lanes": team},
             "batched_build_ms": bb, "batched_query_ms": bq, "graph_replay_query_ms": bqg,
             "graph_replay_identical": graph_same,
+            "graph_replay_build_query_ms": bpg, "graph_replay_build_query_identical": plan_same,
             "batched_ms": bb + bq, "per_call_ms": per_call, "speedup": per_call / (bb + bq),
             "build_mpts_per_s": n / (bb * 1e-3) / 1e6, "queries_per_s": m / (bq * 1e-3),
             "identical_to_per_call": same}
@@ -605,7 +640,7 @@ def main() -> int:
                           "step_efficiency": steps * 64 / w_steps if w_steps else None},
         "roofline": {"kernel": "k_traverse", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("knn_query.hip", "traffic_k_traverse_cosmo_clustered.json"),
+                     "traffic": measured_traffic("knn_traverse.h", "traffic_k_traverse_cosmo_clustered.json"),
                      "bytes_per_launch": bpq * m, "bytes_per_query": bpq,
                      "visit_counts": visits,
                      "oracle_visits_per_query": leg["oracle_visits"] if leg else None,

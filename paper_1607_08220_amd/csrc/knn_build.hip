@@ -95,9 +95,11 @@ struct Level {
 
 // Build-wide device counters (the id and subtree counters before the
 // current level are kept in G_BASE_ID / G_BASE_SUB for the plan writes).
+// G_MOVED: 64-bit count of points partitioned (slots 6-7).
 // G_NONFINITE: set by the ingest when an input coordinate is NaN or infinite.
+// G_LEVEL_NODES: nodes of the level the latest pass wrote (its cnt[0]).
 enum { G_NEXT_ID = 0, G_NSUB = 1, G_ERR = 2, G_BASE_ID = 3, G_BASE_SUB = 4, G_MOVED = 6,
-       G_NONFINITE = 8, G_COUNT = 9 };  // G_MOVED: 64-bit count of points partitioned (slots 6-7)
+       G_NONFINITE = 8, G_LEVEL_NODES = 9, G_COUNT = 10 };
 constexpr int kPlanVals = 5;  // split nodes, level children, subtrees, blocks, histogram blocks
 constexpr int kPlanStride = 8;
 constexpr int kErrOverflow = -100;
@@ -228,22 +230,27 @@ __device__ inline void wave_sort1024(float (&u)[16])
 // B1-B3: one wavefront per node (kWavesPerBlock nodes per block).  Sample
 // s = min(count, 1024) points at the systematic positions, pick the
 // dimension of largest sample variance (FP64, fixed pairwise order), sort
-// the sample along it and keep the values of ranks jl..jh; clear the node's
-// histogram row.
-__global__ __launch_bounds__(kBlock) void k_sample(Level L, const float* __restrict__ cols,
+// the sample along it (kept in registers from the variance pass, moved to
+// the sort's layout through LDS) and keep the values of ranks jl..jh; clear
+// the node's histogram row.  Bounded to 128 registers: four wavefronts per
+// SIMD, without spills.
+__global__ __launch_bounds__(kBlock, 4) void k_sample(Level L, const float* __restrict__ cols,
                                                    int64_t n, int d, float* __restrict__ samples,
                                                    int32_t* __restrict__ out_dim,
                                                    uint32_t* __restrict__ hist)
 {
+    __shared__ float tr[kWavesPerBlock][kSampleMax];  // the best column's sample, transposed
     const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // wavefront-uniform: node data loads through the scalar unit
-    const int node = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int node = blockIdx.x * kWavesPerBlock + w;
     if (node >= L.cnt[0]) return;
     const int64_t start = L.start[node], c = L.count[node];
     for (int i = lane; i < kWinRow; i += kWave) hist[(int64_t)node * kWinRow + i] = 0u;
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
     double bestV = -1.0;
     int best = 0;
+    float* t = tr[w];  // the sample of the best dimension so far, element j at t[j]
     for (int dd = 0; dd < d; ++dd) {
         const float* col = cols + (int64_t)dd * n + start;
         double v[16], q[16];
@@ -265,19 +272,22 @@ __global__ __launch_bounds__(kBlock) void k_sample(Level L, const float* __restr
         if (V > bestV) {
             bestV = V;
             best = dd;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = lane + 64 * r;
+                t[j] = j < s ? f[r] : INFINITY;
+            }
         }
     }
     if (!(bestV > 0.0)) {  // sample constant in every dimension
         if (lane == 0) out_dim[node] = -1;
         return;
     }
-    const float* col = cols + (int64_t)best * n + start;
+    // element j to lane j / 16, register j % 16: the sort's layout
+    wave_sync();
     float u[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int j = 16 * lane + r;
-        u[r] = j < s ? col[sample_pos_fast(j, c, s)] : INFINITY;
-    }
+    for (int r = 0; r < 16; ++r) u[r] = t[16 * lane + r];
     wave_sort1024(u);
     int jl, jh;
     sample_window(s, &jl, &jh);
@@ -318,12 +328,28 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
     const int nwin = jh - jl;  // window bins jl+1 .. jh
     const int64_t beg = L.hbeg[b];
     const int64_t end = beg + kHistChunk < c ? beg + kHistChunk : c;
-    for (int i = t; i <= nwin; i += kBlock) sv[i] = samples[(int64_t)node * kWinStride + i];
+    // the block's chunk: len <= kHistChunk points from position beg of the node
+    const float* col = cols + (int64_t)dim * n + start + beg;
+    const int len = (int)(end - beg);
+    constexpr int kIlp = 8;
+    constexpr int kStep = kBlock * kIlp;
+    const int wbeg = w * kWave * kIlp;
+    float xn[kIlp];  // the next iteration's values, loaded while this one is binned
+    if (wbeg < len) {  // the first ones before the window values arrive
+#pragma unroll
+        for (int u = 0; u < kIlp; ++u) {  // unconditional loads, clamped in range
+            const int e = wbeg + u * kWave + lane;
+            xn[u] = col[e < len ? e : len - 1];
+        }
+    }
+    // past nwin the values read +inf: a search step there never moves (an
+    // in-window point is below sv[nwin]), so the search needs no bound test
+    for (int i = t; i <= 2 * kWinHalf; i += kBlock)
+        sv[i] = i <= nwin ? samples[(int64_t)node * kWinStride + i] : INFINITY;
     for (int i = t; i < kWinRow; i += kBlock) h[i] = 0u;
     __syncthreads();
     const float lo_v = sv[0], hi_v = sv[nwin];
-    const float* col = cols + (int64_t)dim * n + start;
-    uint32_t below = 0, above = 0;
+    uint32_t below = 0, above = 0;  // wavefront-uniform counts (ballots)
     int qn = 0;  // queued points of this wavefront (uniform)
     float* qw = queue[w];
     // place the first 64 queued points: bin = jl + 1 + #{1 <= i < nwin : sv[i] <= x}
@@ -331,30 +357,31 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
         __builtin_amdgcn_wave_barrier();
         const float x = qw[lane];
         int pos = 0;
-        for (int step = kWinHalf; step > 0; step >>= 1) {
-            const int np = pos + step;
-            if (np < nwin && sv[np] <= x) pos = np;
-        }
+#pragma unroll
+        for (int step = kWinHalf; step > 0; step >>= 1) pos = sv[pos + step] <= x ? pos + step : pos;
         atomicAdd(&h[1 + pos], 1u);
         const float tail = qw[kWave + lane];
         if (lane < qn - kWave) qw[lane] = tail;
         __builtin_amdgcn_wave_barrier();
         qn -= kWave;
     };
-    constexpr int kIlp = 8;
-    const int64_t wbeg = beg + (int64_t)w * kWave * kIlp;
-    for (int64_t e0 = wbeg; e0 < end; e0 += (int64_t)kBlock * kIlp) {
+    for (int e0 = wbeg; e0 < len; e0 += kStep) {
         float x[kIlp];
 #pragma unroll
-        for (int u = 0; u < kIlp; ++u) {  // unconditional loads, clamped in range
-            const int64_t e = e0 + (int64_t)u * kWave + lane;
-            x[u] = col[e < end ? e : end - 1];
+        for (int u = 0; u < kIlp; ++u) x[u] = xn[u];
+        if (e0 + kStep < len) {
+#pragma unroll
+            for (int u = 0; u < kIlp; ++u) {
+                const int e = e0 + kStep + u * kWave + lane;
+                xn[u] = col[e < len ? e : len - 1];
+            }
         }
+        const int rem = len - e0;  // points left from this iteration's first
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) {
-            const bool ok = e0 + (int64_t)u * kWave + lane < end;
-            below += ok && x[u] < lo_v;
-            above += ok && x[u] >= hi_v;
+            const bool ok = u * kWave + lane < rem;
+            below += (uint32_t)__popcll(__ballot(ok && x[u] < lo_v));
+            above += (uint32_t)__popcll(__ballot(ok && x[u] >= hi_v));
             const bool in = ok && x[u] >= lo_v && x[u] < hi_v;
             const unsigned long long m = __ballot(in);
             const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
@@ -369,24 +396,24 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
         const float x = qw[lane];
         if (lane < qn) {
             int pos = 0;
-            for (int step = kWinHalf; step > 0; step >>= 1) {
-                const int np = pos + step;
-                if (np < nwin && sv[np] <= x) pos = np;
-            }
+#pragma unroll
+            for (int step = kWinHalf; step > 0; step >>= 1)
+                pos = sv[pos + step] <= x ? pos + step : pos;
             atomicAdd(&h[1 + pos], 1u);
         }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        below += __shfl_xor(below, o);
-        above += __shfl_xor(above, o);
     }
     if (lane == 0) {
         atomicAdd(&h[0], below);
         atomicAdd(&h[nwin + 1], above);
     }
     __syncthreads();
-    for (int i = t; i <= nwin + 1; i += kBlock)
-        if (h[i]) atomicAdd(&hist[(int64_t)node * kWinRow + i], h[i]);
+    uint32_t* row = hist + (int64_t)node * kWinRow;
+    if (c <= kHistChunk) {  // the node's only block: its row, stored whole
+        for (int i = t; i <= nwin + 1; i += kBlock) row[i] = h[i];
+    } else {
+        for (int i = t; i <= nwin + 1; i += kBlock)
+            if (h[i]) atomicAdd(&row[i], h[i]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1515,7 +1542,7 @@ __device__ int finish_global(const FinishCtx& cx, const float* __restrict__ scol
 // the index permutation ping-pongs between two arrays, and each bucket's
 // packed rows are written as soon as the bucket is final.
 template <int D>
-__device__ inline void finish_subtree(
+__device__ __forceinline__ void finish_subtree(
     int sub, unsigned char* smem, const SubEntry* __restrict__ subs, float* colsA, int32_t* idxA,
     float* colsB, int32_t* idxB, int64_t n, int leaf, int W, int max_depth,
     size_t per_wave, float* __restrict__ pts, NodeRec* __restrict__ tnodes,
@@ -1654,24 +1681,33 @@ __device__ inline void finish_subtree(
     }
 }
 
-// One wavefront per subtree; subtrees beyond the grid are taken in strides
-// (the count comes from n_sub, or from *n_sub_dev when that is set, for
-// launches whose grid is fixed before the count is known).
-template <int D>
+// One wavefront per subtree, subtrees sub0 + (wavefront index) of the grid;
+// with kStride, also every grid-sized stride beyond (the tail of a launch
+// whose grid was fixed before the count was known).  The count is n_sub, or
+// *n_sub_dev when that is set.  The single-subtree form keeps the register
+// count of a body without a loop around it (occupancy 4).
+template <int D, bool kStride>
 __global__ __launch_bounds__(kBlock) void k_finish(
-    const SubEntry* __restrict__ subs, int32_t n_sub, const int32_t* __restrict__ n_sub_dev,
-    float* colsA, int32_t* idxA, float* colsB, int32_t* idxB, int64_t n, int leaf, int W,
-    int max_depth, size_t per_wave, float* __restrict__ pts, NodeRec* __restrict__ tnodes,
-    float* __restrict__ tbox, int32_t* __restrict__ sub_nodes, int32_t* __restrict__ err,
-    int32_t* __restrict__ depth_seen)
+    const SubEntry* __restrict__ subs, int32_t sub0, int32_t n_sub,
+    const int32_t* __restrict__ n_sub_dev, float* colsA, int32_t* idxA, float* colsB,
+    int32_t* idxB, int64_t n, int leaf, int W, int max_depth, size_t per_wave,
+    float* __restrict__ pts, NodeRec* __restrict__ tnodes, float* __restrict__ tbox,
+    int32_t* __restrict__ sub_nodes, int32_t* __restrict__ err, int32_t* __restrict__ depth_seen)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int total = n_sub_dev ? __builtin_amdgcn_readfirstlane(*n_sub_dev) : n_sub;
     // only wavefront-level synchronization below
-    for (int sub = blockIdx.x * kWavesPerBlock + w; sub < total; sub += gridDim.x * kWavesPerBlock)
-        finish_subtree<D>(sub, smem, subs, colsA, idxA, colsB, idxB, n, leaf, W, max_depth,
-                          per_wave, pts, tnodes, tbox, sub_nodes, err, depth_seen);
+    int sub = sub0 + blockIdx.x * kWavesPerBlock + w;
+    if constexpr (kStride) {
+        for (; sub < total; sub += gridDim.x * kWavesPerBlock)
+            finish_subtree<D>(sub, smem, subs, colsA, idxA, colsB, idxB, n, leaf, W, max_depth,
+                              per_wave, pts, tnodes, tbox, sub_nodes, err, depth_seen);
+    } else {
+        if (sub < total)
+            finish_subtree<D>(sub, smem, subs, colsA, idxA, colsB, idxB, n, leaf, W, max_depth,
+                              per_wave, pts, tnodes, tbox, sub_nodes, err, depth_seen);
+    }
 }
 
 // Final ids: subtree root keeps its level-pass id, local node j >= 1 becomes
@@ -1835,12 +1871,14 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_top(
         nxt.cnt[0] = tot[1];
         nxt.cnt[1] = tot[3];
         nxt.cnt[2] = tot[4];
+        g[G_LEVEL_NODES] = tot[1];
         rng[2 * (level + 1)] = base_id;
         rng[2 * (level + 1) + 1] = base_id + 2 * tot[0];
         if (base_id + 2 * (int64_t)tot[0] > big_cap || base_sub + (int64_t)tot[2] > sub_cap ||
             tot[1] > nn_cap || tot[3] > nb_cap || tot[4] > nbh_cap) {
             atomicExch(&g[G_ERR], kErrOverflow);
             nxt.cnt[0] = nxt.cnt[1] = nxt.cnt[2] = 0;  // nothing more is written
+            g[G_LEVEL_NODES] = 0;
         }
     }
 }
@@ -1959,16 +1997,16 @@ struct LevelMem {
     }
 };
 
-using FinishFn = void (*)(const SubEntry*, int32_t, const int32_t*, float*, int32_t*, float*,
-                          int32_t*, int64_t, int, int, int, size_t, float*, NodeRec*,
+using FinishFn = void (*)(const SubEntry*, int32_t, int32_t, const int32_t*, float*, int32_t*,
+                          float*, int32_t*, int64_t, int, int, int, size_t, float*, NodeRec*,
                           float*, int32_t*, int32_t*, int32_t*);
 
-FinishFn finish_for(int d)
+FinishFn finish_for(int d, bool stride = false)
 {
     switch (d) {
 #define KNN_DIM_CASE(DD) \
     case DD:             \
-        return k_finish<DD>;
+        return stride ? k_finish<DD, true> : k_finish<DD, false>;
         KNN_DIM_CASE(1) KNN_DIM_CASE(2) KNN_DIM_CASE(3) KNN_DIM_CASE(4)
         KNN_DIM_CASE(5) KNN_DIM_CASE(6) KNN_DIM_CASE(7) KNN_DIM_CASE(8)
         KNN_DIM_CASE(9) KNN_DIM_CASE(10) KNN_DIM_CASE(11) KNN_DIM_CASE(12)
@@ -2117,277 +2155,20 @@ size_t finish_lds_bytes_per_wave(int32_t d, int32_t w)
 
 int32_t default_subtree_points(int32_t d) { return finish_max_points(d); }
 
-int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
-               int32_t W, int64_t split_block_nodes, const int64_t* offsets, int32_t T,
-               hipStream_t st, knn_tree** out)
-{
-    prof_mark(st, 0);
-    prof_part_begin();
-    const int64_t nd = n * d;
-    // scratch and the tree's own buffers (pts, nodes, bbox) come from the
-    // library's block cache: a build that follows another, or a freed tree,
-    // reuses that memory instead of mapping fresh pages while the device waits
-    DevBuf colsA(st), colsB(st), idxA(st), idxB(st), pts(st), gbuf(st);
-    // padded by one finish tile of rows: the finish reads whole rows of 64
-    // points, up to 64 * kGlobalRows - 1 elements past a node's last point
-    const int64_t tail = (int64_t)kWave * kGlobalRows;
-    KNN_HIP(colsA.alloc(sizeof(float) * (nd + tail)));
-    KNN_HIP(colsB.alloc(sizeof(float) * (nd + tail)));
-    KNN_HIP(idxA.alloc(sizeof(int32_t) * (n + tail)));
-    KNN_HIP(idxB.alloc(sizeof(int32_t) * (n + tail)));
-    KNN_HIP(pts.alloc(sizeof(float) * (n + kRowPad) * (d + 1)));
-    KNN_HIP(hipMemsetAsync(pts.as<float>() + n * (d + 1), 0, sizeof(float) * kRowPad * (d + 1), st));
-    KNN_HIP(gbuf.alloc(sizeof(int32_t) * G_COUNT));
-    int32_t* g = gbuf.as<int32_t>();
-    KNN_HIP(hipMemsetAsync(g, 0, sizeof(int32_t) * G_COUNT, st));
-    {
-        const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
-        k_ingest<<<(unsigned)blocks, kBlock, 0, st>>>(points, n, d, colsA.as<float>(),
-                                                      idxA.as<int32_t>(), g);
-        KNN_HIP(hipGetLastError());
-        // stop before any split work if a coordinate is not finite
-        int32_t nonfinite = 0;
-        KNN_HIP(hipMemcpyAsync(&nonfinite, g + G_NONFINITE, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, st));
-        KNN_HIP(hipStreamSynchronize(st));
-        if (nonfinite) return fail(KNN_ENOTFINITE, "an input coordinate is NaN or infinite");
-    }
-    prof_mark(st, 1);
-
-    // ---- level passes: nodes above W points (and above the bucket size) -------
-    // a level's nodes hold more than W points each and are disjoint
-    const int64_t nn_cap = n / (W + 1) + 1;
-    const int64_t nb_cap = n / kChunk + nn_cap + 1;
-    const int64_t nbh_cap = n / kHistChunk + nn_cap + 1;
-    const int64_t lv_cap = (int64_t)max_depth + 2;
-    // every level-pass node and subtree entry descends from a level node
-    const int64_t big_cap = T + 2 * nn_cap * lv_cap + 2;
-    const int64_t sub_cap = std::min<int64_t>(n, big_cap);
-    LevelMem lvA(st), lvB(st);
-    DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), wave_left(st), blk_off(st),
-        d_big(st), d_subs(st), d_rng(st), planv(st), planx(st), pblk(st);
-    int32_t n_sub = 0, n_big = T, n_levels = 1;
-    std::vector<int32_t> h_g(G_COUNT, 0);
-    const Level0Host h0 = level0_tables(offsets, T, W, leaf);
-    const std::vector<SubEntry>& small = h0.small;
-    const std::vector<int32_t>& big_roots = h0.big_roots;
-    const int64_t largest = h0.largest;
-    const int32_t r0[2] = {0, T};
-    if (big_roots.empty()) {
-        n_sub = (int32_t)small.size();
-        KNN_HIP(d_subs.alloc(sizeof(SubEntry) * small.size()));
-        KNN_HIP(hipMemcpyAsync(d_subs.p, small.data(), sizeof(SubEntry) * small.size(),
-                               hipMemcpyHostToDevice, st));
-        KNN_HIP(d_big.alloc(sizeof(NodeRec) * T));
-        KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2));
-        KNN_HIP(hipMemcpyAsync(d_rng.p, r0, sizeof(r0), hipMemcpyHostToDevice, st));
-        KNN_HIP(hipStreamSynchronize(st));  // the host staging vector dies here
-    } else {
-        KNN_HIP(lvA.alloc(nn_cap, nb_cap, nbh_cap));
-        KNN_HIP(lvB.alloc(nn_cap, nb_cap, nbh_cap));
-        KNN_HIP(dimv.alloc(sizeof(int32_t) * nn_cap));
-        KNN_HIP(splitv.alloc(sizeof(float) * nn_cap));
-        KNN_HIP(nleft.alloc(sizeof(int32_t) * nn_cap));
-        KNN_HIP(samples.alloc(sizeof(float) * kWinStride * nn_cap));
-        KNN_HIP(hist.alloc(sizeof(uint32_t) * kWinRow * nn_cap));
-        KNN_HIP(wave_left.alloc(sizeof(uint32_t) * kWavesPerBlock * nb_cap));
-        KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
-        KNN_HIP(planv.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
-        KNN_HIP(planx.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
-        KNN_HIP(pblk.alloc(sizeof(int32_t) * kPlanStride * ((nn_cap + kPlanBlock - 1) / kPlanBlock)));
-        KNN_HIP(d_big.alloc(sizeof(NodeRec) * big_cap));
-        KNN_HIP(d_subs.alloc(sizeof(SubEntry) * sub_cap));
-        KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2 * (lv_cap + 1)));
-        {   // level 0: the large roots and their block tables
-            const int32_t nn0 = (int32_t)big_roots.size();
-            const auto& f = h0.f;
-            const auto &bnode = h0.bnode, &bbeg = h0.bbeg, &hnode = h0.hnode, &hbeg = h0.hbeg;
-            const Level& L0 = lvA.L;
-            int32_t* dst[8] = {L0.start, L0.count, L0.id, L0.parent, L0.depth, L0.blk0, L0.nblk,
-                               L0.hblk0};
-            for (int k = 0; k < 8; ++k)
-                KNN_HIP(hipMemcpyAsync(dst[k], f[k].data(), sizeof(int32_t) * nn0,
-                                       hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(L0.bnode, bnode.data(), sizeof(int32_t) * bnode.size(),
-                                   hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(L0.bbeg, bbeg.data(), sizeof(int32_t) * bbeg.size(),
-                                   hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(L0.hnode, hnode.data(), sizeof(int32_t) * hnode.size(),
-                                   hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(L0.hbeg, hbeg.data(), sizeof(int32_t) * hbeg.size(),
-                                   hipMemcpyHostToDevice, st));
-            const int32_t cnt[3] = {nn0, (int32_t)bnode.size(), (int32_t)hnode.size()};
-            KNN_HIP(hipMemcpyAsync(L0.cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice, st));
-            if (!small.empty())
-                KNN_HIP(hipMemcpyAsync(d_subs.p, small.data(), sizeof(SubEntry) * small.size(),
-                                       hipMemcpyHostToDevice, st));
-            const int32_t g0[G_COUNT] = {T, (int32_t)small.size(), 0, 0, 0, 0, 0, 0};
-            KNN_HIP(hipMemcpyAsync(g, g0, sizeof(g0), hipMemcpyHostToDevice, st));
-            KNN_HIP(hipMemcpyAsync(d_rng.p, r0, sizeof(r0), hipMemcpyHostToDevice, st));
-            KNN_HIP(hipStreamSynchronize(st));  // the host staging vectors die here
-        }
-        // levels expected for balanced splits; the host checks for more after that
-        const int expected = expected_levels(largest, W, leaf);
-        LevelWork lw{};
-        lw.cols[0] = colsA.as<float>();
-        lw.cols[1] = colsB.as<float>();
-        lw.idx[0] = idxA.as<int32_t>();
-        lw.idx[1] = idxB.as<int32_t>();
-        lw.dimv = dimv.as<int32_t>();
-        lw.splitv = splitv.as<float>();
-        lw.nleft = nleft.as<int32_t>();
-        lw.samples = samples.as<float>();
-        lw.hist = hist.as<uint32_t>();
-        lw.wave_left = wave_left.as<uint32_t>();
-        lw.blk_off = blk_off.as<uint32_t>();
-        lw.planv = planv.as<int32_t>();
-        lw.planx = planx.as<int32_t>();
-        lw.pblk = pblk.as<int32_t>();
-        lw.big = d_big.as<NodeRec>();
-        lw.subs = d_subs.as<SubEntry>();
-        lw.rng = d_rng.as<int32_t>();
-        lw.g = g;
-        lw.n = n;
-        lw.d = d;
-        lw.leaf = leaf;
-        lw.W = W;
-        lw.max_depth = max_depth;
-        lw.split_block_nodes = split_block_nodes;
-        lw.nn0 = (int64_t)big_roots.size();
-        lw.nn_cap = nn_cap;
-        lw.nb_cap = nb_cap;
-        lw.nbh_cap = nbh_cap;
-        lw.big_cap = big_cap;
-        lw.sub_cap = sub_cap;
-        Level cur = lvA.L, nxt = lvB.L;
-        int buf = 0;
-        for (int level = 0;; ++level) {
-            if (level >= lv_cap) return fail(KNN_EDEPTH, "tree deeper than max_depth");
-            enqueue_level(lw, cur, nxt, level, buf, true, st);
-            KNN_HIP(hipGetLastError());
-            n_levels = level + 2;  // depth ranges 0 .. level + 1 are recorded
-            std::swap(cur, nxt);
-            buf ^= 1;
-            if (level + 1 >= expected) {
-                int32_t h_nn = 0;
-                KNN_HIP(hipMemcpyAsync(&h_nn, cur.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-                KNN_HIP(hipMemcpyAsync(h_g.data(), g, sizeof(int32_t) * G_COUNT,
-                                       hipMemcpyDeviceToHost, st));
-                KNN_HIP(hipStreamSynchronize(st));
-                if (h_g[G_ERR] == KNN_EDEPTH) return fail(KNN_EDEPTH, "tree deeper than max_depth");
-                if (h_g[G_ERR]) return fail(KNN_EDEVICE, "level bookkeeping overflowed its buffers");
-                if (h_nn == 0) break;
-            }
-        }
-        n_sub = h_g[G_NSUB];
-        n_big = h_g[G_NEXT_ID];
-        {
-            uint64_t moved = 0;
-            std::memcpy(&moved, &h_g[G_MOVED], sizeof(moved));
-            prof_part_points((double)moved);
-        }
-        lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); wave_left.reset();
-        blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset(); planv.reset(); planx.reset();
-        pblk.reset();
-    }
-    prof_mark(st, 2);
-
-    // ---- subtree finish -----------------------------------------------------
-    DevBuf tnodes(st), tbox(st), subn(st), flags(st);
-    KNN_HIP(tnodes.alloc(sizeof(NodeRec) * 2 * n));
-    KNN_HIP(tbox.alloc(sizeof(float) * 2 * n * 2 * d));
-    KNN_HIP(subn.alloc(sizeof(int32_t) * n_sub));
-    KNN_HIP(flags.alloc(sizeof(int32_t) * 2));
-    KNN_HIP(hipMemsetAsync(flags.p, 0, sizeof(int32_t) * 2, st));
-    const int32_t Wt = finish_tile_points(d, W);
-    const size_t per_wave = finish_lds_bytes_per_wave(d, Wt);
-    const size_t lds = per_wave * kWavesPerBlock;
-    const int32_t fblocks = (n_sub + kWavesPerBlock - 1) / kWavesPerBlock;
-    FinishFn ff = finish_for(d);
-    if (!ff) return fail(KNN_EINVAL, "unsupported dimension");
-    if (lds > 64 * 1024)
-        KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ff),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(ff, dim3(fblocks), dim3(kBlock), lds, st, d_subs.as<SubEntry>(), n_sub,
-                       nullptr, colsA.as<float>(), idxA.as<int32_t>(), colsB.as<float>(),
-                       idxB.as<int32_t>(), n, leaf, Wt, max_depth, per_wave, pts.as<float>(),
-                       tnodes.as<NodeRec>(), tbox.as<float>(), subn.as<int32_t>(),
-                       flags.as<int32_t>(), flags.as<int32_t>() + 1);
-    KNN_HIP(hipGetLastError());
-    std::vector<int32_t> h_subn(n_sub);
-    int32_t h_flags[2] = {0, 0};
-    KNN_HIP(hipMemcpyAsync(h_subn.data(), subn.p, sizeof(int32_t) * n_sub, hipMemcpyDeviceToHost, st));
-    KNN_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, st));
-    KNN_HIP(hipStreamSynchronize(st));
-    prof_mark(st, 3);
-    if (h_flags[0] == KNN_EDEPTH) return fail(KNN_EDEPTH, "tree deeper than max_depth");
-    if (h_flags[0]) return fail(KNN_EDEVICE, "subtree finish failed");
-
-    // ---- ids, records, boxes --------------------------------------------------
-    std::vector<int32_t> h_base(n_sub);
-    int64_t total = n_big;
-    for (int32_t i = 0; i < n_sub; ++i) {
-        h_base[i] = (int32_t)total;
-        total += h_subn[i] - 1;
-    }
-    DevBuf nodes(st), bbox(st), d_base(st), badc(st);
-    KNN_HIP(nodes.alloc(sizeof(NodeRec) * total));
-    KNN_HIP(bbox.alloc(sizeof(float) * total * 2 * d));
-    KNN_HIP(badc.alloc(sizeof(unsigned long long)));
-    KNN_HIP(hipMemsetAsync(badc.p, 0, sizeof(unsigned long long), st));
-    KNN_HIP(d_base.alloc(sizeof(int32_t) * n_sub));
-    if (n_big > 1)
-        KNN_HIP(hipMemcpyAsync(nodes.p, d_big.p, sizeof(NodeRec) * n_big, hipMemcpyDeviceToDevice, st));
-    KNN_HIP(hipMemcpyAsync(d_base.p, h_base.data(), sizeof(int32_t) * n_sub, hipMemcpyHostToDevice, st));
-    k_compact<<<fblocks, kBlock, 0, st>>>(d_subs.as<SubEntry>(), n_sub, nullptr, subn.as<int32_t>(),
-                                          d_base.as<int32_t>(), tnodes.as<NodeRec>(),
-                                          tbox.as<float>(), d, nodes.as<NodeRec>(),
-                                          bbox.as<float>());
-    KNN_HIP(hipGetLastError());
-    for (int dep = n_levels - 1; dep >= 0; --dep) {
-        const int64_t cap = std::min<int64_t>(dep < 40 ? (int64_t)T << dep : total, total);
-        k_bbox_up<<<blocks_for(cap, kBlock), kBlock, 0, st>>>(d_rng.as<int32_t>() + 2 * dep,
-                                                             nodes.as<NodeRec>(), bbox.as<float>(), d);
-        KNN_HIP(hipGetLastError());
-    }
-    KNN_HIP(hipStreamSynchronize(st));
-    prof_mark(st, 4);
-
-    knn_tree* t = new knn_tree();
-    t->n = n;
-    t->d = d;
-    t->leaf = leaf;
-    t->n_trees = T;
-    t->depth = h_flags[1];
-    t->sub_pts = W;
-    t->n_nodes = total;
-    (void)hipGetDevice(&t->device);
-    t->bytes = (int64_t)(pts.bytes + nodes.bytes + bbox.bytes + badc.bytes);
-    t->pts = pts.as<float>();
-    t->nodes = nodes.as<NodeRec>();
-    t->bbox = bbox.as<float>();
-    t->bad = badc.as<unsigned long long>();
-    pts.release();
-    nodes.release();
-    bbox.release();
-    badc.release();
-    *out = t;
-    return KNN_OK;
-}
-
-
 // ---------------------------------------------------------------------------
-// Build plans: the build above for a fixed point count and forest layout,
-// with every buffer sized once at creation and no host round trip between
-// kernels.  A run is a fixed sequence of kernel launches (no allocation,
-// copy, fill or wait), so a HIP graph can capture it; results come back
-// through device status words that knn_build_plan_finish reads.
+// Device-side steps shared by the eager build and build plans: level 0 from
+// one uploaded copy, the end of the level passes, the subtree id bases and
+// the run status, so that no step between kernels needs the host.
 // ---------------------------------------------------------------------------
 
-// Status words of a plan run.
+// Blocks of the strided finish launch that takes the subtrees past the main
+// grid of a plan run.
+constexpr int kTailBlocks = 256;
+
+// Status words of a build.
 enum { PS_ERR = 0, PS_NSUB = 1, PS_NSUB_COMPACT = 2, PS_TOTAL = 3, PS_DEPTH = 4, PS_COUNT = 8 };
 
-// Level 0 as uploaded at plan creation.
+// Level 0 as uploaded (once per build, or once per plan).
 struct PlanLevel0 {
     const int32_t* f;        // [8][nn0]: start, count, id, parent, depth, blk0, nblk, hblk0
     const int32_t* bnode;    // [nb0]
@@ -2527,7 +2308,288 @@ __global__ void k_run_done(const int32_t* __restrict__ status, NodeRec* __restri
     for (int t = 0; t < 2 * d; ++t) bbox[(int64_t)i * 2 * d + t] = 0.0f;
 }
 
+
+// The words of level 0's upload: the node fields, the block tables, then the
+// small roots' subtree entries; and the device view of them at `dev`.
+std::vector<int32_t> level0_words(const Level0Host& h0)
+{
+    std::vector<int32_t> w;
+    for (int k = 0; k < 8; ++k) w.insert(w.end(), h0.f[k].begin(), h0.f[k].end());
+    for (auto* v : {&h0.bnode, &h0.bbeg, &h0.hnode, &h0.hbeg}) w.insert(w.end(), v->begin(), v->end());
+    const size_t at = w.size();
+    w.resize(at + h0.small.size() * (sizeof(SubEntry) / sizeof(int32_t)));
+    if (!h0.small.empty()) std::memcpy(w.data() + at, h0.small.data(), sizeof(SubEntry) * h0.small.size());
+    return w;
+}
+
+PlanLevel0 level0_view(const Level0Host& h0, const int32_t* dev, int32_t T)
+{
+    const size_t nn0 = h0.big_roots.size(), nb0 = h0.bnode.size(), nbh0 = h0.hbeg.size();
+    const int32_t* f = dev;
+    const int32_t* tab = f + 8 * nn0;
+    return PlanLevel0{f, tab, tab + nb0, tab + 2 * nb0, tab + 2 * nb0 + nbh0,
+                      reinterpret_cast<const SubEntry*>(tab + 2 * nb0 + 2 * nbh0),
+                      (int32_t)nn0, (int32_t)nb0, (int32_t)nbh0, (int32_t)h0.small.size(), T};
+}
+
+unsigned level0_blocks(const PlanLevel0& l0)
+{
+    const int64_t items = std::max<int64_t>({8 * (int64_t)l0.nn0, l0.nb0, l0.nbh0, l0.n_small, 1});
+    return (unsigned)std::min<int64_t>(blocks_for(items, kBlock), 4096);
+}
+
+// The error a build's status word records, as a return code with its message.
+int status_error(int32_t code)
+{
+    switch (code) {
+    case KNN_OK: return KNN_OK;
+    case KNN_ENOTFINITE: return fail(KNN_ENOTFINITE, "an input coordinate is NaN or infinite");
+    case KNN_EDEPTH: return fail(KNN_EDEPTH, "tree deeper than max_depth");
+    default: return fail(KNN_EDEVICE, "the build overflowed its buffers");
+    }
+}
+
+int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t max_depth,
+               int32_t W, int64_t split_block_nodes, const int64_t* offsets, int32_t T,
+               hipStream_t st, knn_tree** out)
+{
+    FinishFn ff = finish_for(d);
+    if (!ff) return fail(KNN_EINVAL, "unsupported dimension");
+    prof_mark(st, 0);
+    prof_part_begin();
+    // level 0's host words outlive every buffer below, whose release waits
+    // for the stream (and so for their upload)
+    const Level0Host h0 = level0_tables(offsets, T, W, leaf);
+    const std::vector<int32_t> l0host = level0_words(h0);
+    const int64_t nd = n * d;
+    // scratch and the tree's own buffers (pts, nodes, bbox) come from the
+    // library's block cache: a build that follows another, or a freed tree,
+    // reuses that memory instead of mapping fresh pages while the device waits
+    DevBuf colsA(st), colsB(st), idxA(st), idxB(st), pts(st), gbuf(st), l0buf(st);
+    // padded by one finish tile of rows: the finish reads whole rows of 64
+    // points, up to 64 * kGlobalRows - 1 elements past a node's last point
+    const int64_t tail = (int64_t)kWave * kGlobalRows;
+    KNN_HIP(colsA.alloc(sizeof(float) * (nd + tail)));
+    KNN_HIP(colsB.alloc(sizeof(float) * (nd + tail)));
+    KNN_HIP(idxA.alloc(sizeof(int32_t) * (n + tail)));
+    KNN_HIP(idxB.alloc(sizeof(int32_t) * (n + tail)));
+    KNN_HIP(pts.alloc(sizeof(float) * (n + kRowPad) * (d + 1)));
+    KNN_HIP(hipMemsetAsync(pts.as<float>() + n * (d + 1), 0, sizeof(float) * kRowPad * (d + 1), st));
+    // build counters, status words and the finish's error and depth flags
+    constexpr int kWords = G_COUNT + PS_COUNT + 2;
+    KNN_HIP(gbuf.alloc(sizeof(int32_t) * kWords));
+    int32_t* g = gbuf.as<int32_t>();
+    int32_t* status = g + G_COUNT;
+    int32_t* flags = status + PS_COUNT;
+    KNN_HIP(hipMemsetAsync(g, 0, sizeof(int32_t) * kWords, st));
+    KNN_HIP(l0buf.alloc(sizeof(int32_t) * l0host.size()));
+    KNN_HIP(hipMemcpyAsync(l0buf.p, l0host.data(), sizeof(int32_t) * l0host.size(),
+                           hipMemcpyHostToDevice, st));
+    {
+        const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
+        k_ingest<<<(unsigned)blocks, kBlock, 0, st>>>(points, n, d, colsA.as<float>(),
+                                                      idxA.as<int32_t>(), g);
+        KNN_HIP(hipGetLastError());
+    }
+    prof_mark(st, 1);
+
+    // ---- level passes: nodes above W points (and above the bucket size) -------
+    // a level's nodes hold more than W points each and are disjoint
+    const int64_t nn_cap = n / (W + 1) + 1;
+    const int64_t nb_cap = n / kChunk + nn_cap + 1;
+    const int64_t nbh_cap = n / kHistChunk + nn_cap + 1;
+    const int64_t lv_cap = (int64_t)max_depth + 2;
+    // every level-pass node and subtree entry descends from a level node
+    const int64_t big_cap = T + 2 * nn_cap * lv_cap + 2;
+    const int64_t sub_cap = std::min<int64_t>(n, big_cap);
+    const std::vector<int32_t>& big_roots = h0.big_roots;
+    const int32_t nn0 = (int32_t)big_roots.size();
+    LevelMem lvA(st), lvB(st);
+    DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), wave_left(st), blk_off(st),
+        d_big(st), d_subs(st), d_rng(st), planv(st), planx(st), pblk(st);
+    int32_t n_sub = (int32_t)h0.small.size(), n_big = T, n_levels = 1;
+    std::vector<int32_t> h_g(G_COUNT + PS_COUNT, 0);
+    if (nn0) {
+        KNN_HIP(lvA.alloc(nn_cap, nb_cap, nbh_cap));
+        KNN_HIP(lvB.alloc(nn_cap, nb_cap, nbh_cap));
+        KNN_HIP(dimv.alloc(sizeof(int32_t) * nn_cap));
+        KNN_HIP(splitv.alloc(sizeof(float) * nn_cap));
+        KNN_HIP(nleft.alloc(sizeof(int32_t) * nn_cap));
+        KNN_HIP(samples.alloc(sizeof(float) * kWinStride * nn_cap));
+        KNN_HIP(hist.alloc(sizeof(uint32_t) * kWinRow * nn_cap));
+        KNN_HIP(wave_left.alloc(sizeof(uint32_t) * kWavesPerBlock * nb_cap));
+        KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
+        KNN_HIP(planv.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
+        KNN_HIP(planx.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
+        KNN_HIP(pblk.alloc(sizeof(int32_t) * kPlanStride * ((nn_cap + kPlanBlock - 1) / kPlanBlock)));
+        KNN_HIP(d_big.alloc(sizeof(NodeRec) * big_cap));
+        KNN_HIP(d_subs.alloc(sizeof(SubEntry) * sub_cap));
+        KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2 * (lv_cap + 1)));
+    } else {
+        KNN_HIP(d_big.alloc(sizeof(NodeRec) * T));
+        KNN_HIP(d_subs.alloc(sizeof(SubEntry) * h0.small.size()));
+        KNN_HIP(d_rng.alloc(sizeof(int32_t) * 2));
+    }
+    {   // level 0 and the small roots from the upload; a non-finite
+        // coordinate leaves both empty (checked at the next host wait)
+        const PlanLevel0 l0 = level0_view(h0, l0buf.as<int32_t>(), T);
+        k_run_level0<<<level0_blocks(l0), kBlock, 0, st>>>(l0, lvA.L, d_subs.as<SubEntry>(), g,
+                                                           d_rng.as<int32_t>(), status);
+        KNN_HIP(hipGetLastError());
+    }
+    if (nn0) {
+        // levels expected for balanced splits; the host checks for more after that
+        const int expected = expected_levels(h0.largest, W, leaf);
+        LevelWork lw{};
+        lw.cols[0] = colsA.as<float>();
+        lw.cols[1] = colsB.as<float>();
+        lw.idx[0] = idxA.as<int32_t>();
+        lw.idx[1] = idxB.as<int32_t>();
+        lw.dimv = dimv.as<int32_t>();
+        lw.splitv = splitv.as<float>();
+        lw.nleft = nleft.as<int32_t>();
+        lw.samples = samples.as<float>();
+        lw.hist = hist.as<uint32_t>();
+        lw.wave_left = wave_left.as<uint32_t>();
+        lw.blk_off = blk_off.as<uint32_t>();
+        lw.planv = planv.as<int32_t>();
+        lw.planx = planx.as<int32_t>();
+        lw.pblk = pblk.as<int32_t>();
+        lw.big = d_big.as<NodeRec>();
+        lw.subs = d_subs.as<SubEntry>();
+        lw.rng = d_rng.as<int32_t>();
+        lw.g = g;
+        lw.n = n;
+        lw.d = d;
+        lw.leaf = leaf;
+        lw.W = W;
+        lw.max_depth = max_depth;
+        lw.split_block_nodes = split_block_nodes;
+        lw.nn0 = nn0;
+        lw.nn_cap = nn_cap;
+        lw.nb_cap = nb_cap;
+        lw.nbh_cap = nbh_cap;
+        lw.big_cap = big_cap;
+        lw.sub_cap = sub_cap;
+        Level cur = lvA.L, nxt = lvB.L;
+        int buf = 0;
+        for (int level = 0;; ++level) {
+            if (level >= lv_cap) return fail(KNN_EDEPTH, "tree deeper than max_depth");
+            enqueue_level(lw, cur, nxt, level, buf, true, st);
+            KNN_HIP(hipGetLastError());
+            n_levels = level + 2;  // depth ranges 0 .. level + 1 are recorded
+            std::swap(cur, nxt);
+            buf ^= 1;
+            if (level + 1 >= expected) {
+                // the counters and the status words in one read
+                KNN_HIP(hipMemcpyAsync(h_g.data(), g, sizeof(int32_t) * (G_COUNT + PS_COUNT),
+                                       hipMemcpyDeviceToHost, st));
+                KNN_HIP(hipStreamSynchronize(st));
+                if (h_g[G_COUNT + PS_ERR]) return status_error(h_g[G_COUNT + PS_ERR]);
+                if (h_g[G_ERR] == KNN_EDEPTH) return fail(KNN_EDEPTH, "tree deeper than max_depth");
+                if (h_g[G_ERR]) return fail(KNN_EDEVICE, "level bookkeeping overflowed its buffers");
+                if (h_g[G_LEVEL_NODES] == 0) break;
+            }
+        }
+        n_sub = h_g[G_NSUB];
+        n_big = h_g[G_NEXT_ID];
+        {
+            uint64_t moved = 0;
+            std::memcpy(&moved, &h_g[G_MOVED], sizeof(moved));
+            prof_part_points((double)moved);
+        }
+        lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); wave_left.reset();
+        blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset(); planv.reset(); planx.reset();
+        pblk.reset();
+    }
+    // the subtree count on the device (0 after a non-finite coordinate)
+    k_run_levels_done<<<1, kWave, 0, st>>>(nullptr, g, d_rng.as<int32_t>(), n_levels, status);
+    prof_mark(st, 2);
+
+    // ---- subtree finish -----------------------------------------------------
+    DevBuf tnodes(st), tbox(st), subn(st), d_base(st);
+    KNN_HIP(tnodes.alloc(sizeof(NodeRec) * 2 * n));
+    KNN_HIP(tbox.alloc(sizeof(float) * 2 * n * 2 * d));
+    KNN_HIP(subn.alloc(sizeof(int32_t) * n_sub));
+    KNN_HIP(d_base.alloc(sizeof(int32_t) * n_sub));
+    const int32_t Wt = finish_tile_points(d, W);
+    const size_t per_wave = finish_lds_bytes_per_wave(d, Wt);
+    const size_t lds = per_wave * kWavesPerBlock;
+    const int32_t fblocks = (n_sub + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (lds > 64 * 1024)
+        KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ff),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(ff, dim3(fblocks), dim3(kBlock), lds, st, d_subs.as<SubEntry>(), 0, n_sub,
+                       status + PS_NSUB, colsA.as<float>(), idxA.as<int32_t>(), colsB.as<float>(),
+                       idxB.as<int32_t>(), n, leaf, Wt, max_depth, per_wave, pts.as<float>(),
+                       tnodes.as<NodeRec>(), tbox.as<float>(), subn.as<int32_t>(), flags,
+                       flags + 1);
+    KNN_HIP(hipGetLastError());
+    // ids: level-pass nodes first, then each subtree's nodes in subtree order
+    k_run_bases<<<1, kPlanBlock, 0, st>>>(subn.as<int32_t>(), g, flags, d_base.as<int32_t>(),
+                                          status, (int64_t)INT32_MAX, d_rng.as<int32_t>(),
+                                          n_levels);
+    KNN_HIP(hipGetLastError());
+    int32_t h_status[PS_COUNT] = {};
+    KNN_HIP(hipMemcpyAsync(h_status, status, sizeof(h_status), hipMemcpyDeviceToHost, st));
+    KNN_HIP(hipStreamSynchronize(st));
+    prof_mark(st, 3);
+    if (int rc = status_error(h_status[PS_ERR])) return rc;
+
+    // ---- records and boxes ----------------------------------------------------
+    const int64_t total = h_status[PS_TOTAL];
+    DevBuf nodes(st), bbox(st), badc(st);
+    KNN_HIP(nodes.alloc(sizeof(NodeRec) * total));
+    KNN_HIP(bbox.alloc(sizeof(float) * total * 2 * d));
+    KNN_HIP(badc.alloc(sizeof(unsigned long long)));
+    KNN_HIP(hipMemsetAsync(badc.p, 0, sizeof(unsigned long long), st));
+    if (n_big > 1)
+        KNN_HIP(hipMemcpyAsync(nodes.p, d_big.p, sizeof(NodeRec) * n_big, hipMemcpyDeviceToDevice, st));
+    k_compact<<<fblocks, kBlock, 0, st>>>(d_subs.as<SubEntry>(), n_sub, status + PS_NSUB_COMPACT,
+                                          subn.as<int32_t>(), d_base.as<int32_t>(),
+                                          tnodes.as<NodeRec>(), tbox.as<float>(), d,
+                                          nodes.as<NodeRec>(), bbox.as<float>());
+    KNN_HIP(hipGetLastError());
+    for (int dep = n_levels - 1; dep >= 0; --dep) {
+        const int64_t cap = std::min<int64_t>(dep < 40 ? (int64_t)T << dep : total, total);
+        k_bbox_up<<<blocks_for(cap, kBlock), kBlock, 0, st>>>(d_rng.as<int32_t>() + 2 * dep,
+                                                             nodes.as<NodeRec>(), bbox.as<float>(), d);
+        KNN_HIP(hipGetLastError());
+    }
+    KNN_HIP(hipStreamSynchronize(st));
+    prof_mark(st, 4);
+
+    knn_tree* t = new knn_tree();
+    t->n = n;
+    t->d = d;
+    t->leaf = leaf;
+    t->n_trees = T;
+    t->depth = h_status[PS_DEPTH];
+    t->sub_pts = W;
+    t->n_nodes = total;
+    (void)hipGetDevice(&t->device);
+    t->bytes = (int64_t)(pts.bytes + nodes.bytes + bbox.bytes + badc.bytes);
+    t->pts = pts.as<float>();
+    t->nodes = nodes.as<NodeRec>();
+    t->bbox = bbox.as<float>();
+    t->bad = badc.as<unsigned long long>();
+    pts.release();
+    nodes.release();
+    bbox.release();
+    badc.release();
+    *out = t;
+    return KNN_OK;
+}
+
 }  // namespace knn
+
+// ---------------------------------------------------------------------------
+// Build plans: the build above for a fixed point count and forest layout,
+// with every buffer sized once at creation and no host round trip between
+// kernels.  A run is a fixed sequence of kernel launches (no allocation,
+// copy, fill or wait), so a HIP graph can capture it; results come back
+// through device status words that knn_build_plan_finish reads.
+// ---------------------------------------------------------------------------
 
 struct knn_build_plan {
     int32_t device = 0;
@@ -2538,7 +2600,8 @@ struct knn_build_plan {
     int32_t Wt = 0;
     size_t per_wave = 0, lds = 0;
     unsigned fgrid = 0;
-    knn::FinishFn ff = nullptr;
+    knn::FinishFn ff = nullptr;       // one subtree per wavefront
+    knn::FinishFn ff_tail = nullptr;  // strided, for subtrees past ff's grid
     std::vector<void*> blocks;  // every device block the plan holds (block cache)
     knn::LevelWork lw{};
     knn::Level lv[2]{};
@@ -2624,7 +2687,6 @@ int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t T, int32_t
     int32_t* lvbuf[2] = {nullptr, nullptr};
     int32_t* rng = nullptr;
     int32_t* l0buf = nullptr;
-    SubEntry* small = nullptr;
     KNN_HIP(plan_alloc(P.get(), &w.cols[0], nd + tail));
     KNN_HIP(plan_alloc(P.get(), &w.cols[1], nd + tail));
     KNN_HIP(plan_alloc(P.get(), &w.idx[0], n + tail));
@@ -2661,29 +2723,17 @@ int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t T, int32_t
                            (size_t)kPlanStride * ((P->nn_cap + kPlanBlock - 1) / kPlanBlock)));
     }
     // level 0 and the small roots, uploaded once
-    const size_t nb0 = h0.bnode.size(), nbh0 = h0.hbeg.size();
-    const size_t l0_words = 8 * (size_t)nn0 + 2 * nb0 + 2 * nbh0;
-    KNN_HIP(plan_alloc(P.get(), &l0buf, l0_words));
-    KNN_HIP(plan_alloc(P.get(), &small, h0.small.size()));
     {
-        std::vector<int32_t> host;
-        host.reserve(l0_words);
-        for (int k = 0; k < 8; ++k) host.insert(host.end(), h0.f[k].begin(), h0.f[k].end());
-        for (auto* v : {&h0.bnode, &h0.bbeg, &h0.hnode, &h0.hbeg})
-            host.insert(host.end(), v->begin(), v->end());
+        const std::vector<int32_t> host = level0_words(h0);
+        KNN_HIP(plan_alloc(P.get(), &l0buf, host.size()));
         if (!host.empty())
             KNN_HIP(hipMemcpyAsync(l0buf, host.data(), sizeof(int32_t) * host.size(),
                                    hipMemcpyHostToDevice, st));
-        if (!h0.small.empty())
-            KNN_HIP(hipMemcpyAsync(small, h0.small.data(), sizeof(SubEntry) * h0.small.size(),
-                                   hipMemcpyHostToDevice, st));
         // the pad rows past the last point read as zeros
         KNN_HIP(hipMemsetAsync(P->pts + n * (d + 1), 0, sizeof(float) * kRowPad * (d + 1), st));
-        KNN_HIP(hipStreamSynchronize(st));  // the host copies die here
+        KNN_HIP(hipStreamSynchronize(st));  // the host copy dies here
     }
-    P->l0 = PlanLevel0{l0buf, l0buf + 8 * (size_t)nn0, l0buf + 8 * (size_t)nn0 + nb0,
-                       l0buf + 8 * (size_t)nn0 + 2 * nb0, l0buf + 8 * (size_t)nn0 + 2 * nb0 + nbh0,
-                       small, nn0, (int32_t)nb0, (int32_t)nbh0, (int32_t)h0.small.size(), T};
+    P->l0 = level0_view(h0, l0buf, T);
     w.big = P->nodes;  // level-pass records go straight to their final ids
     w.rng = rng;
     w.g = g;
@@ -2700,12 +2750,14 @@ int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t T, int32_t
     w.big_cap = P->big_cap;
     w.sub_cap = P->sub_cap;
     P->ff = ff;
+    P->ff_tail = finish_for(d, true);
     P->Wt = finish_tile_points(d, W);
     P->per_wave = finish_lds_bytes_per_wave(d, P->Wt);
     P->lds = P->per_wave * kWavesPerBlock;
     if (P->lds > 64 * 1024)
-        KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ff),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P->lds));
+        for (FinishFn f : {P->ff, P->ff_tail})
+            KNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)P->lds));
     // one wavefront per subtree for the usual count (subtrees hold more than
     // W / 2 points when splits are near even); more are taken in strides
     const int64_t usual = std::min<int64_t>(P->sub_cap, 3 * n / W + 2 * (int64_t)T + 256);
@@ -2743,13 +2795,8 @@ int plan_run(knn_build_plan* P, const float* points, hipStream_t st)
         const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
         k_ingest<<<(unsigned)blocks, kBlock, 0, st>>>(points, n, d, w.cols[0], w.idx[0], w.g);
     }
-    {
-        const PlanLevel0& l0 = P->l0;
-        const int64_t items = std::max<int64_t>({8 * (int64_t)l0.nn0, l0.nb0, l0.nbh0,
-                                                 l0.n_small, 1});
-        k_run_level0<<<(unsigned)std::min<int64_t>(blocks_for(items, kBlock), 4096), kBlock, 0,
-                       st>>>(l0, P->lv[0], w.subs, w.g, w.rng, P->status);
-    }
+    k_run_level0<<<level0_blocks(P->l0), kBlock, 0, st>>>(P->l0, P->lv[0], w.subs, w.g, w.rng,
+                                                          P->status);
     int buf = 0;
     for (int level = 0; level < P->levels; ++level) {
         enqueue_level(w, P->lv[buf], P->lv[buf ^ 1], level, buf, false, st);
@@ -2757,10 +2804,15 @@ int plan_run(knn_build_plan* P, const float* points, hipStream_t st)
     }
     k_run_levels_done<<<1, 64, 0, st>>>(P->levels ? P->lv[buf].cnt : nullptr, w.g, w.rng,
                                         P->levels + 1, P->status);
-    hipLaunchKernelGGL(P->ff, dim3(P->fgrid), dim3(kBlock), P->lds, st, w.subs, 0,
+    hipLaunchKernelGGL(P->ff, dim3(P->fgrid), dim3(kBlock), P->lds, st, w.subs, 0, 0,
                        P->status + PS_NSUB, w.cols[0], w.idx[0], w.cols[1], w.idx[1], n, P->leaf,
                        P->Wt, P->max_depth, P->per_wave, P->pts, P->tnodes, P->tbox, P->subn,
                        P->flags, P->flags + 1);
+    // subtrees past the main grid (uneven splits), if any
+    hipLaunchKernelGGL(P->ff_tail, dim3(kTailBlocks), dim3(kBlock), P->lds, st, w.subs,
+                       (int32_t)(P->fgrid * kWavesPerBlock), 0, P->status + PS_NSUB, w.cols[0],
+                       w.idx[0], w.cols[1], w.idx[1], n, P->leaf, P->Wt, P->max_depth,
+                       P->per_wave, P->pts, P->tnodes, P->tbox, P->subn, P->flags, P->flags + 1);
     k_run_bases<<<1, kPlanBlock, 0, st>>>(P->subn, w.g, P->flags, P->base, P->status,
                                           P->node_cap, w.rng, P->levels + 1);
     k_compact<<<P->fgrid, kBlock, 0, st>>>(w.subs, 0, P->status + PS_NSUB_COMPACT, P->subn,
@@ -2789,12 +2841,7 @@ int plan_finish(knn_build_plan* P, hipStream_t st)
     KNN_HIP(hipStreamSynchronize(st));
     knn_tree* t = P->tree;
     t->n_nodes = h[PS_ERR] ? P->T : h[PS_TOTAL];
-    switch (h[PS_ERR]) {
-    case KNN_OK: return KNN_OK;
-    case KNN_ENOTFINITE: return fail(KNN_ENOTFINITE, "an input coordinate is NaN or infinite");
-    case KNN_EDEPTH: return fail(KNN_EDEPTH, "tree deeper than the plan's max_depth");
-    default: return fail(KNN_EDEVICE, "the build overflowed the plan's buffers");
-    }
+    return status_error(h[PS_ERR]);
 }
 
 int plan_destroy(knn_build_plan* P)
