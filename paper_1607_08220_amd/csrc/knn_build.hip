@@ -2245,39 +2245,60 @@ __global__ void k_run_levels_done(const int32_t* __restrict__ left, const int32_
 
 // Final ids of the subtree nodes: subtree i's nodes other than its root get
 // ids base[i] .. base[i] + sub_nodes[i] - 2, after the level-pass ids, in
-// subtree order (the eager build's host prefix sum).  One block of
-// kPlanBlock threads, each over a contiguous run of subtrees.  A finish error
-// (or too many nodes) stops the run as k_run_levels_done does.
+// subtree order (the eager build's host prefix sum).  One block, over passes
+// of 8192 subtrees staged in LDS (coalesced loads and stores; each thread
+// scans 8 consecutive subtrees).  A finish error (or too many nodes) stops
+// the run as k_run_levels_done does.
 __global__ __launch_bounds__(kPlanBlock) void k_run_bases(
     const int32_t* __restrict__ sub_nodes, const int32_t* __restrict__ g,
     const int32_t* __restrict__ flags, int32_t* __restrict__ base,
     int32_t* __restrict__ status, int64_t node_cap, int32_t* __restrict__ rng, int n_rng)
 {
+    constexpr int kChunkN = 8192;               // subtrees per pass, staged in LDS
+    constexpr int kPer = kChunkN / kPlanBlock;  // consecutive subtrees per thread
+    __shared__ int32_t tile[kChunkN];
     __shared__ long long wsum[kPlanBlock / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int ns = status[PS_NSUB];
     const int64_t n_big = g[G_NEXT_ID];
-    const int seg = (ns + kPlanBlock - 1) / kPlanBlock;
-    const int lo = min(t * seg, ns), hi = min(lo + seg, ns);
-    long long mine = 0;
-    for (int i = lo; i < hi; ++i) mine += sub_nodes[i] - 1;
-    long long x = mine;
-    for (int o = 1; o < 64; o <<= 1) {
-        const long long y = __shfl_up(x, o);
-        if (lane >= o) x += y;
+    long long carry = n_big;  // first id of the pass's first subtree's nodes
+    for (int c0 = 0; c0 < ns; c0 += kChunkN) {
+        const int cn = min(kChunkN, ns - c0);
+        for (int i = t; i < cn; i += kPlanBlock) tile[i] = sub_nodes[c0 + i] - 1;
+        __syncthreads();
+        int v[kPer];
+        long long mine = 0;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int i = t * kPer + r;
+            v[r] = i < cn ? tile[i] : 0;
+            mine += v[r];
+        }
+        long long x = mine;
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        long long before = 0, all = 0;
+        for (int j = 0; j < kPlanBlock / 64; ++j) {
+            if (j < w) before += wsum[j];
+            all += wsum[j];
+        }
+        long long run = carry + before + x - mine;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int i = t * kPer + r;
+            if (i < cn) tile[i] = (int32_t)run;
+            run += v[r];
+        }
+        carry += all;
+        __syncthreads();
+        for (int i = t; i < cn; i += kPlanBlock) base[c0 + i] = tile[i];
+        __syncthreads();  // tile and wsum are reused by the next pass
     }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    long long before = 0, all = 0;
-    for (int j = 0; j < kPlanBlock / 64; ++j) {
-        if (j < w) before += wsum[j];
-        all += wsum[j];
-    }
-    long long run = n_big + before + x - mine;
-    for (int i = lo; i < hi; ++i) {
-        base[i] = (int32_t)run;
-        run += sub_nodes[i] - 1;
-    }
+    const long long all = carry - n_big;
     if (t == 0) {
         const long long total = n_big + all;
         int err = status[PS_ERR];
