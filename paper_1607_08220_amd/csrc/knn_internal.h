@@ -190,6 +190,9 @@ struct QuerySpec {
 };
 
 int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t stream);
+// Device workspace query_tree takes for qs (the grouping of queries by home
+// leaf, when the traversal form it picks groups them); 0 otherwise.
+size_t query_workspace_bytes(const knn_tree* t, const QuerySpec& qs);
 // Record that `stream` has enqueued work reading the tree (skipped while the
 // stream is being captured into a graph).
 int note_tree_use(const knn_tree* t, hipStream_t stream);

@@ -312,6 +312,58 @@ int note_tree_use(const knn_tree* t, hipStream_t st)
     return KNN_OK;
 }
 
+namespace {
+
+// The traversal form query_tree takes for qs, and the sizes of its grouping.
+struct FormChoice {
+    bool use_team, use_wave, grouped;
+    int trav;     // the asked form with an unusable team request dropped
+    int team;     // lanes per query of the team form
+    int shift;    // grouping key: packed position >> shift
+    int64_t N;    // counting-sort buckets (0 without grouping)
+    int64_t nsb;  // their scan blocks
+    size_t bytes; // workspace
+};
+
+FormChoice choose_form(const knn_tree* t, const QuerySpec& qs)
+{
+    FormChoice f{};
+    const int d = t->d;
+    const int64_t m = qs.m;
+    // one wavefront per query (the tree's depth bounds the lanes' stack):
+    // asked for, or by default for batches too small to fill the device with
+    // one lane per query; it runs in input order (grouping by home leaf costs
+    // more than the coherence it buys a wavefront that walks one query)
+    // a team of lanes per query: asked for, or by default for mid-size batches
+    // of deep (high-dimensional) searches; k and the tree's depth must fit
+    const bool high = d >= kStackMinDim;
+    const bool team_default = qs.traversal == 0 && high && m > kWaveQueriesMaxHigh &&
+                              m <= kTeamQueriesMax;
+    f.team = qs.team ? qs.team : kTeamDefault;
+    f.use_team = (qs.traversal == 4 || team_default) && qs.stats == nullptr &&
+                 qs.k <= f.team && t->depth + 1 <= f.team;
+    f.trav = qs.traversal == 4 && !f.use_team ? 0 : qs.traversal;
+    const bool wave_ok = t->depth + 1 <= kWave && qs.stats == nullptr;
+    const int64_t wave_max = high ? kWaveQueriesMaxHigh : kWaveQueriesMax;
+    f.use_wave = !f.use_team && wave_ok && (f.trav == 3 || (f.trav == 0 && m <= wave_max));
+    f.grouped = qs.order != 1 && !f.use_wave;
+    // key range: packed positions >> shift, at most 2^22 buckets
+    while ((t->n >> f.shift) > (int64_t(1) << 22)) ++f.shift;
+    f.N = f.grouped ? (t->n >> f.shift) + 1 : 0;
+    f.nsb = (f.N + kScanChunk - 1) / kScanChunk;
+    const int64_t mg = f.grouped ? m : 0;
+    // workspace: cnt[N], block sums[nsb], home[m], order[m], shome[m]
+    f.bytes = sizeof(uint32_t) * (size_t)(f.N + f.nsb) + sizeof(int32_t) * 3 * (size_t)mg;
+    return f;
+}
+
+}  // namespace
+
+size_t query_workspace_bytes(const knn_tree* t, const QuerySpec& qs)
+{
+    return choose_form(t, qs).bytes;
+}
+
 int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
 {
     const int d = t->d;
@@ -322,31 +374,11 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     prof_mark(st, 5);
     const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
     const unsigned tgrid = (unsigned)((grid + kXcds - 1) / kXcds * kXcds);  // multiple of 8
-    // one wavefront per query (the tree's depth bounds the lanes' stack):
-    // asked for, or by default for batches too small to fill the device with
-    // one lane per query; it runs in input order (grouping by home leaf costs
-    // more than the coherence it buys a wavefront that walks one query)
-    // a team of lanes per query: asked for, or by default for mid-size batches
-    // of deep (high-dimensional) searches; k and the tree's depth must fit
-    const bool high = d >= kStackMinDim;
-    const bool team_default = qs.traversal == 0 && high && m > kWaveQueriesMaxHigh &&
-                              m <= kTeamQueriesMax;
-    const int team = qs.team ? qs.team : kTeamDefault;
-    const bool use_team = (qs.traversal == 4 || team_default) && qs.stats == nullptr &&
-                          qs.k <= team && t->depth + 1 <= team;
-    const int trav = qs.traversal == 4 && !use_team ? 0 : qs.traversal;
-    const bool wave_ok = t->depth + 1 <= kWave && qs.stats == nullptr;
-    const int64_t wave_max = high ? kWaveQueriesMaxHigh : kWaveQueriesMax;
-    const bool use_wave = !use_team && wave_ok && (trav == 3 || (trav == 0 && m <= wave_max));
-    const bool grouped = qs.order != 1 && !use_wave;
-    // key range: packed positions >> shift, at most 2^22 buckets
-    int shift = 0;
-    while ((t->n >> shift) > (int64_t(1) << 22)) ++shift;
-    const int64_t N = grouped ? (t->n >> shift) + 1 : 0;
-    const int64_t nsb = (N + kScanChunk - 1) / kScanChunk;
-    const int64_t mg = grouped ? m : 0;
-    // workspace: cnt[N], block sums[nsb], home[m], order[m], shome[m]
-    const size_t bytes = sizeof(uint32_t) * (size_t)(N + nsb) + sizeof(int32_t) * 3 * (size_t)mg;
+    const FormChoice f = choose_form(t, qs);
+    const bool use_team = f.use_team, use_wave = f.use_wave, grouped = f.grouped;
+    const int trav = f.trav, team = f.team, shift = f.shift;
+    const int64_t N = f.N, nsb = f.nsb, mg = grouped ? m : 0;
+    const size_t bytes = f.bytes;
     StreamBuf ws;
     ws.s = st;
     void* base = nullptr;

@@ -425,19 +425,25 @@ struct knn_server {
 
 namespace {
 
-// Device bytes a batch needs: staging for its queries, self ids, per-query
-// k and output offsets, and results, plus the grouping workspace of the
-// query path when it runs.
-size_t batch_bytes(const knn_tree* t, int64_t total, int64_t outputs)
+// The query of a batch of `total` queries whose largest k is kmax (its
+// device pointers are filled in at launch).
+knn::QuerySpec batch_query(int64_t total, int32_t kmax)
 {
-    size_t b = (size_t)total * (sizeof(float) * t->d + sizeof(int32_t) * 2 + sizeof(int64_t)) +
-               (size_t)outputs * 8;
-    if (total >= kGroupMin) {
-        int shift = 0;
-        while ((t->n >> shift) > (int64_t(1) << 22)) ++shift;
-        b += sizeof(uint32_t) * ((size_t)(t->n >> shift) + 2 + 4096) + sizeof(int32_t) * 3 * total;
-    }
-    return b;
+    knn::QuerySpec qs;
+    qs.m = total;
+    qs.k = kmax;
+    qs.order = total >= kGroupMin ? 0 : 1;
+    qs.batch = knn::kDefaultLeafBatch;
+    return qs;
+}
+
+// Device bytes a batch needs: staging for its queries, self ids, per-query
+// k and output offsets, and results, plus the workspace of the query path
+// (its grouping, when the traversal form it picks groups).
+size_t batch_bytes(const knn_tree* t, int64_t total, int64_t outputs, int32_t kmax)
+{
+    return (size_t)total * (sizeof(float) * t->d + sizeof(int32_t) * 2 + sizeof(int64_t)) +
+           (size_t)outputs * 8 + knn::query_workspace_bytes(t, batch_query(total, kmax));
 }
 
 int launch_batch(knn_server* s, Batch& b)
@@ -477,15 +483,11 @@ int launch_batch(knn_server* s, Batch& b)
     const unsigned g1 = (unsigned)((total + kBlockS - 1) / kBlockS);
     k_gather<<<g1, kBlockS, 0, b.stream>>>(T, q, self, qk, qout);
     KNN_HIP(hipGetLastError());
-    knn::QuerySpec qs;
+    knn::QuerySpec qs = batch_query(total, b.kmax);
     qs.queries = q;
-    qs.m = total;
-    qs.k = b.kmax;
     qs.qk = qk;
     qs.qout = qout;
     qs.self_ids = self;
-    qs.order = total >= kGroupMin ? 0 : 1;
-    qs.batch = knn::kDefaultLeafBatch;
     qs.out_idx = oi;
     qs.out_d2 = od;
     const int rc = knn::query_tree(t, qs, b.stream);
@@ -665,7 +667,7 @@ void worker_loop(knn_server* s)
                 }
             }
             b.queries = total;
-            b.bytes = batch_bytes(t, total, b.outputs);
+            b.bytes = batch_bytes(t, total, b.outputs, b.kmax);
             if (!s->inflight.empty() && s->inflight_bytes + (int64_t)b.bytes > s->budget) {
                 // not enough memory beside the batches in flight: wait for one to retire
                 for (auto it = b.reqs.rbegin(); it != b.reqs.rend(); ++it) s->pending.push_front(*it);
