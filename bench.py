@@ -502,8 +502,8 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md and not implemented",
+        print(json.dumps({"error": "runs on one GPU only: the sharded multi-GPU path (each "
+                                   "GPU owning a region of the global tree) is not implemented",
                           "n_gpus": max(args.gpus, world)}))
         return 2
 

@@ -44,7 +44,7 @@ def test_pins_catch_planted_mistake(tmp_path, mid):
     assert failures, f"no pin noticed mutant {mid}: {what}"
 
 
-def test_oracle_cfg1_kd_equals_bf(orc):
+def test_oracle_tiny_uniform_kd_equals_bf(orc):
     """The 65,536-point uniform workload: KD32 == BF32 on all 4,096 queries."""
     from paper_1607_08220_amd import inputs
     w = inputs.workload("tiny_uniform")
