@@ -34,7 +34,7 @@ def dist64(X: np.ndarray, q: np.ndarray, ids: np.ndarray) -> np.ndarray:
     return acc
 
 
-def _judge(a: float, b: float, d: int) -> str:
+def _classify_pair(a: float, b: float, d: int) -> str:
     if a == b or abs(a - b) < 1e-6 * max(a, b):
         return "rule"
     g = (d + 2) * U32
@@ -61,13 +61,13 @@ def classify(X, Q, idx32, idx64, d64) -> dict:
         # rank by rank, where the indices differ
         for j in np.flatnonzero(idx32[r][valid] != idx64[r][valid]):
             out["differing_ranks"] += 1
-            v = _judge(float(mine[j]), float(d64[r, j]), d)
+            v = _classify_pair(float(mine[j]), float(d64[r, j]), d)
             if v == "bad":
                 out["bad"].append((int(r), int(j), float(mine[j]), float(d64[r, j])))
             else:
                 out[v] += 1
         # the multiset of FP64 distances of the returned set, rank by rank
         for j, (a, b) in enumerate(zip(np.sort(mine), d64[r][valid])):
-            if _judge(float(a), float(b), d) == "bad":
+            if _classify_pair(float(a), float(b), d) == "bad":
                 out["bad"].append((int(r), int(j), float(a), float(b)))
     return out
