@@ -497,6 +497,8 @@ def main() -> int:
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the per-call loop's capacity")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--plasma-only", action="store_true",
+                    help="run only the plasma-like 4-D bucket-size sweep (for profiling it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -512,6 +514,12 @@ def main() -> int:
     from paper_1607_08220_amd import inputs
 
     knn.load_library()
+    if args.plasma_only:
+        knn.knn_set_profiling(True)
+        threads = min(16, len(os.sched_getaffinity(0)))
+        print(json.dumps({"plasma_4d": bench_plasma(knn, torch, torch.device("cuda:0"), threads)}),
+              flush=True)
+        return 0
     t0 = time.perf_counter()
     w = inputs.workload("cosmo_clustered", scale=args.scale)
     n, d = w.points.shape
