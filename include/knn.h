@@ -419,9 +419,12 @@ int knn_tree_export(const knn_tree* t, knn_tree_host* h);
 /* Builds take their scratch and the trees' memory from a cache of device
  * blocks kept by the library (per device), which gives memory a build or a
  * freed tree handed back to later builds instead of mapping fresh memory;
- * at most 96 GiB of unused blocks are kept.  This call waits for the current
- * device and frees every unused block (and trims the device's stream-ordered
- * pool, which query workspaces come from). */
+ * at most 96 GiB of unused blocks are kept.  Query workspaces and serving
+ * batches come from the device's default stream-ordered pool, whose release
+ * threshold the library raises to 8 GiB on first use (so freed workspace stays
+ * mapped for the next call instead of being returned at every
+ * synchronisation).  This call waits for the current device, frees every
+ * unused block and trims that pool. */
 int knn_release_memory(void);
 
 /* Message describing the last failure of the calling thread. */

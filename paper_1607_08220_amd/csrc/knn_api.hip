@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -121,6 +122,35 @@ void cache_free(void* p)
     g_cache_free_bytes += it->second.second;
     if (g_cache_free_bytes > kCacheKeepMax) (void)cache_shrink(-1, kCacheKeepMax);
 }
+
+// Bytes of freed memory the default pool keeps mapped between calls.
+constexpr uint64_t kPoolKeep = 8ull << 30;
+
+hipError_t keep_pool_memory(hipStream_t st)
+{
+    static std::mutex mu;
+    static std::vector<bool> done;
+    // not while `st` is being captured (the pool is left as it is until a
+    // call outside a capture)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)done.size() > dev && done[dev]) return hipSuccess;
+    hipMemPool_t pool;
+    e = hipDeviceGetDefaultMemPool(&pool, dev);
+    if (e != hipSuccess) return e;
+    uint64_t keep = kPoolKeep;
+    e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    if (e != hipSuccess) return e;
+    if ((int)done.size() <= dev) done.resize(dev + 1, false);
+    done[dev] = true;
+    return hipSuccess;
+}
+
 
 hipError_t cache_trim()
 {

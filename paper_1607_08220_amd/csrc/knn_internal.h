@@ -190,6 +190,10 @@ struct QuerySpec {
 };
 
 int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t stream);
+// Raise the current device's default stream-ordered pool's release threshold
+// (once per device, at a call on `stream` outside a graph capture) so that
+// freed query and batch workspaces stay mapped.
+hipError_t keep_pool_memory(hipStream_t stream);
 // Device workspace query_tree takes for qs (the grouping of queries by home
 // leaf, when the traversal form it picks groups them); 0 otherwise.
 size_t query_workspace_bytes(const knn_tree* t, const QuerySpec& qs);
