@@ -576,9 +576,16 @@ def main() -> int:
 
     mean = {kk: float(np.mean([p[kk] for p in phases])) for kk in phases[0]}
     build_ms, query_ms, trav_ms = mean["build_total"], mean["query_total"], mean["query_traverse"]
-    part_launches = mean["build_partition_launches"]
-    part_avg_ms = mean["build_partition_ms"] / part_launches
-    part_bytes = partition_bytes_per_point(d) * mean["build_partition_mpts"] * 1e6 / part_launches
+    # the partition kernel's launches timed one by one in a build of its own
+    # after the timed steps (its events would idle the device inside them)
+    knn.knn_set_profiling(2)
+    tp = knn.knn_build(P, w.leaf)
+    pp = knn.knn_get_profile()
+    tp.free()
+    knn.knn_set_profiling(1)
+    part_launches = pp["build_partition_launches"]
+    part_avg_ms = pp["build_partition_ms"] / part_launches
+    part_bytes = partition_bytes_per_point(d) * pp["build_partition_mpts"] * 1e6 / part_launches
 
     # visit counts of this traversal on this tree (untimed, instrumented run)
     stats = torch.zeros(knn.KNN_QUERY_STATS, dtype=torch.int64, device=dev)

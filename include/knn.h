@@ -436,7 +436,10 @@ const char* knn_strerror(int code);
 
 /* Per-phase device times of the most recent build and query on this thread,
  * in milliseconds, taken with HIP events on the call's stream while profiling
- * is enabled (knn_set_profiling(1)).  Slots:
+ * is enabled: knn_set_profiling(1) records the phase boundaries; 2 also
+ * records an event before and after every launch of the build's partition
+ * kernel (slots 9-11), which leaves the device idle a few microseconds per
+ * event; 0 turns profiling off.  Slots:
  *   build: 0 ingest, 1 level passes (sample, histogram, split, partition),
  *          2 subtree finish in LDS, 3 node compaction and boxes, 4 total
  *   query: 5 locate home leaves, 6 group queries by leaf, 7 traversal, 8 total

@@ -651,8 +651,12 @@ def knn_last_error() -> str:
     return load_library().knn_last_error().decode()
 
 
-def knn_set_profiling(enable: bool):
-    _check(load_library().knn_set_profiling(1 if enable else 0))
+def knn_set_profiling(enable):
+    """False/0: off; True/1: phase events; 2: also an event around every
+    launch of the build's partition kernel (which idles the device a few
+    microseconds per event)."""
+    level = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+    _check(load_library().knn_set_profiling(level))
 
 
 def knn_get_profile() -> dict:

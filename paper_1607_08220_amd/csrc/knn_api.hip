@@ -173,7 +173,7 @@ void prof_part_begin()
 
 void prof_part_mark(hipStream_t s)
 {
-    if (!g_prof.on) return;
+    if (!g_prof.on || !g_prof.part) return;
     if (g_prof.part_used == (int)g_prof.part_ev.size()) {
         hipEvent_t e = nullptr;
         if (hipEventCreate(&e) != hipSuccess) return;
@@ -574,6 +574,7 @@ int knn_release_memory(void)
 int knn_set_profiling(int32_t enable)
 {
     g_prof.on = enable != 0;
+    g_prof.part = enable >= 2;
     for (int i = 0; i < KNN_PHASES + 4; ++i) g_prof.have[i] = false;
     return KNN_OK;
 }

@@ -2024,7 +2024,7 @@ inline unsigned blocks_for(int64_t items, int per) { return (unsigned)((items + 
 // others form level 0, with their block tables.
 struct Level0Host {
     std::vector<int32_t> f[8];  // per large root: start, count, id, parent, depth, blk0, nblk, hblk0
-    std::vector<int32_t> bnode, bbeg, hnode, hbeg;
+    int32_t nb0 = 0, nbh0 = 0;  // partition and histogram blocks of level 0
     std::vector<SubEntry> small;
     std::vector<int32_t> big_roots;
     int64_t largest = 0;
@@ -2039,22 +2039,14 @@ Level0Host level0_tables(const int64_t* offsets, int32_t T, int32_t W, int32_t l
             h.small.push_back(SubEntry{(int32_t)offsets[r], (int32_t)c, r, -1, 0, 0, 0, 0});
             continue;
         }
-        const int32_t i = (int32_t)h.big_roots.size();
         h.big_roots.push_back(r);
         h.largest = std::max(h.largest, c);
         const int32_t nb = (int32_t)((c + kChunk - 1) / kChunk);
         const int32_t nbh = (int32_t)((c + kHistChunk - 1) / kHistChunk);
-        const int32_t vals[8] = {(int32_t)offsets[r], (int32_t)c, r, -1, 0,
-                                 (int32_t)h.bnode.size(), nb, (int32_t)h.hnode.size()};
+        const int32_t vals[8] = {(int32_t)offsets[r], (int32_t)c, r, -1, 0, h.nb0, nb, h.nbh0};
         for (int k = 0; k < 8; ++k) h.f[k].push_back(vals[k]);
-        for (int32_t j = 0; j < nb; ++j) {
-            h.bnode.push_back(i);
-            h.bbeg.push_back(j * kChunk);
-        }
-        for (int32_t j = 0; j < nbh; ++j) {
-            h.hnode.push_back(i);
-            h.hbeg.push_back(j * kHistChunk);
-        }
+        h.nb0 += nb;
+        h.nbh0 += nbh;
     }
     return h;
 }
@@ -2168,16 +2160,26 @@ constexpr int kTailBlocks = 256;
 // Status words of a build.
 enum { PS_ERR = 0, PS_NSUB = 1, PS_NSUB_COMPACT = 2, PS_TOTAL = 3, PS_DEPTH = 4, PS_COUNT = 8 };
 
-// Level 0 as uploaded (once per build, or once per plan).
+// Level 0 as uploaded (once per build, or once per plan): its node list; its
+// block tables (nb0 partition blocks, nbh0 histogram blocks) are derived on
+// the device from each node's first block.
 struct PlanLevel0 {
     const int32_t* f;        // [8][nn0]: start, count, id, parent, depth, blk0, nblk, hblk0
-    const int32_t* bnode;    // [nb0]
-    const int32_t* bbeg;     // [nb0]
-    const int32_t* hnode;    // [nbh0]
-    const int32_t* hbeg;     // [nbh0]
     const SubEntry* small;   // [n_small]: roots that go straight to the subtree finish
     int32_t nn0, nb0, nbh0, n_small, T;
 };
+
+// The node whose first block (first[0 .. nn)) is the largest <= b.
+__device__ inline int owner_of_block(const int32_t* __restrict__ first, int nn, int b)
+{
+    int lo = 0, hi = nn - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // Start of a run: counters, status and the tree's query error count to zero.
 __global__ void k_run_init(int32_t* __restrict__ g, int32_t* __restrict__ status,
@@ -2203,13 +2205,17 @@ __global__ void k_run_level0(PlanLevel0 P, Level L0, SubEntry* __restrict__ subs
                              L0.hblk0};
     for (int64_t i = i0; i < 8 * (int64_t)P.nn0; i += stride)
         dst[i / P.nn0][i % P.nn0] = P.f[i];
+    const int32_t* blk0 = P.f + 5 * (int64_t)P.nn0;
+    const int32_t* hblk0 = P.f + 7 * (int64_t)P.nn0;
     for (int64_t i = i0; i < P.nb0; i += stride) {
-        L0.bnode[i] = P.bnode[i];
-        L0.bbeg[i] = P.bbeg[i];
+        const int o = owner_of_block(blk0, P.nn0, (int)i);
+        L0.bnode[i] = o;
+        L0.bbeg[i] = ((int)i - blk0[o]) * kChunk;
     }
     for (int64_t i = i0; i < P.nbh0; i += stride) {
-        L0.hnode[i] = P.hnode[i];
-        L0.hbeg[i] = P.hbeg[i];
+        const int o = owner_of_block(hblk0, P.nn0, (int)i);
+        L0.hnode[i] = o;
+        L0.hbeg[i] = ((int)i - hblk0[o]) * kHistChunk;
     }
     for (int64_t i = i0; i < P.n_small; i += stride) subs[i] = P.small[i];
     if (i0 == 0) {
@@ -2330,13 +2336,12 @@ __global__ void k_run_done(const int32_t* __restrict__ status, NodeRec* __restri
 }
 
 
-// The words of level 0's upload: the node fields, the block tables, then the
-// small roots' subtree entries; and the device view of them at `dev`.
+// The words of level 0's upload: the node fields, then the small roots'
+// subtree entries; and the device view of them at `dev`.
 std::vector<int32_t> level0_words(const Level0Host& h0)
 {
     std::vector<int32_t> w;
     for (int k = 0; k < 8; ++k) w.insert(w.end(), h0.f[k].begin(), h0.f[k].end());
-    for (auto* v : {&h0.bnode, &h0.bbeg, &h0.hnode, &h0.hbeg}) w.insert(w.end(), v->begin(), v->end());
     const size_t at = w.size();
     w.resize(at + h0.small.size() * (sizeof(SubEntry) / sizeof(int32_t)));
     if (!h0.small.empty()) std::memcpy(w.data() + at, h0.small.data(), sizeof(SubEntry) * h0.small.size());
@@ -2345,12 +2350,9 @@ std::vector<int32_t> level0_words(const Level0Host& h0)
 
 PlanLevel0 level0_view(const Level0Host& h0, const int32_t* dev, int32_t T)
 {
-    const size_t nn0 = h0.big_roots.size(), nb0 = h0.bnode.size(), nbh0 = h0.hbeg.size();
-    const int32_t* f = dev;
-    const int32_t* tab = f + 8 * nn0;
-    return PlanLevel0{f, tab, tab + nb0, tab + 2 * nb0, tab + 2 * nb0 + nbh0,
-                      reinterpret_cast<const SubEntry*>(tab + 2 * nb0 + 2 * nbh0),
-                      (int32_t)nn0, (int32_t)nb0, (int32_t)nbh0, (int32_t)h0.small.size(), T};
+    const size_t nn0 = h0.big_roots.size();
+    return PlanLevel0{dev, reinterpret_cast<const SubEntry*>(dev + 8 * nn0), (int32_t)nn0,
+                      h0.nb0, h0.nbh0, (int32_t)h0.small.size(), T};
 }
 
 unsigned level0_blocks(const PlanLevel0& l0)

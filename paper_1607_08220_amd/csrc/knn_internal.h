@@ -131,6 +131,7 @@ struct DevBuf {
 // Profiling: events recorded at phase boundaries on the call's stream.
 struct Profiler {
     bool on = false;
+    bool part = false;  // also time each launch of the build's partition kernel
     hipEvent_t ev[KNN_PHASES + 4] = {};
     bool have[KNN_PHASES + 4] = {};
     // events around each launch of the build's partition kernel
