@@ -299,6 +299,93 @@ __global__ __launch_bounds__(kBlock, 4) void k_sample(Level L, const float* __re
     if (lane == 0) out_dim[node] = best;
 }
 
+// B1-B3 for levels of few nodes: the same computation as k_sample with a
+// workgroup of kSampleMax threads per node (thread t holds sample element t),
+// so the few nodes of the top levels are not each left to one wavefront.
+// The FP64 sums run the same pairwise tree (element t += element t + w for
+// w = 512 .. 1) and the sort the same bitonic network, in LDS.
+__global__ __launch_bounds__(kSampleMax) void k_sample_block(Level L,
+                                                            const float* __restrict__ cols,
+                                                            int64_t n, int d,
+                                                            float* __restrict__ samples,
+                                                            int32_t* __restrict__ out_dim,
+                                                            uint32_t* __restrict__ hist)
+{
+    __shared__ double acc[kSampleMax];
+    __shared__ float sv[kSampleMax];
+    const int node = blockIdx.x, t = threadIdx.x;
+    if (node >= L.cnt[0]) return;
+    const int64_t start = L.start[node], c = L.count[node];
+    for (int i = t; i < kWinRow; i += kSampleMax) hist[(int64_t)node * kWinRow + i] = 0u;
+    const int s = (int)(c < kSampleMax ? c : kSampleMax);
+    const bool in = t < s;
+    const int64_t pos = start + sample_pos_fast(in ? t : s - 1, c, s);
+    float f[16];  // this element in every dimension, all loads in flight at once
+#pragma unroll
+    for (int dd = 0; dd < 16; ++dd) f[dd] = dd < d ? cols[(int64_t)dd * n + pos] : 0.0f;
+    // pairwise sum over the 1024 elements, to every thread: strides 512 .. 64
+    // through LDS, 32 .. 1 by shuffles inside the first wavefront
+    auto tree = [&](double v) {
+        acc[t] = v;
+        __syncthreads();
+        for (int w = kSampleMax / 2; w >= kWave; w >>= 1) {
+            if (t < w) acc[t] = acc[t] + acc[t + w];
+            __syncthreads();
+        }
+        if (t < kWave) {
+            double x = acc[t];
+            for (int w = kWave / 2; w >= 1; w >>= 1) x = x + __shfl_down(x, w);
+            if (t == 0) acc[0] = x;
+        }
+        __syncthreads();
+        const double r = acc[0];
+        __syncthreads();
+        return r;
+    };
+    double bestV = -1.0;
+    int best = 0;
+    float fb = 0.0f;
+#pragma unroll
+    for (int dd = 0; dd < 16; ++dd) {
+        if (dd < d) {
+            const double S = tree(in ? (double)f[dd] : 0.0);
+            const double wv = (double)s * (double)f[dd] - S;
+            const double V = tree(in ? wv * wv : 0.0);
+            if (V > bestV) {
+                bestV = V;
+                best = dd;
+                fb = f[dd];
+            }
+        }
+    }
+    if (!(bestV > 0.0)) {  // sample constant in every dimension
+        if (t == 0) out_dim[node] = -1;
+        return;
+    }
+    // bitonic network: partners 64 or more apart through LDS, nearer ones by
+    // shuffles inside the wavefront
+    float e = in ? fb : INFINITY;
+    for (int k = 2; k <= kSampleMax; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            float p;
+            if (j >= kWave) {
+                sv[t] = e;
+                __syncthreads();
+                p = sv[t ^ j];
+                __syncthreads();
+            } else {
+                p = __shfl_xor(e, j);
+            }
+            const bool asc = (t & k) == 0, lower = (t & j) == 0;
+            e = lower == asc ? fminf(e, p) : fmaxf(e, p);
+        }
+    }
+    int jl, jh;
+    sample_window(s, &jl, &jh);
+    if (t >= jl && t <= jh) samples[(int64_t)node * kWinStride + (t - jl)] = e;
+    if (t == 0) out_dim[node] = best;
+}
+
 // ---------------------------------------------------------------------------
 // B4: histogram over the sorted sample (blocks over node chunks)
 // ---------------------------------------------------------------------------
@@ -2101,7 +2188,10 @@ void enqueue_level(const LevelWork& w, const Level& cur, const Level& nxt, int l
     float* dst = w.cols[buf ^ 1];
     int32_t* dsti = w.idx[buf ^ 1];
     const unsigned g_nw = (g_nn + kWavesPerBlock - 1) / kWavesPerBlock;
-    k_sample<<<g_nw, kBlock, 0, st>>>(cur, src, n, w.d, w.samples, w.dimv, w.hist);
+    if (nn_l <= w.split_block_nodes)  // few nodes: a workgroup each
+        k_sample_block<<<g_nn, kSampleMax, 0, st>>>(cur, src, n, w.d, w.samples, w.dimv, w.hist);
+    else
+        k_sample<<<g_nw, kBlock, 0, st>>>(cur, src, n, w.d, w.samples, w.dimv, w.hist);
     k_hist<<<g_nbh, kBlock, 0, st>>>(cur, w.dimv, w.samples, src, n, w.hist);
     if (nn_l <= w.split_block_nodes)  // few large nodes: a block each
         k_choose<<<g_nn, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, src, n, w.d, w.splitv);
