@@ -67,18 +67,18 @@ __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ n
     }
 }
 
+// Counting-sort scatter: query i takes the next slot of its home leaf's
+// bucket; slot p gets (i, home leaf) in one 8-byte store.
 __global__ __launch_bounds__(kBlock) void k_group(const NodeRec* __restrict__ nodes,
                                                   const int32_t* __restrict__ home, int64_t m,
                                                   int shift, uint32_t* __restrict__ offs,
-                                                  int32_t* __restrict__ order,
-                                                  int32_t* __restrict__ shome)
+                                                  int2* __restrict__ slots)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= m) return;
     const int h = home[i];
     const uint32_t p = atomicAdd(&offs[nodes[h].a >> shift], 1u);
-    order[p] = (int32_t)i;
-    shome[p] = h;
+    slots[p] = make_int2((int)i, h);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero(uint32_t* __restrict__ a, int64_t len)
@@ -352,8 +352,9 @@ FormChoice choose_form(const knn_tree* t, const QuerySpec& qs)
     f.N = f.grouped ? (t->n >> f.shift) + 1 : 0;
     f.nsb = (f.N + kScanChunk - 1) / kScanChunk;
     const int64_t mg = f.grouped ? m : 0;
-    // workspace: cnt[N], block sums[nsb], home[m], order[m], shome[m]
-    f.bytes = sizeof(uint32_t) * (size_t)(f.N + f.nsb) + sizeof(int32_t) * 3 * (size_t)mg;
+    // workspace: slots[m] (int2), cnt[N], block sums[nsb], home[m]
+    f.bytes = sizeof(int2) * (size_t)mg + sizeof(uint32_t) * (size_t)(f.N + f.nsb) +
+              sizeof(int32_t) * (size_t)mg;
     return f;
 }
 
@@ -394,11 +395,10 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
         KNN_HIP(hipMallocAsync(&ws.p, bytes, st));
         base = ws.p;
     }
-    uint32_t* cnt = static_cast<uint32_t*>(base);
+    int2* slots = static_cast<int2*>(base);  // first: 8-byte aligned
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(slots + mg);
     uint32_t* bsum = cnt + N;
     int32_t* home = reinterpret_cast<int32_t*>(bsum + nsb);
-    int32_t* ord = home + mg;
-    int32_t* shome = ord + mg;
     if (grouped) {
         // cleared by a kernel, not a memset node, so the call can be captured in a graph
         k_zero<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N);
@@ -412,7 +412,7 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
         k_scan_local<<<(unsigned)nsb, kBlock, 0, st>>>(cnt, N, bsum);
         k_scan_sums<<<1, kBlock, 0, st>>>(bsum, nsb);
         k_scan_add<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N, bsum);
-        k_group<<<grid, kBlock, 0, st>>>(t->nodes, home, m, shift, cnt, ord, shome);
+        k_group<<<grid, kBlock, 0, st>>>(t->nodes, home, m, shift, cnt, slots);
         KNN_HIP(hipGetLastError());
     }
     prof_mark(st, 7);
@@ -421,8 +421,8 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     A.bbox = t->bbox;
     A.pts = t->pts;
     A.queries = qs.queries;
-    A.order = grouped ? ord : nullptr;
-    A.home = grouped ? shome : nullptr;
+    A.slots = grouped ? slots : nullptr;
+    A.start_home = grouped;
     A.root = qs.qroot;
     A.n_roots = t->n_trees;
     A.bad = t->bad;
@@ -444,7 +444,7 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     if (use_team) {  // grouped order (when asked) for locality; each team starts at its root
         TraverseFn ft = team_for(d, team);
         if (!ft) return fail(KNN_EINVAL, "unsupported dimension or team size");
-        A.home = nullptr;
+        A.start_home = false;
         const int64_t per_block = (int64_t)kWavesPerBlock * (kWave / team);
         hipLaunchKernelGGL(ft, dim3((unsigned)((m + per_block - 1) / per_block)), dim3(kBlock), 0,
                            st, A);

@@ -191,8 +191,8 @@ struct TravArgs {
     const float* bbox;
     const float* pts;
     const float* queries;   // [m][D]
-    const int32_t* order;   // slot -> query (NULL: identity)
-    const int32_t* home;    // slot -> home leaf (NULL: start at the query's root)
+    const int2* slots;      // grouped order: slot -> (query, its home leaf); NULL: input order
+    bool start_home;        // the lane-per-query walk starts at the home leaf (else the root)
     const int32_t* root;    // per-query root node (a forest's tree), else node 0
     int32_t n_roots;        // valid root ids: [0, n_roots)
     unsigned long long* bad;  // count of queries whose root id is out of range
@@ -246,8 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
     const float* __restrict__ bbox = A.bbox;
     const float* __restrict__ pts = A.pts;
     const float* __restrict__ queries = A.queries;
-    const int32_t* __restrict__ order = A.order;
-    const int32_t* __restrict__ home = A.home;
+    const int2* __restrict__ slots = A.slots;
     const int32_t* __restrict__ self_ids = A.self_ids;
     const int64_t m = A.m;
     const int batch = A.batch;
@@ -262,7 +261,8 @@ __global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
     unsigned long long n_enter = 0, n_leaf = 0, n_pts = 0, n_step = 0, n_ins = 0;
     unsigned long long w_step = 0, w_rows = 0, w_round = 0, w_ins = 0;
     if (slot < m) {  // every lane meets the counter sums below
-    const int64_t qid = order ? order[slot] : slot;
+    const int2 sl = slots ? slots[slot] : make_int2(0, 0);
+    const int64_t qid = slots ? (int64_t)sl.x : slot;
     float q[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) q[t] = queries[qid * D + t];
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(TravArgs A)
 #pragma unroll
     for (int j = 0; j < KC; ++j) h[j] = j < pad ? 0 : empty;
     const int root = query_root(A, qid);
-    int cur = root < 0 ? -1 : (home ? home[slot] : root);
+    int cur = root < 0 ? -1 : (slots && A.start_home ? sl.y : root);
     int from = -1;  // -1: arrived from the parent; otherwise the child we came from
     // The record and box of `cur` are loaded at the end of the step that moves
     // there, together, so one memory latency is exposed per step.
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse_stack(TravArgs A, int sdept
     unsigned long long n_enter = 0, n_leaf = 0, n_pts = 0, n_step = 0, n_ins = 0;
     unsigned long long w_step = 0, w_rows = 0, w_round = 0, w_ins = 0;
     if (slot < m) {  // every lane meets the counter sums below
-    const int64_t qid = A.order ? A.order[slot] : slot;
+    const int64_t qid = A.slots ? (int64_t)A.slots[slot].x : slot;
     float q[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) q[t] = A.queries[qid * D + t];
@@ -741,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse_wave(TravArgs A)
     const int64_t slot =
         (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (slot >= A.m) return;  // the whole wavefront
-    const int64_t qid = A.order ? A.order[slot] : slot;
+    const int64_t qid = A.slots ? (int64_t)A.slots[slot].x : slot;
     float q[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) q[t] = A.queries[qid * D + t];
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse_team(TravArgs A)
     const int tb = lane & ~(T - 1);
     const int64_t slot = ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * kQpw + lane / T;
     if (slot >= A.m) return;  // the whole team
-    const int64_t qid = A.order ? A.order[slot] : slot;
+    const int64_t qid = A.slots ? (int64_t)A.slots[slot].x : slot;
     float q[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) q[t] = A.queries[qid * D + t];
