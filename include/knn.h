@@ -73,9 +73,10 @@ typedef struct {
                        5 traversal-loop iterations, 6 bucket-row batches, 7 leaf
                        rounds, 8 heap-insert executions */
     int32_t traversal; /* 0 (default): below 5 dimensions form 3 for batches of at most
-                          16,384 queries, else 1; from 5 dimensions form 3 up to 4,096
-                          queries, form 4 with 32 lanes up to 32,768 (where k and the
-                          depth fit), else 2; 1: stack-free walk from the
+                          16,384 queries, else 1 (2 in 4 dimensions from k = 16 with buckets
+                          of 16 or more points); from 5
+                          dimensions form 3 up to 4,096 queries, form 4 with 32 lanes up
+                          to 32,768 (where k and the depth fit), else 2; 1: stack-free walk from the
                           query's home leaf (each node keeps its parent); 2: Algorithm 1's
                           explicit stack, kept in LDS (used when the tree's depth fits);
                           3: Algorithm 1's explicit stack with one wavefront per query

@@ -17,6 +17,16 @@ using WaveFn = void (*)(TravArgs);
 // that kLocQ independent node loads are in flight per step.
 constexpr int kLocQ = 4;
 
+// In 4 dimensions the default takes the explicit stack from k = 16 on, for
+// buckets of 16 or more points: on 2^28 plasma-like points with 2^24 of them
+// as queries it answers k = 16 in 58.2 / 57.4 / 62.8 ms (buckets of 16 / 32 /
+// 64) against 63.8 / 61.5 / 66.1 for the stack-free walk, while the walk stays
+// ahead for buckets of 8 (a deeper tree, a longer stack: 72.0 against 89.3
+// ms), at k = 8 (36.6 against 40.2 ms) and in 3 dimensions (clustered, 2^26
+// points, 2^22 queries: 4.2 against 5.5 ms at k = 8, 6.3 against 7.7 at 16).
+constexpr int kStackMinK4 = 16;
+constexpr int kStackMinLeaf4 = 16;
+
 // A query whose tree id is out of range descends tree 0 here (only its
 // place in the grouped order depends on it); the traversal answers it with
 // padding rows.
@@ -440,7 +450,9 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     // the explicit stack needs (depth + 1) entries of 8 bytes per lane in LDS
     const size_t stk_bytes = sizeof(int2) * (size_t)(t->depth + 1) * kBlock;
     const bool use_stack = stk_bytes <= kMaxStackLds &&
-                           (trav == 2 || (trav == 0 && d >= kStackMinDim));
+                           (trav == 2 || (trav == 0 && (d >= kStackMinDim ||
+                                                        (d == 4 && qs.k >= kStackMinK4 &&
+                                                         t->leaf >= kStackMinLeaf4))));
     if (use_team) {  // grouped order (when asked) for locality; each team starts at its root
         TraverseFn ft = team_for(d, team);
         if (!ft) return fail(KNN_EINVAL, "unsupported dimension or team size");
