@@ -421,11 +421,11 @@ int knn_tree_export(const knn_tree* t, knn_tree_host* h);
  * blocks kept by the library (per device), which gives memory a build or a
  * freed tree handed back to later builds instead of mapping fresh memory;
  * at most 96 GiB of unused blocks are kept.  Query workspaces and serving
- * batches come from the device's default stream-ordered pool, whose release
- * threshold the library raises to 8 GiB on first use (so freed workspace stays
- * mapped for the next call instead of being returned at every
- * synchronisation).  This call waits for the current device, frees every
- * unused block and trims that pool. */
+ * batches come from a stream-ordered pool the library creates per device,
+ * which keeps up to 8 GiB of freed memory mapped for the next call instead of
+ * returning it at every synchronisation (the device's default pool is left as
+ * it is, and serves a first call made under graph capture).  This call waits
+ * for the current device, frees every unused block and trims both pools. */
 int knn_release_memory(void);
 
 /* Message describing the last failure of the calling thread. */

@@ -123,34 +123,54 @@ void cache_free(void* p)
     if (g_cache_free_bytes > kCacheKeepMax) (void)cache_shrink(-1, kCacheKeepMax);
 }
 
-// Bytes of freed memory the default pool keeps mapped between calls.
+// Bytes of freed memory the library's pool keeps mapped between calls.
 constexpr uint64_t kPoolKeep = 8ull << 30;
 
-hipError_t keep_pool_memory(hipStream_t st)
+// The library's stream-ordered pool of the current device: with `create`,
+// made at the first call whose stream is not being captured; *out = NULL
+// while none exists.
+hipError_t work_pool(hipStream_t st, bool create, hipMemPool_t* out)
 {
     static std::mutex mu;
-    static std::vector<bool> done;
-    // not while `st` is being captured (the pool is left as it is until a
-    // call outside a capture)
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(st, &cs);
-    if (e != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
+    static std::vector<hipMemPool_t> pools;
+    *out = nullptr;
     int dev = 0;
-    e = hipGetDevice(&dev);
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lk(mu);
-    if ((int)done.size() > dev && done[dev]) return hipSuccess;
-    hipMemPool_t pool;
-    e = hipDeviceGetDefaultMemPool(&pool, dev);
+    if ((int)pools.size() > dev && pools[dev]) {
+        *out = pools[dev];
+        return hipSuccess;
+    }
+    if (!create) return hipSuccess;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    e = hipMemPoolCreate(&pool, &props);
     if (e != hipSuccess) return e;
     uint64_t keep = kPoolKeep;
     e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
     if (e != hipSuccess) return e;
-    if ((int)done.size() <= dev) done.resize(dev + 1, false);
-    done[dev] = true;
+    if ((int)pools.size() <= dev) pools.resize(dev + 1, nullptr);
+    pools[dev] = pool;
+    *out = pool;
     return hipSuccess;
 }
 
+hipError_t work_alloc(void** p, size_t bytes, hipStream_t st)
+{
+    hipMemPool_t pool = nullptr;
+    hipError_t e = work_pool(st, true, &pool);
+    if (e != hipSuccess) return e;
+    // no pool yet during a first use under capture: the device's default pool
+    return pool ? hipMallocFromPoolAsync(p, bytes, pool, st) : hipMallocAsync(p, bytes, st);
+}
 
 hipError_t cache_trim()
 {
@@ -568,6 +588,8 @@ int knn_release_memory(void)
     hipMemPool_t pool;
     KNN_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
     KNN_HIP(hipMemPoolTrimTo(pool, 0));
+    KNN_HIP(work_pool(nullptr, false, &pool));
+    if (pool) KNN_HIP(hipMemPoolTrimTo(pool, 0));
     return KNN_OK;
 }
 

@@ -191,10 +191,13 @@ struct QuerySpec {
 };
 
 int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t stream);
-// Raise the current device's default stream-ordered pool's release threshold
-// (once per device, at a call on `stream` outside a graph capture) so that
-// freed query and batch workspaces stay mapped.
-hipError_t keep_pool_memory(hipStream_t stream);
+// Stream-ordered allocation of query and batch workspaces from the library's
+// own pool on the current device, which keeps up to 8 GiB of freed memory
+// mapped between calls (created at the first call outside a graph capture;
+// the device's default pool serves a first call under capture).  Freed with
+// hipFreeAsync.
+hipError_t work_alloc(void** p, size_t bytes, hipStream_t stream);
+hipError_t work_pool(hipStream_t stream, bool create, hipMemPool_t* out);
 // Device workspace query_tree takes for qs (the grouping of queries by home
 // leaf, when the traversal form it picks groups them); 0 otherwise.
 size_t query_workspace_bytes(const knn_tree* t, const QuerySpec& qs);

@@ -401,8 +401,7 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
                                         " (order 1 needs none)");
         base = qs.ws;
     } else if (bytes) {
-        KNN_HIP(keep_pool_memory(st));
-        KNN_HIP(hipMallocAsync(&ws.p, bytes, st));
+        KNN_HIP(work_alloc(&ws.p, bytes, st));
         base = ws.p;
     }
     int2* slots = static_cast<int2*>(base);  // first: 8-byte aligned

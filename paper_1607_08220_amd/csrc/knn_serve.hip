@@ -472,8 +472,7 @@ int launch_batch(knn_server* s, Batch& b)
     // oi [outs], od [outs] (8-byte array first)
     const size_t b_qout = sizeof(int64_t) * total, b_q = sizeof(float) * total * d;
     const size_t b_i = sizeof(int32_t) * total, b_o = sizeof(int32_t) * outs;
-    KNN_HIP(knn::keep_pool_memory(b.stream));
-    KNN_HIP(hipMallocAsync(&b.mem, b_qout + b_q + 2 * b_i + 2 * b_o, b.stream));
+    KNN_HIP(knn::work_alloc(&b.mem, b_qout + b_q + 2 * b_i + 2 * b_o, b.stream));
     char* base = static_cast<char*>(b.mem);
     int64_t* qout = reinterpret_cast<int64_t*>(base);
     float* q = reinterpret_cast<float*>(base + b_qout);
