@@ -14,8 +14,10 @@ using WaveFn = void (*)(TravArgs);
 // leaf) >> shift: buckets are contiguous in packed order, so key order is the
 // tree's spatial order.  Each lane descends kLocQ queries at once (blocks of
 // kBlock * kLocQ consecutive queries, lane t taking t, t + kBlock, ...), so
-// that kLocQ independent node loads are in flight per step.
-constexpr int kLocQ = 4;
+// that kLocQ independent node loads are in flight per step (two per lane:
+// 0.454 ms for 2^22 queries on the clustered 2^26-point tree, against 0.61
+// with one, 0.466 with four and 0.52 with eight).
+constexpr int kLocQ = 2;
 
 // In 4 dimensions the default takes the explicit stack from k = 16 on, for
 // buckets of 16 or more points: on 2^28 plasma-like points with 2^24 of them
