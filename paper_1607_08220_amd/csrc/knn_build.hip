@@ -9,13 +9,14 @@
 //                  FP64 variance per dim, split dim = argmax, the sample of
 //                  that dim sorted in registers; keeps the ranks around the
 //                  middle that the histogram resolves
-//       k_hist     counts below / above that window of ranks and the bins
-//                  inside it (per-wavefront LDS queue, LDS binary search)
+//       k_hist     counts below that window of ranks and the bins inside it
+//                  (per-wavefront LDS queue, LDS binary search), per node and
+//                  as a prefix row per partition block
 //       k_choose   C_j over the window, j* = argmin |2 C_j - cnt| once the
 //                  window is shown to hold it, else the node's full histogram
-//                  (k_choose_wave: the same with one wavefront per node)
-//       k_count    per-wavefront count of points going left (ballot)
-//       k_blkscan  per-node exclusive scan of block counts
+//                  (k_choose_wave: the same with one wavefront per node); then
+//                  each partition block's left count (a read of its prefix
+//                  row) and their exclusive scan over the node
 //       k_scatter  stable partition of coordinates + index into the other
 //                  ping-pong buffer (ballot + mbcnt ranks, LDS staging)
 //       k_plan_*   children ids, next level's node list and block tables,
@@ -47,12 +48,11 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;       // 4
 constexpr int kItems = 16;                           // elements per lane per block pass
-constexpr int kWaveChunk = kWave * kItems;           // 1024 elements per wavefront
 constexpr int kChunk = kBlock * kItems;              // 4096 elements per block
 constexpr int kBins = kSampleMax + 1;                // histogram bins per node (full)
 // The level histogram only resolves the sample ranks jl..jh around the middle
 // (jl = s/2 - kWinHalf, jh = s/2 + kWinHalf, clamped): a node's row holds
-// [#{x < s_jl}, the bins jl+1..jh, #{x >= s_jh}].
+// [#{x < s_jl}, the bins jl+1..jh] (entries 0 .. jh - jl).
 constexpr int kWinHalf = 128;
 constexpr int kWinRow = 2 * kWinHalf + 2;
 constexpr int kWinStride = 2 * kWinHalf + 8;  // sorted sample values s_jl..s_jh per node
@@ -60,6 +60,13 @@ constexpr int kWinStride = 2 * kWinHalf + 8;  // sorted sample values s_jl..s_jh
 // its LDS histogram into the node's global one, so fewer blocks mean fewer
 // global atomics on the same counters.
 constexpr int kHistChunk = 8 * kChunk;
+constexpr int kSubs = kHistChunk / kChunk;  // partition blocks per histogram block
+// The histogram pass also leaves, for every partition block of kChunk points,
+// the inclusive prefix of the block's own window row: entry m is the number
+// of the block's points below s_(jl + m), so once the split s_j is chosen the
+// block's left count is one read at m = j - jl (counts <= kChunk fit 16 bits).
+constexpr int kCrowStride = kWinRow;
+static_assert(kChunk <= 65535, "per-block prefix counts are stored in 16 bits");
 constexpr int kStack = 32;                           // subtree DFS stack (entries)
 
 // A subtree handed to the finish kernel: points [start, start + count) of
@@ -389,20 +396,24 @@ __global__ __launch_bounds__(kSampleMax) void k_sample_block(Level L,
 // ---------------------------------------------------------------------------
 // B4: histogram over the sorted sample (blocks over node chunks)
 // ---------------------------------------------------------------------------
-// Counts, over the node's points x, #{x < s_jl}, #{x >= s_jh} and the bins
+// Counts, over the node's points x, #{x < s_jl} and the bins
 // b = #{j : s_j <= x} for the points in between (jl < b <= jh), which give
-// C_j = #{x < s_j} exactly for every j in [jl, jh].  Points outside the
-// window are counted with wavefront ballots; the points inside are first
-// queued per wavefront in LDS so that every lane of a binary search over the
-// window's sample values has a point to place.
+// C_j = #{x < s_j} exactly for every j in [jl, jh].  Points below the window
+// are counted with wavefront ballots; the points inside are first queued per
+// wavefront in LDS so that every lane of a binary search over the window's
+// sample values has a point to place.  The counts are kept per partition
+// block of kChunk points (the queue carries each point's block) and leave as
+// the node's row and as each block's prefix row (see kCrowStride).
 __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restrict__ dimv,
                                                  const float* __restrict__ samples,
                                                  const float* __restrict__ cols, int64_t n,
-                                                 uint32_t* __restrict__ hist)
+                                                 uint32_t* __restrict__ hist,
+                                                 uint16_t* __restrict__ crow)
 {
     __shared__ float sv[2 * kWinHalf + 1];
-    __shared__ uint32_t h[kWinRow];
+    __shared__ uint32_t h[kSubs][kWinRow];
     __shared__ float queue[kWavesPerBlock][2 * kWave];
+    __shared__ uint8_t qsub[kWavesPerBlock][2 * kWave];
     const int b = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
     if (b >= L.cnt[2]) return;
     const int node = L.hnode[b];
@@ -420,6 +431,9 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
     const int len = (int)(end - beg);
     constexpr int kIlp = 8;
     constexpr int kStep = kBlock * kIlp;
+    // iteration it covers elements kStep * it .. kStep * it + kStep - 1 of the
+    // chunk, all in partition block it / 2 of it
+    static_assert(2 * kStep == kChunk, "two histogram iterations per partition block");
     const int wbeg = w * kWave * kIlp;
     float xn[kIlp];  // the next iteration's values, loaded while this one is binned
     if (wbeg < len) {  // the first ones before the window values arrive
@@ -433,26 +447,33 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
     // in-window point is below sv[nwin]), so the search needs no bound test
     for (int i = t; i <= 2 * kWinHalf; i += kBlock)
         sv[i] = i <= nwin ? samples[(int64_t)node * kWinStride + i] : INFINITY;
-    for (int i = t; i < kWinRow; i += kBlock) h[i] = 0u;
+    const int nsub = (len + kChunk - 1) / kChunk;  // partition blocks in the chunk
+    for (int i = t; i < nsub * kWinRow; i += kBlock) (&h[0][0])[i] = 0u;
     __syncthreads();
     const float lo_v = sv[0], hi_v = sv[nwin];
-    uint32_t below = 0, above = 0;  // wavefront-uniform counts (ballots)
     int qn = 0;  // queued points of this wavefront (uniform)
     float* qw = queue[w];
+    uint8_t* qs = qsub[w];
     // place the first 64 queued points: bin = jl + 1 + #{1 <= i < nwin : sv[i] <= x}
     auto drain = [&]() {
         __builtin_amdgcn_wave_barrier();
         const float x = qw[lane];
+        const int sb = qs[lane];
         int pos = 0;
 #pragma unroll
         for (int step = kWinHalf; step > 0; step >>= 1) pos = sv[pos + step] <= x ? pos + step : pos;
-        atomicAdd(&h[1 + pos], 1u);
+        atomicAdd(&h[sb][1 + pos], 1u);
         const float tail = qw[kWave + lane];
-        if (lane < qn - kWave) qw[lane] = tail;
+        const uint8_t tsb = qs[kWave + lane];
+        if (lane < qn - kWave) {
+            qw[lane] = tail;
+            qs[lane] = tsb;
+        }
         __builtin_amdgcn_wave_barrier();
         qn -= kWave;
     };
-    for (int e0 = wbeg; e0 < len; e0 += kStep) {
+    for (int e0 = wbeg, it = 0; e0 < len; e0 += kStep, ++it) {
+        const int sub = it >> 1;
         float x[kIlp];
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) x[u] = xn[u];
@@ -464,42 +485,73 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
             }
         }
         const int rem = len - e0;  // points left from this iteration's first
+        uint32_t below = 0;  // wavefront-uniform (ballots)
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) {
             const bool ok = u * kWave + lane < rem;
             below += (uint32_t)__popcll(__ballot(ok && x[u] < lo_v));
-            above += (uint32_t)__popcll(__ballot(ok && x[u] >= hi_v));
             const bool in = ok && x[u] >= lo_v && x[u] < hi_v;
             const unsigned long long m = __ballot(in);
             const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
-            if (in) qw[qn + off] = x[u];
+            if (in) {
+                qw[qn + off] = x[u];
+                qs[qn + off] = (uint8_t)sub;
+            }
             qn += __popcll(m);
             if (qn >= kWave) drain();
         }
+        if (lane == 0 && below) atomicAdd(&h[sub][0], below);
     }
     if (qn > 0) {  // the last partial queue: lanes past qn place nothing
         __builtin_amdgcn_wave_barrier();
         const float x = qw[lane];
+        const int sb = qs[lane];
         if (lane < qn) {
             int pos = 0;
 #pragma unroll
             for (int step = kWinHalf; step > 0; step >>= 1)
                 pos = sv[pos + step] <= x ? pos + step : pos;
-            atomicAdd(&h[1 + pos], 1u);
+            atomicAdd(&h[sb][1 + pos], 1u);
         }
-    }
-    if (lane == 0) {
-        atomicAdd(&h[0], below);
-        atomicAdd(&h[nwin + 1], above);
     }
     __syncthreads();
     uint32_t* row = hist + (int64_t)node * kWinRow;
-    if (c <= kHistChunk) {  // the node's only block: its row, stored whole
-        for (int i = t; i <= nwin + 1; i += kBlock) row[i] = h[i];
-    } else {
-        for (int i = t; i <= nwin + 1; i += kBlock)
-            if (h[i]) atomicAdd(&row[i], h[i]);
+    for (int i = t; i <= nwin; i += kBlock) {
+        uint32_t v = 0;
+        for (int sb = 0; sb < nsub; ++sb) v += h[sb][i];
+        if (c <= kHistChunk) row[i] = v;  // the node's only block: its row, stored whole
+        else if (v) atomicAdd(&row[i], v);
+    }
+    __syncthreads();
+    // each partition block's row becomes its inclusive prefix (a wavefront per
+    // block; lane l holds the entries 5 l .. 5 l + 4)
+    for (int sb = w; sb < nsub; sb += kWavesPerBlock) {
+        uint32_t v[5], sum = 0;
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const int e = 5 * lane + r;
+            v[r] = e <= nwin ? h[sb][e] : 0u;
+            sum += v[r];
+        }
+        uint32_t x = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        uint32_t run = x - sum;
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const int e = 5 * lane + r;
+            run += v[r];
+            if (e <= nwin) h[sb][e] = run;
+        }
+    }
+    __syncthreads();
+    const int64_t gb0 = L.blk0[node] + beg / kChunk;  // the chunk's first partition block
+    for (int sb = 0; sb < nsub; ++sb) {
+        uint16_t* dst = crow + (gb0 + sb) * kCrowStride;
+        for (int i = t; i <= nwin; i += kBlock) dst[i] = (uint16_t)h[sb][i];
     }
 }
 
@@ -564,16 +616,153 @@ __device__ long long block_split_key(const uint32_t (&v)[R], int j0, int jend, i
     return key;
 }
 
+// Children of a split node that need another level pass: more than W
+// points and more than the bucket size.
+__host__ __device__ inline bool needs_level_pass(int c, int W, int leaf) { return c > W && c > leaf; }
+
+// How a node's partition blocks find their left counts once the split is
+// chosen: the block's prefix row at m = j - jl (split s_j inside the
+// histogram window), a count of the split column below the split value, or
+// all of the block (a node that stays a bucket).
+enum { kLeftPrefix = 0, kLeftCount = 1, kLeftAll = 2 };
+
+// The node's left count and plan counters: split (0/1), children needing a
+// level pass, subtree entries, and the children's blocks of kChunk and
+// kHistChunk points.
+__device__ void node_plan(int node, int cnt, int nl, bool split, int W, int leaf,
+                          int32_t* __restrict__ n_left, int32_t* __restrict__ planv)
+{
+    n_left[node] = nl;
+    int v[kPlanVals] = {0, 0, 0, 0, 0};
+    if (split) {
+        const int cc[2] = {nl, cnt - nl};
+        v[0] = 1;
+        for (int k = 0; k < 2; ++k) {
+            if (needs_level_pass(cc[k], W, leaf)) {
+                v[1] += 1;
+                v[3] += (cc[k] + kChunk - 1) / kChunk;
+                v[4] += (cc[k] + kHistChunk - 1) / kHistChunk;
+            } else {
+                v[2] += 1;
+            }
+        }
+    } else {
+        v[2] = 1;
+    }
+    for (int k = 0; k < kPlanVals; ++k) planv[(int64_t)node * kPlanStride + k] = v[k];
+}
+
+// Wavefront w of the block (or the calling wavefront, step 1) counts, for the
+// node's partition blocks i = first, first + step, ..., the points of column
+// ccol below split, into blk_off[b0 + i].
+__device__ void count_block_lefts(const float* __restrict__ ccol, int64_t c, float split, int b0,
+                                  int nb, int first, int step, uint32_t* __restrict__ blk_off)
+{
+    const int lane = threadIdx.x & 63;
+    for (int i = first; i < nb; i += step) {
+        const int64_t e0 = (int64_t)i * kChunk;
+        const int64_t e1 = e0 + kChunk < c ? e0 + kChunk : c;
+        uint32_t cnt = 0;
+        for (int64_t ew = e0; ew < e1; ew += kWave) {
+            const int64_t e = ew + lane;
+            cnt += (uint32_t)__popcll(__ballot(e < e1 && ccol[e] < split));
+        }
+        if (lane == 0) blk_off[b0 + i] = cnt;
+    }
+}
+
+// Left count of partition block i of a node (see kLeftPrefix).
+struct BlockLefts {
+    const uint16_t* crow;
+    const uint32_t* counted;
+    int64_t c;
+    int b0, m, mode;
+    __device__ uint32_t operator()(int i) const
+    {
+        if (mode == kLeftPrefix) return crow[(int64_t)(b0 + i) * kCrowStride + m];
+        if (mode == kLeftCount) return counted[b0 + i];
+        const int64_t e0 = (int64_t)i * kChunk;
+        return (uint32_t)(c - e0 < kChunk ? c - e0 : kChunk);
+    }
+};
+
+// Exclusive scan of the node's block left counts into blk_off[b0 ..
+// b0 + nb), by the whole block (16 consecutive blocks per thread and pass);
+// returns the node's left count to every thread.  A thread reads only the
+// entries it writes, so the counts may come from blk_off itself.
+__device__ uint32_t block_lefts_scan(const BlockLefts& lefts, int nb,
+                                     uint32_t* __restrict__ blk_off, uint32_t* wsum)
+{
+    constexpr int R = 16;
+    const int t = threadIdx.x;
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kBlock * R) {
+        uint32_t v[R], sum = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = base + R * t + r;
+            v[r] = i < nb ? lefts(i) : 0u;
+            sum += v[r];
+        }
+        uint32_t tot;
+        uint32_t ex = carry + block_excl_scan(sum, &tot, wsum);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = base + R * t + r;
+            if (i < nb) blk_off[lefts.b0 + i] = ex;
+            ex += v[r];
+        }
+        carry += tot;
+    }
+    return carry;
+}
+
+// The same by one wavefront.
+__device__ uint32_t wave_lefts_scan(const BlockLefts& lefts, int nb, uint32_t* __restrict__ blk_off)
+{
+    constexpr int R = 16;
+    const int lane = threadIdx.x & 63;
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kWave * R) {
+        uint32_t v[R], sum = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = base + R * lane + r;
+            v[r] = i < nb ? lefts(i) : 0u;
+            sum += v[r];
+        }
+        uint32_t x = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        const uint32_t tot = (uint32_t)__shfl((int)x, 63);
+        uint32_t ex = carry + x - sum;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = base + R * lane + r;
+            if (i < nb) blk_off[lefts.b0 + i] = ex;
+            ex += v[r];
+        }
+        carry += tot;
+    }
+    return carry;
+}
+
 // One block per node.  From the window counts, C_j is exact for j in
 // [jl, jh]; since C_j does not decrease with j, the rank closest to half lies
 // in the window whenever 2 C_jl <= c <= 2 C_jh (a rank outside the window with
 // the same gap has the same C_j, hence the same sample value, as jl or jh).
-// Otherwise the block counts the full histogram of the node itself.
-__global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict__ dimv,
-                                                   const float* __restrict__ samples,
-                                                   const uint32_t* __restrict__ hist,
-                                                   const float* __restrict__ cols, int64_t n,
-                                                   int d, float* __restrict__ splitv)
+// Otherwise the block counts the full histogram of the node itself.  With
+// the split known, the block also gives every partition block of the node its
+// number of left points before it (blk_off), the node its left count and its
+// plan counters.
+__global__ __launch_bounds__(kBlock) void k_choose(
+    Level L, int32_t* __restrict__ dimv, const float* __restrict__ samples,
+    const uint32_t* __restrict__ hist, const uint16_t* __restrict__ crow,
+    const float* __restrict__ cols, int64_t n, int d, int W, int leaf,
+    float* __restrict__ splitv, uint32_t* __restrict__ blk_off, int32_t* __restrict__ n_left,
+    int32_t* __restrict__ planv)
 {
     __shared__ uint32_t wsum[kWavesPerBlock];
     __shared__ long long gbest[kBlock];
@@ -585,6 +774,8 @@ __global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict_
     const int64_t start = L.start[node], c = L.count[node];
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
     const int dim = dimv[node];
+    int mode, m = 0, cdim = dim;
+    float split;
     if (dim >= 0) {
         int jl, jh;
         sample_window(s, &jl, &jh);
@@ -642,59 +833,72 @@ __global__ __launch_bounds__(kBlock) void k_choose(Level L, int32_t* __restrict_
             for (int r = 0; r < 4; ++r) vf[r] = 4 * t + r < s ? hfull[4 * t + r] : 0u;
             key = block_split_key<4>(vf, 0, s, c, wsum, gbest);
         }
-        if (t == 0) {
-            // V > 0 guarantees a valid j; the guard only keeps the index in range
-            const int j = key == LLONG_MAX ? (in_window ? jl : 0) : (int)(key % 2048);
-            splitv[node] = in_window ? samples[(int64_t)node * kWinStride + (j - jl)] : sv[j];
-        }
-        return;
-    }
-    // The sample is constant in every dimension: split the dimension of
-    // largest extent at its maximum, or keep a leaf if all points coincide.
-    double bext = 0.0;
-    int bd = -1;
-    float bhi = 0.0f;
-    for (int dd = 0; dd < d; ++dd) {
-        const float* col = cols + (int64_t)dd * n + start;
-        float lo = INFINITY, hi = -INFINITY;
-        for (int64_t e = t; e < c; e += kBlock) {
-            float x = col[e];
-            lo = fminf(lo, x);
-            hi = fmaxf(hi, x);
-        }
-        fl[t] = lo;
-        fh[t] = hi;
-        __syncthreads();
-        for (int w = kBlock / 2; w >= 1; w >>= 1) {
-            if (t < w) {
-                fl[t] = fminf(fl[t], fl[t + w]);
-                fh[t] = fmaxf(fh[t], fh[t + w]);
+        // V > 0 guarantees a valid j; the guard only keeps the index in range
+        const int j = key == LLONG_MAX ? (in_window ? jl : 0) : (int)(key % 2048);
+        split = in_window ? samples[(int64_t)node * kWinStride + (j - jl)] : sv[j];
+        mode = in_window ? kLeftPrefix : kLeftCount;
+        m = j - jl;
+    } else {
+        // The sample is constant in every dimension: split the dimension of
+        // largest extent at its maximum, or keep a leaf if all points coincide.
+        double bext = 0.0;
+        int bd = -1;
+        float bhi = 0.0f;
+        for (int dd = 0; dd < d; ++dd) {
+            const float* col = cols + (int64_t)dd * n + start;
+            float lo = INFINITY, hi = -INFINITY;
+            for (int64_t e = t; e < c; e += kBlock) {
+                float x = col[e];
+                lo = fminf(lo, x);
+                hi = fmaxf(hi, x);
+            }
+            fl[t] = lo;
+            fh[t] = hi;
+            __syncthreads();
+            for (int w = kBlock / 2; w >= 1; w >>= 1) {
+                if (t < w) {
+                    fl[t] = fminf(fl[t], fl[t + w]);
+                    fh[t] = fmaxf(fh[t], fh[t + w]);
+                }
+                __syncthreads();
+            }
+            const double ext = (double)fh[0] - (double)fl[0];
+            if (ext > bext) {
+                bext = ext;
+                bd = dd;
+                bhi = fh[0];
             }
             __syncthreads();
         }
-        const double ext = (double)fh[0] - (double)fl[0];
-        if (ext > bext) {
-            bext = ext;
-            bd = dd;
-            bhi = fh[0];
-        }
+        if (t == 0) dimv[node] = bd;  // -1 keeps a leaf
+        cdim = bd;
+        split = bhi;
+        mode = bd >= 0 ? kLeftCount : kLeftAll;
+    }
+    if (t == 0) splitv[node] = split;
+    const int b0 = L.blk0[node], nb = L.nblk[node];
+    if (mode == kLeftCount) {  // every wavefront counts some blocks; the scan reads them all
+        count_block_lefts(cols + (int64_t)cdim * n + start, c, split, b0, nb, t >> 6,
+                          kWavesPerBlock, blk_off);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    if (t == 0) {
-        dimv[node] = bd;  // -1 keeps a leaf
-        splitv[node] = bhi;
-    }
+    const BlockLefts lefts{crow, blk_off, c, b0, m, mode};
+    const uint32_t nl = block_lefts_scan(lefts, nb, blk_off, wsum);
+    if (t == 0) node_plan(node, (int)c, (int)nl, mode != kLeftAll, W, leaf, n_left, planv);
 }
 
 // k_choose with one wavefront per node (kWavesPerBlock nodes per block), for
-// levels of many small nodes; same result.  Lane L holds the window entries
+// levels of many small nodes; same results.  Lane L holds the window entries
 // 5 L .. 5 L + 4.  The full-histogram path sorts the sample in registers and
 // counts in a per-wavefront LDS histogram.
-__global__ __launch_bounds__(kBlock) void k_choose_wave(Level L, int32_t* __restrict__ dimv,
-                                                        const float* __restrict__ samples,
-                                                        const uint32_t* __restrict__ hist,
-                                                        const float* __restrict__ cols, int64_t n,
-                                                        int d, float* __restrict__ splitv)
+__global__ __launch_bounds__(kBlock) void k_choose_wave(
+    Level L, int32_t* __restrict__ dimv, const float* __restrict__ samples,
+    const uint32_t* __restrict__ hist, const uint16_t* __restrict__ crow,
+    const float* __restrict__ cols, int64_t n, int d, int W, int leaf,
+    float* __restrict__ splitv, uint32_t* __restrict__ blk_off, int32_t* __restrict__ n_left,
+    int32_t* __restrict__ planv)
 {
     __shared__ float sv_all[kWavesPerBlock][kSampleMax];
     __shared__ uint32_t hf_all[kWavesPerBlock][kBins];
@@ -731,6 +935,8 @@ __global__ __launch_bounds__(kBlock) void k_choose_wave(Level L, int32_t* __rest
         }
         return key;
     };
+    int mode, m = 0, cdim = dim;
+    float split;
     if (dim >= 0) {
         int jl, jh;
         sample_window(s, &jl, &jh);
@@ -747,11 +953,12 @@ __global__ __launch_bounds__(kBlock) void k_choose_wave(Level L, int32_t* __rest
         for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
         const uint64_t below = row[0];
         const bool in_window = 2 * (int64_t)below <= c && 2 * (int64_t)(below + part) >= c;
-        float split;
         if (in_window) {
             const long long key = wave_key(v, 5, jl, jh + 1);
             const int j = key == LLONG_MAX ? jl : (int)(key % 2048);
             split = samples[(int64_t)node * kWinStride + (j - jl)];
+            mode = kLeftPrefix;
+            m = j - jl;
         } else {
             float* sv = sv_all[w];
             uint32_t* hf = hf_all[w];
@@ -782,129 +989,51 @@ __global__ __launch_bounds__(kBlock) void k_choose_wave(Level L, int32_t* __rest
             for (int r = 0; r < 16; ++r) vf[r] = 16 * lane + r < s ? hf[16 * lane + r] : 0u;
             const long long key = wave_key(vf, 16, 0, s);
             split = sv[key == LLONG_MAX ? 0 : (int)(key % 2048)];
+            mode = kLeftCount;
         }
-        if (lane == 0) splitv[node] = split;
-        return;
-    }
-    // the sample is constant in every dimension (see k_choose)
-    double bext = 0.0;
-    int bd = -1;
-    float bhi = 0.0f;
-    for (int dd = 0; dd < d; ++dd) {
-        const float* col = cols + (int64_t)dd * n + start;
-        float lo = INFINITY, hi = -INFINITY;
-        for (int64_t e = lane; e < c; e += kWave) {
-            const float x = col[e];
-            lo = fminf(lo, x);
-            hi = fmaxf(hi, x);
-        }
-        lo = wave_min(lo);
-        hi = wave_max(hi);
-        const double ext = (double)hi - (double)lo;
-        if (ext > bext) {
-            bext = ext;
-            bd = dd;
-            bhi = hi;
-        }
-    }
-    if (lane == 0) {
-        dimv[node] = bd;
-        splitv[node] = bhi;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// B6: stable partition -- count, per-node scan, scatter
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_count(Level L, const int32_t* __restrict__ dimv,
-                                                  const float* __restrict__ splitv,
-                                                  const float* __restrict__ cols, int64_t n,
-                                                  uint32_t* __restrict__ wave_left)
-{
-    const int b = blockIdx.x, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (b >= L.cnt[1]) return;
-    const int node = L.bnode[b];
-    const int64_t start = L.start[node], c = L.count[node];
-    const int64_t beg = L.bbeg[b];
-    const int64_t end = beg + kChunk < c ? beg + kChunk : c;
-    const int64_t wb = beg + (int64_t)w * kWaveChunk;
-    const int64_t we = wb + kWaveChunk < end ? wb + kWaveChunk : end;
-    const int dim = dimv[node];
-    uint32_t cnt = 0;
-    if (dim < 0) {
-        cnt = we > wb ? (uint32_t)(we - wb) : 0u;
     } else {
-        const float split = splitv[node];
-        const float* col = cols + (int64_t)dim * n + start;
-        float x[kItems];
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {  // every load in flight at once, clamped in range
-            const int64_t e = wb + (int64_t)i * kWave + lane;
-            x[i] = col[e < we ? e : we - 1];
-        }
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-            const bool f = wb + (int64_t)i * kWave + lane < we && x[i] < split;
-            cnt += (uint32_t)__popcll(__ballot(f));
-        }
-    }
-    if (lane == 0) wave_left[(int64_t)b * kWavesPerBlock + w] = cnt;
-}
-
-// Children of a split node that need another level pass: more than W
-// points and more than the bucket size.
-__host__ __device__ inline bool needs_level_pass(int c, int W, int leaf) { return c > W && c > leaf; }
-
-// Per-node exclusive scan of the block counts (the left count before each
-// block), the node's left count, and the node's plan counters: split (0/1),
-// children needing a level pass, subtree entries, and their blocks of kChunk
-// and kHistChunk points.
-__global__ __launch_bounds__(kBlock) void k_blkscan(Level L, const uint32_t* __restrict__ wave_left,
-                                                    const int32_t* __restrict__ dimv, int W,
-                                                    int leaf, uint32_t* __restrict__ blk_off,
-                                                    int32_t* __restrict__ n_left,
-                                                    int32_t* __restrict__ planv)
-{
-    __shared__ uint32_t wsum[kWavesPerBlock];
-    const int node = blockIdx.x, t = threadIdx.x;
-    if (node >= L.cnt[0]) return;
-    const int b0 = L.blk0[node], nb = L.nblk[node];
-    uint32_t carry = 0;
-    for (int base = 0; base < nb; base += kBlock) {
-        const int i = base + t;
-        uint32_t v = 0;
-        if (i < nb)
-            for (int w = 0; w < kWavesPerBlock; ++w)
-                v += wave_left[(int64_t)(b0 + i) * kWavesPerBlock + w];
-        uint32_t tot;
-        uint32_t ex = block_excl_scan(v, &tot, wsum);
-        if (i < nb) blk_off[b0 + i] = carry + ex;
-        carry += tot;
-    }
-    if (t == 0) {
-        n_left[node] = (int32_t)carry;
-        int v[kPlanVals] = {0, 0, 0, 0, 0};
-        const int cnt = L.count[node];
-        if (dimv[node] >= 0) {
-            const int cc[2] = {(int)carry, cnt - (int)carry};
-            v[0] = 1;
-            for (int k = 0; k < 2; ++k) {
-                if (needs_level_pass(cc[k], W, leaf)) {
-                    v[1] += 1;
-                    v[3] += (cc[k] + kChunk - 1) / kChunk;
-                    v[4] += (cc[k] + kHistChunk - 1) / kHistChunk;
-                } else {
-                    v[2] += 1;
-                }
+        // the sample is constant in every dimension (see k_choose)
+        double bext = 0.0;
+        int bd = -1;
+        float bhi = 0.0f;
+        for (int dd = 0; dd < d; ++dd) {
+            const float* col = cols + (int64_t)dd * n + start;
+            float lo = INFINITY, hi = -INFINITY;
+            for (int64_t e = lane; e < c; e += kWave) {
+                const float x = col[e];
+                lo = fminf(lo, x);
+                hi = fmaxf(hi, x);
             }
-        } else {
-            v[2] = 1;
+            lo = wave_min(lo);
+            hi = wave_max(hi);
+            const double ext = (double)hi - (double)lo;
+            if (ext > bext) {
+                bext = ext;
+                bd = dd;
+                bhi = hi;
+            }
         }
-        for (int k = 0; k < kPlanVals; ++k) planv[(int64_t)node * kPlanStride + k] = v[k];
+        if (lane == 0) dimv[node] = bd;
+        cdim = bd;
+        split = bhi;
+        mode = bd >= 0 ? kLeftCount : kLeftAll;
     }
+    if (lane == 0) splitv[node] = split;
+    const int b0 = L.blk0[node], nb = L.nblk[node];
+    if (mode == kLeftCount) {  // lane 0 writes the counts, every lane reads some
+        count_block_lefts(cols + (int64_t)cdim * n + start, c, split, b0, nb, 0, 1, blk_off);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    const BlockLefts lefts{crow, blk_off, c, b0, m, mode};
+    const uint32_t nl = wave_lefts_scan(lefts, nb, blk_off);
+    if (lane == 0) node_plan(node, (int)c, (int)nl, mode != kLeftAll, W, leaf, n_left, planv);
 }
 
+// ---------------------------------------------------------------------------
+// B6: stable partition (the per-node block offsets come from k_choose)
+// ---------------------------------------------------------------------------
 // The block's chunk of kChunk points is reordered in LDS so that every
 // column leaves as two contiguous runs (its left part, then its right part):
 // element e = 256 r + thread goes to slot rank(e) of the chunk's output.
@@ -2155,7 +2284,7 @@ struct LevelWork {
     int32_t* nleft;
     float* samples;
     uint32_t* hist;
-    uint32_t* wave_left;
+    uint16_t* crow;       // per partition block: prefix row of its window counts
     uint32_t* blk_off;
     int32_t* planv;
     int32_t* planx;
@@ -2192,15 +2321,14 @@ void enqueue_level(const LevelWork& w, const Level& cur, const Level& nxt, int l
         k_sample_block<<<g_nn, kSampleMax, 0, st>>>(cur, src, n, w.d, w.samples, w.dimv, w.hist);
     else
         k_sample<<<g_nw, kBlock, 0, st>>>(cur, src, n, w.d, w.samples, w.dimv, w.hist);
-    k_hist<<<g_nbh, kBlock, 0, st>>>(cur, w.dimv, w.samples, src, n, w.hist);
+    k_hist<<<g_nbh, kBlock, 0, st>>>(cur, w.dimv, w.samples, src, n, w.hist, w.crow);
     if (nn_l <= w.split_block_nodes)  // few large nodes: a block each
-        k_choose<<<g_nn, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, src, n, w.d, w.splitv);
+        k_choose<<<g_nn, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, w.crow, src, n, w.d,
+                                          w.W, w.leaf, w.splitv, w.blk_off, w.nleft, w.planv);
     else
-        k_choose_wave<<<g_nw, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, src, n, w.d,
-                                               w.splitv);
-    k_count<<<g_nb, kBlock, 0, st>>>(cur, w.dimv, w.splitv, src, n, w.wave_left);
-    k_blkscan<<<g_nn, kBlock, 0, st>>>(cur, w.wave_left, w.dimv, w.W, w.leaf, w.blk_off, w.nleft,
-                                       w.planv);
+        k_choose_wave<<<g_nw, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, w.crow, src, n,
+                                               w.d, w.W, w.leaf, w.splitv, w.blk_off, w.nleft,
+                                               w.planv);
     if (prof) prof_part_mark(st);
     k_scatter<<<g_nb, kBlock, 0, st>>>(cur, w.dimv, w.splitv, w.blk_off, w.nleft, src, srci, dst,
                                        dsti, n, w.d);
@@ -2518,7 +2646,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     const std::vector<int32_t>& big_roots = h0.big_roots;
     const int32_t nn0 = (int32_t)big_roots.size();
     LevelMem lvA(st), lvB(st);
-    DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), wave_left(st), blk_off(st),
+    DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), crow(st), blk_off(st),
         d_big(st), d_subs(st), d_rng(st), planv(st), planx(st), pblk(st);
     int32_t n_sub = (int32_t)h0.small.size(), n_big = T, n_levels = 1;
     std::vector<int32_t> h_g(G_COUNT + PS_COUNT, 0);
@@ -2530,7 +2658,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(nleft.alloc(sizeof(int32_t) * nn_cap));
         KNN_HIP(samples.alloc(sizeof(float) * kWinStride * nn_cap));
         KNN_HIP(hist.alloc(sizeof(uint32_t) * kWinRow * nn_cap));
-        KNN_HIP(wave_left.alloc(sizeof(uint32_t) * kWavesPerBlock * nb_cap));
+        KNN_HIP(crow.alloc(sizeof(uint16_t) * kCrowStride * nb_cap));
         KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
         KNN_HIP(planv.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
         KNN_HIP(planx.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
@@ -2563,7 +2691,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         lw.nleft = nleft.as<int32_t>();
         lw.samples = samples.as<float>();
         lw.hist = hist.as<uint32_t>();
-        lw.wave_left = wave_left.as<uint32_t>();
+        lw.crow = crow.as<uint16_t>();
         lw.blk_off = blk_off.as<uint32_t>();
         lw.planv = planv.as<int32_t>();
         lw.planx = planx.as<int32_t>();
@@ -2611,7 +2739,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
             std::memcpy(&moved, &h_g[G_MOVED], sizeof(moved));
             prof_part_points((double)moved);
         }
-        lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); wave_left.reset();
+        lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); crow.reset();
         blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset(); planv.reset(); planx.reset();
         pblk.reset();
     }
@@ -2828,7 +2956,7 @@ int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t T, int32_t
         KNN_HIP(plan_alloc(P.get(), &w.nleft, P->nn_cap));
         KNN_HIP(plan_alloc(P.get(), &w.samples, (size_t)kWinStride * P->nn_cap));
         KNN_HIP(plan_alloc(P.get(), &w.hist, (size_t)kWinRow * P->nn_cap));
-        KNN_HIP(plan_alloc(P.get(), &w.wave_left, (size_t)kWavesPerBlock * P->nb_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.crow, (size_t)kCrowStride * P->nb_cap));
         KNN_HIP(plan_alloc(P.get(), &w.blk_off, P->nb_cap));
         KNN_HIP(plan_alloc(P.get(), &w.planv, (size_t)kPlanStride * P->nn_cap));
         KNN_HIP(plan_alloc(P.get(), &w.planx, (size_t)kPlanStride * P->nn_cap));

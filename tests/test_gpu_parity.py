@@ -167,7 +167,9 @@ def test_heavy_duplicates_and_identical_big_nodes(knn):
     _full_check(knn, X, Q, 9, 32, what="duplicates")
     Y = np.concatenate([np.zeros((5000, 2), np.float32), np.ones((3, 2), np.float32)])
     Y = Y[rng.permutation(len(Y))]
-    _full_check(knn, Y, Y[:50], 4, 2, what="constant sample", subtree_points=64)
+    for sbn in (0, -1):  # the split (and its left counts) by a workgroup, then a wavefront
+        _full_check(knn, Y, Y[:50], 4, 2, what="constant sample", subtree_points=64,
+                    split_block_nodes=sbn)
 
 
 def test_subtree_nodes_above_the_lds_tile(knn):
@@ -197,15 +199,17 @@ def test_split_outside_sample_window(knn):
     systematic sample positions hit only the large, or only the small,
     values of the split dimension), so the full-histogram path decides."""
     rng = np.random.default_rng(5)
-    for big_even in (True, False):
-        x = np.empty(4096, np.float32)
-        hi = (1.0 + rng.random(2048) * 0.01).astype(np.float32)
-        lo = (rng.random(2048) * 0.001).astype(np.float32)
+    # 4,096 points: sample positions 4j + 2; 20,480 (five partition blocks of
+    # 4,096, counted one by one): 10 (2j + 1); all even either way
+    for n, big_even in ((4096, True), (4096, False), (20480, True)):
+        x = np.empty(n, np.float32)
+        hi = (1.0 + rng.random(n // 2) * 0.01).astype(np.float32)
+        lo = (rng.random(n // 2) * 0.001).astype(np.float32)
         x[0::2], x[1::2] = (hi, lo) if big_even else (lo, hi)
-        X = np.stack([x, (rng.random(4096) * 1e-4).astype(np.float32)], 1)
+        X = np.stack([x, (rng.random(n) * 1e-4).astype(np.float32)], 1)
         for sbn in (0, -1):  # split chosen by a workgroup, then by a wavefront
-            _full_check(knn, X, X[::7], 5, 32, self_ids=np.arange(0, 4096, 7),
-                        what=f"window big_even={big_even}", split_block_nodes=sbn)
+            _full_check(knn, X, X[::7], 5, 32, self_ids=np.arange(0, n, 7),
+                        what=f"window n={n} big_even={big_even}", split_block_nodes=sbn)
 
 
 def test_determinism_and_order_independence(knn):
