@@ -68,6 +68,13 @@ constexpr int kSubs = kHistChunk / kChunk;  // partition blocks per histogram bl
 constexpr int kCrowStride = kWinRow;
 static_assert(kChunk <= 65535, "per-block prefix counts are stored in 16 bits");
 constexpr int kStack = 32;                           // subtree DFS stack (entries)
+// Children of at least this many points that need another level pass get
+// their sample written by the partition that creates them (1024 values per
+// dimension, in a slot of the pre-gathered sample buffer), so the next
+// level's sampler reads it whole instead of gathering strided points: from
+// 4096 points on the strided gather fetches more lines than the slot costs
+// to write and read.
+constexpr int kPreSampleMin = 4 * kSampleMax;
 
 // A subtree handed to the finish kernel: points [start, start + count) of
 // ping-pong buffer `buf`, node id, parent id, depth of its root; leaf_only
@@ -79,9 +86,10 @@ struct SubEntry {
 };
 
 // One level of the level passes, all in device memory: the node list
-// (start, count, id, parent, depth), each node's blocks of kChunk points
-// (blk0, nblk) and the block tables (bnode, bbeg for kChunk blocks; hnode,
-// hbeg for kHistChunk blocks).  cnt = {nodes, blocks, histogram blocks}.
+// (start, count, id, parent, depth, pre-gathered sample slot or -1), each
+// node's blocks of kChunk points (blk0, nblk) and the block tables (bnode,
+// bbeg for kChunk blocks; hnode, hbeg for kHistChunk blocks).
+// cnt = {nodes, blocks, histogram blocks}.
 // Kernels are launched with grids sized for the largest possible level and
 // return at once past these counts, so no level needs a host round trip.
 struct Level {
@@ -97,6 +105,7 @@ struct Level {
     int32_t* hnode;
     int32_t* hbeg;
     int32_t* hblk0;
+    int32_t* sslot;
     int32_t* cnt;
 };
 
@@ -107,7 +116,9 @@ struct Level {
 // G_LEVEL_NODES: nodes of the level the latest pass wrote (its cnt[0]).
 enum { G_NEXT_ID = 0, G_NSUB = 1, G_ERR = 2, G_BASE_ID = 3, G_BASE_SUB = 4, G_MOVED = 6,
        G_NONFINITE = 8, G_LEVEL_NODES = 9, G_COUNT = 10 };
-constexpr int kPlanVals = 5;  // split nodes, level children, subtrees, blocks, histogram blocks
+// split nodes, level children, subtrees, blocks, histogram blocks, children
+// with a pre-gathered sample
+constexpr int kPlanVals = 6;
 constexpr int kPlanStride = 8;
 constexpr int kErrOverflow = -100;
 
@@ -242,7 +253,8 @@ __device__ inline void wave_sort1024(float (&u)[16])
 // the node's histogram row.  Bounded to 128 registers: four wavefronts per
 // SIMD, without spills.
 __global__ __launch_bounds__(kBlock, 4) void k_sample(Level L, const float* __restrict__ cols,
-                                                   int64_t n, int d, float* __restrict__ samples,
+                                                   const float* __restrict__ psamp, int64_t n,
+                                                   int d, float* __restrict__ samples,
                                                    int32_t* __restrict__ out_dim,
                                                    uint32_t* __restrict__ hist)
 {
@@ -253,6 +265,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_sample(Level L, const float* __re
     const int node = blockIdx.x * kWavesPerBlock + w;
     if (node >= L.cnt[0]) return;
     const int64_t start = L.start[node], c = L.count[node];
+    const int sl = L.sslot[node];  // >= 0: the partition wrote this node's sample (s = 1024)
     for (int i = lane; i < kWinRow; i += kWave) hist[(int64_t)node * kWinRow + i] = 0u;
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
     double bestV = -1.0;
@@ -260,12 +273,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_sample(Level L, const float* __re
     float* t = tr[w];  // the sample of the best dimension so far, element j at t[j]
     for (int dd = 0; dd < d; ++dd) {
         const float* col = cols + (int64_t)dd * n + start;
+        const float* pre = psamp + ((int64_t)(sl >= 0 ? sl : 0) * d + dd) * kSampleMax;
         double v[16], q[16];
         float f[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int j = lane + 64 * r;
-            f[r] = col[sample_pos_fast(j < s ? j : s - 1, c, s)];
+            f[r] = sl >= 0 ? pre[j] : col[sample_pos_fast(j < s ? j : s - 1, c, s)];
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = lane + 64 * r < s ? (double)f[r] : 0.0;
@@ -313,6 +327,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_sample(Level L, const float* __re
 // w = 512 .. 1) and the sort the same bitonic network, in LDS.
 __global__ __launch_bounds__(kSampleMax) void k_sample_block(Level L,
                                                             const float* __restrict__ cols,
+                                                            const float* __restrict__ psamp,
                                                             int64_t n, int d,
                                                             float* __restrict__ samples,
                                                             int32_t* __restrict__ out_dim,
@@ -327,9 +342,13 @@ __global__ __launch_bounds__(kSampleMax) void k_sample_block(Level L,
     const int s = (int)(c < kSampleMax ? c : kSampleMax);
     const bool in = t < s;
     const int64_t pos = start + sample_pos_fast(in ? t : s - 1, c, s);
+    const int sl = L.sslot[node];  // >= 0: the partition wrote this node's sample (s = 1024)
     float f[16];  // this element in every dimension, all loads in flight at once
 #pragma unroll
-    for (int dd = 0; dd < 16; ++dd) f[dd] = dd < d ? cols[(int64_t)dd * n + pos] : 0.0f;
+    for (int dd = 0; dd < 16; ++dd)
+        f[dd] = dd >= d ? 0.0f
+                        : sl >= 0 ? psamp[((int64_t)sl * d + dd) * kSampleMax + t]
+                                  : cols[(int64_t)dd * n + pos];
     // pairwise sum over the 1024 elements, to every thread: strides 512 .. 64
     // through LDS, 32 .. 1 by shuffles inside the first wavefront
     auto tree = [&](double v) {
@@ -627,13 +646,13 @@ __host__ __device__ inline bool needs_level_pass(int c, int W, int leaf) { retur
 enum { kLeftPrefix = 0, kLeftCount = 1, kLeftAll = 2 };
 
 // The node's left count and plan counters: split (0/1), children needing a
-// level pass, subtree entries, and the children's blocks of kChunk and
-// kHistChunk points.
+// level pass, subtree entries, the children's blocks of kChunk and
+// kHistChunk points, and the children that get a pre-gathered sample.
 __device__ void node_plan(int node, int cnt, int nl, bool split, int W, int leaf,
                           int32_t* __restrict__ n_left, int32_t* __restrict__ planv)
 {
     n_left[node] = nl;
-    int v[kPlanVals] = {0, 0, 0, 0, 0};
+    int v[kPlanVals] = {};
     if (split) {
         const int cc[2] = {nl, cnt - nl};
         v[0] = 1;
@@ -642,6 +661,7 @@ __device__ void node_plan(int node, int cnt, int nl, bool split, int W, int leaf
                 v[1] += 1;
                 v[3] += (cc[k] + kChunk - 1) / kChunk;
                 v[4] += (cc[k] + kHistChunk - 1) / kHistChunk;
+                v[5] += cc[k] >= kPreSampleMin;
             } else {
                 v[2] += 1;
             }
@@ -1037,17 +1057,26 @@ __global__ __launch_bounds__(kBlock) void k_choose_wave(
 // The block's chunk of kChunk points is reordered in LDS so that every
 // column leaves as two contiguous runs (its left part, then its right part):
 // element e = 256 r + thread goes to slot rank(e) of the chunk's output.
+// With kSamples, a child with a pre-gathered sample slot (cslot) also gets,
+// from each coordinate column, the values at its sample positions that fall
+// in this chunk's run for it (levels whose nodes have no such children take
+// the plain instance: four fewer registers, a wavefront more per SIMD).
+template <bool kSamples>
 __global__ __launch_bounds__(kBlock) void k_scatter(
     Level L, const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
     const uint32_t* __restrict__ blk_off, const int32_t* __restrict__ n_left,
-    const float* __restrict__ src_cols, const int32_t* __restrict__ src_idx,
-    float* __restrict__ dst_cols, int32_t* __restrict__ dst_idx, int64_t n, int d)
+    const int32_t* __restrict__ cslot, int64_t ps_cap, const float* __restrict__ src_cols,
+    const int32_t* __restrict__ src_idx, float* __restrict__ dst_cols,
+    int32_t* __restrict__ dst_idx, float* __restrict__ psamp, int64_t n, int d)
 {
     constexpr int kR = kChunk / kBlock;  // 16 elements per thread
     __shared__ uint16_t perm[kChunk];
     __shared__ uint32_t stage[kChunk];
     __shared__ uint32_t cnt[kR][kWavesPerBlock];
     __shared__ uint32_t pre[kR * kWavesPerBlock + 1];
+    // per child: sample slot (-1: none), first sample rank in the run, run
+    // length, child count, child position of the run's first point
+    __shared__ int ps_par[2][5];
     const int b = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
     if (b >= L.cnt[1]) return;
     const int node = L.bnode[b];
@@ -1103,6 +1132,33 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
             perm[slot] = (uint16_t)e;
         }
     }
+    if (kSamples && t < 2) {
+        // the children's sample ranks from j0 on lie in this chunk's runs: run
+        // k holds child positions p0 .. p0 + rlen - 1 at output slots from
+        // k ? nl_chunk : 0 (the sample position of rank j is
+        // floor((2j + 1) c' / 2048), s = 1024); thread k takes child k
+        const int k = t;
+        const int cc = k ? (int)(c - nl) : (int)nl;
+        const int p0 = (int)(k ? beg - lefts_before : lefts_before);
+        const int rl = k ? len - (int)nl_chunk : (int)nl_chunk;
+        const int sl = dim >= 0 ? cslot[2 * (int64_t)node + k] : -1;
+        const bool on = sl >= 0 && sl < ps_cap && cc >= kPreSampleMin && rl > 0;
+        int j0 = 0;
+        if (on) {  // the smallest j with (2j + 1) c' >= 2048 p0
+            const int64_t num = 2 * (int64_t)kSampleMax * p0 - cc, den = 2 * (int64_t)cc;
+            if (num > 0) {
+                int64_t j = (int64_t)ceil((double)num / (double)den);  // exact after the fix-ups
+                if (j * den < num) ++j;
+                if (j > 0 && (j - 1) * den >= num) --j;
+                j0 = (int)j;
+            }
+        }
+        ps_par[k][0] = on ? sl : -1;
+        ps_par[k][1] = j0;
+        ps_par[k][2] = rl;
+        ps_par[k][3] = cc;
+        ps_par[k][4] = p0;
+    }
     __syncthreads();
     // columns 0 .. d (d is the index column): stage in LDS, then write the
     // left and right runs contiguously; the next column's loads are issued
@@ -1142,6 +1198,31 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
             if (i < len) {
                 const int64_t dst = i < (int)nl_chunk ? base_l + i : base_r + (i - (int)nl_chunk);
                 dstw[dst] = stage[perm[i]];
+            }
+        }
+        // the children's samples (the loop bodies stay rolled: unrolled, they
+        // need more registers)
+        if (kSamples && col < d) {
+#pragma unroll 1
+            for (int k = 0; k < 2; ++k) {  // block-uniform values, in scalar registers
+                const int sl = __builtin_amdgcn_readfirstlane(ps_par[k][0]);
+                if (sl < 0) continue;
+                uint32_t* ps = reinterpret_cast<uint32_t*>(psamp) +
+                               ((int64_t)sl * d + col) * kSampleMax;
+                const int i0 = k == 0 ? 0 : __builtin_amdgcn_readfirstlane((int)nl_chunk);
+                const int rlen = __builtin_amdgcn_readfirstlane(ps_par[k][2]);
+                const uint32_t cc = (uint32_t)__builtin_amdgcn_readfirstlane(ps_par[k][3]);
+                const int p0 = __builtin_amdgcn_readfirstlane(ps_par[k][4]);
+#pragma unroll 1
+                for (int j = __builtin_amdgcn_readfirstlane(ps_par[k][1]) + t; j < kSampleMax;
+                     j += kBlock) {
+                    // (2j + 1) c' >> 11 from the 64-bit product's two halves
+                    const uint32_t a = 2u * (uint32_t)j + 1u;
+                    const uint32_t pos = (__umulhi(a, cc) << 21) | ((a * cc) >> 11);
+                    const int q = (int)pos - p0;
+                    if (q >= rlen) break;
+                    ps[j] = stage[perm[i0 + q]];
+                }
             }
         }
         __syncthreads();
@@ -2002,7 +2083,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_local(
     const int nn = cur.cnt[0];
     const int i = blockIdx.x * kPlanBlock + t;
     if (blockIdx.x * kPlanBlock >= nn) return;  // block-uniform
-    int v[kPlanVals] = {0, 0, 0, 0, 0};
+    int v[kPlanVals] = {};
     unsigned long long pts = 0;  // points this level partitions (profiling counter)
     if (i < nn) {
 #pragma unroll
@@ -2040,12 +2121,12 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_local(
 __global__ __launch_bounds__(kPlanBlock) void k_plan_top(
     Level cur, Level nxt, int32_t* __restrict__ pblk, int32_t* __restrict__ g,
     int32_t* __restrict__ rng, int level, int64_t big_cap, int64_t sub_cap, int64_t nn_cap,
-    int64_t nb_cap, int64_t nbh_cap)
+    int64_t nb_cap, int64_t nbh_cap, int64_t ps_cap)
 {
     __shared__ int wsum[kPlanBlock / 64][kPlanVals];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int nblk = (cur.cnt[0] + kPlanBlock - 1) / kPlanBlock;
-    int carry[kPlanVals] = {0, 0, 0, 0, 0};
+    int carry[kPlanVals] = {};
     for (int b0 = 0; b0 < nblk; b0 += kPlanBlock) {  // exclusive scan of the block totals
         const int b = b0 + t;
         int v[kPlanVals], x[kPlanVals];
@@ -2091,7 +2172,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_top(
         rng[2 * (level + 1)] = base_id;
         rng[2 * (level + 1) + 1] = base_id + 2 * tot[0];
         if (base_id + 2 * (int64_t)tot[0] > big_cap || base_sub + (int64_t)tot[2] > sub_cap ||
-            tot[1] > nn_cap || tot[3] > nb_cap || tot[4] > nbh_cap) {
+            tot[1] > nn_cap || tot[3] > nb_cap || tot[4] > nbh_cap || tot[5] > ps_cap) {
             atomicExch(&g[G_ERR], kErrOverflow);
             nxt.cnt[0] = nxt.cnt[1] = nxt.cnt[2] = 0;  // nothing more is written
             g[G_LEVEL_NODES] = 0;
@@ -2101,16 +2182,20 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_top(
 
 // One thread per node of the level: the split node's record (children get
 // ids L and L+1, L = base + 2 * (split nodes before it)), its children in
-// the next level's node list or in the subtree list, and nodes whose points
-// all coincide as oversized buckets.
+// the next level's node list (with their pre-gathered sample slots when the
+// partition of this level writes them, also left in cslot for it) or in the
+// subtree list, and nodes whose points all coincide as oversized buckets.
 __global__ __launch_bounds__(kBlock) void k_plan_write(
     Level cur, Level nxt, const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
     const int32_t* __restrict__ nleft, const int32_t* __restrict__ planx,
     const int32_t* __restrict__ pblk, int leaf, int W, int max_depth, int nbuf,
-    NodeRec* __restrict__ big, SubEntry* __restrict__ subs, int32_t* __restrict__ g)
+    NodeRec* __restrict__ big, SubEntry* __restrict__ subs, int32_t* __restrict__ cslot,
+    int presample, int32_t* __restrict__ g)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cur.cnt[0] || g[G_ERR] == kErrOverflow) return;
+    if (i >= cur.cnt[0]) return;
+    cslot[2 * (int64_t)i] = cslot[2 * (int64_t)i + 1] = -1;
+    if (g[G_ERR] == kErrOverflow) return;
     const int st = cur.start[i], cnt = cur.count[i], id = cur.id[i];
     const int par = cur.parent[i], dep = cur.depth[i], dm = dimv[i];
     int x[kPlanVals];
@@ -2127,9 +2212,12 @@ __global__ __launch_bounds__(kBlock) void k_plan_write(
     big[id] = NodeRec{L, par, splitv[i], dm};
     if (dep + 1 > max_depth) atomicCAS(&g[G_ERR], 0, KNN_EDEPTH);
     const int cs[2] = {st, st + nl}, cc[2] = {nl, cnt - nl};
-    int pos = x[1], b0 = x[3], h0 = x[4], sidx = base_sub + x[2];
+    int pos = x[1], b0 = x[3], h0 = x[4], sidx = base_sub + x[2], ps = x[5];
     for (int k = 0; k < 2; ++k) {
         if (needs_level_pass(cc[k], W, leaf)) {
+            const int sl = presample && cc[k] >= kPreSampleMin ? ps++ : -1;
+            cslot[2 * (int64_t)i + k] = sl;
+            nxt.sslot[pos] = sl;
             nxt.start[pos] = cs[k];
             nxt.count[pos] = cc[k];
             nxt.id[pos] = L + k;
@@ -2176,7 +2264,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_fill(Level nxt)
 // Int32 words of one Level with the given capacities.
 inline size_t level_words(int64_t nn_cap, int64_t nb_cap, int64_t nbh_cap)
 {
-    return 8 * (size_t)nn_cap + 2 * (size_t)nb_cap + 2 * (size_t)nbh_cap + 4;
+    return 9 * (size_t)nn_cap + 2 * (size_t)nb_cap + 2 * (size_t)nbh_cap + 4;
 }
 
 // The arrays of one Level laid out in level_words() words at p.
@@ -2195,6 +2283,7 @@ inline Level carve_level(int32_t* p, int64_t nn_cap, int64_t nb_cap, int64_t nbh
     L.hnode = p; p += nbh_cap;
     L.hbeg = p; p += nbh_cap;
     L.hblk0 = p; p += nn_cap;
+    L.sslot = p; p += nn_cap;
     L.cnt = p;
     return L;
 }
@@ -2285,6 +2374,8 @@ struct LevelWork {
     float* samples;
     uint32_t* hist;
     uint16_t* crow;       // per partition block: prefix row of its window counts
+    float* psamp;         // pre-gathered samples: [slot][d][1024]
+    int32_t* cslot;       // per level node: its two children's sample slots (or -1)
     uint32_t* blk_off;
     int32_t* planv;
     int32_t* planx;
@@ -2297,12 +2388,16 @@ struct LevelWork {
     int d, leaf, W, max_depth;
     int64_t split_block_nodes;
     int64_t nn0;          // nodes of level 0
-    int64_t nn_cap, nb_cap, nbh_cap, big_cap, sub_cap;
+    int64_t largest;      // points of the largest root
+    int64_t nn_cap, nb_cap, nbh_cap, big_cap, sub_cap, ps_cap;
 };
 
 // Enqueues one level pass (B1-B7) over the nodes of `cur`, writing the next
 // level into `nxt`.  Grids are sized for the largest level possible at this
-// depth; the kernels read the actual counts from cur.cnt on the device.
+// depth; the kernels read the actual counts from cur.cnt on the device.  The
+// bookkeeping runs before the partition (it needs only the split and the left
+// counts), so the partition knows which children take a pre-gathered sample
+// and where.
 void enqueue_level(const LevelWork& w, const Level& cur, const Level& nxt, int level, int buf,
                    bool prof, hipStream_t st)
 {
@@ -2318,9 +2413,10 @@ void enqueue_level(const LevelWork& w, const Level& cur, const Level& nxt, int l
     int32_t* dsti = w.idx[buf ^ 1];
     const unsigned g_nw = (g_nn + kWavesPerBlock - 1) / kWavesPerBlock;
     if (nn_l <= w.split_block_nodes)  // few nodes: a workgroup each
-        k_sample_block<<<g_nn, kSampleMax, 0, st>>>(cur, src, n, w.d, w.samples, w.dimv, w.hist);
+        k_sample_block<<<g_nn, kSampleMax, 0, st>>>(cur, src, w.psamp, n, w.d, w.samples, w.dimv,
+                                                    w.hist);
     else
-        k_sample<<<g_nw, kBlock, 0, st>>>(cur, src, n, w.d, w.samples, w.dimv, w.hist);
+        k_sample<<<g_nw, kBlock, 0, st>>>(cur, src, w.psamp, n, w.d, w.samples, w.dimv, w.hist);
     k_hist<<<g_nbh, kBlock, 0, st>>>(cur, w.dimv, w.samples, src, n, w.hist, w.crow);
     if (nn_l <= w.split_block_nodes)  // few large nodes: a block each
         k_choose<<<g_nn, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, w.crow, src, n, w.d,
@@ -2329,20 +2425,24 @@ void enqueue_level(const LevelWork& w, const Level& cur, const Level& nxt, int l
         k_choose_wave<<<g_nw, kBlock, 0, st>>>(cur, w.dimv, w.samples, w.hist, w.crow, src, n,
                                                w.d, w.W, w.leaf, w.splitv, w.blk_off, w.nleft,
                                                w.planv);
-    if (prof) prof_part_mark(st);
-    k_scatter<<<g_nb, kBlock, 0, st>>>(cur, w.dimv, w.splitv, w.blk_off, w.nleft, src, srci, dst,
-                                       dsti, n, w.d);
-    if (prof) prof_part_mark(st);
     k_plan_local<<<blocks_for(nn_l, kPlanBlock), kPlanBlock, 0, st>>>(cur, w.planv, w.planx,
                                                                        w.pblk, w.g);
     k_plan_top<<<1, kPlanBlock, 0, st>>>(cur, nxt, w.pblk, w.g, w.rng, level, w.big_cap,
-                                         w.sub_cap, w.nn_cap, w.nb_cap, w.nbh_cap);
+                                         w.sub_cap, w.nn_cap, w.nb_cap, w.nbh_cap, w.ps_cap);
+    // pre-gathered samples while the largest tree's children can still hold
+    // kPreSampleMin points (splits near the median halve the nodes)
+    const bool pres = level < 62 && (w.largest >> (level + 1)) >= kPreSampleMin;
     k_plan_write<<<blocks_for(nn_l, kBlock), kBlock, 0, st>>>(
         cur, nxt, w.dimv, w.splitv, w.nleft, w.planx, w.pblk, w.leaf, w.W, w.max_depth, buf ^ 1,
-        w.big, w.subs, w.g);
+        w.big, w.subs, w.cslot, pres ? 1 : 0, w.g);
     const int64_t nn_next = std::min<int64_t>(2 * nn_l, w.nn_cap);
     const int64_t fill = std::min<int64_t>(n / kChunk + nn_next + 1, w.nb_cap);
     k_plan_fill<<<blocks_for(fill, kBlock), kBlock, 0, st>>>(nxt);
+    if (prof) prof_part_mark(st);
+    (pres ? k_scatter<true> : k_scatter<false>)<<<g_nb, kBlock, 0, st>>>(
+        cur, w.dimv, w.splitv, w.blk_off, w.nleft, w.cslot, w.ps_cap, src, srci, dst, dsti,
+        w.psamp, n, w.d);
+    if (prof) prof_part_mark(st);
 }
 
 }  // namespace
@@ -2436,6 +2536,7 @@ __global__ void k_run_level0(PlanLevel0 P, Level L0, SubEntry* __restrict__ subs
         L0.hbeg[i] = ((int)i - hblk0[o]) * kHistChunk;
     }
     for (int64_t i = i0; i < P.n_small; i += stride) subs[i] = P.small[i];
+    for (int64_t i = i0; i < P.nn0; i += stride) L0.sslot[i] = -1;  // roots gather their sample
     if (i0 == 0) {
         if (P.nn0) {
             L0.cnt[0] = bad ? 0 : P.nn0;
@@ -2639,6 +2740,8 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     const int64_t nn_cap = n / (W + 1) + 1;
     const int64_t nb_cap = n / kChunk + nn_cap + 1;
     const int64_t nbh_cap = n / kHistChunk + nn_cap + 1;
+    // a level's children with pre-gathered samples hold kPreSampleMin points each
+    const int64_t ps_cap = n / kPreSampleMin + 1;
     const int64_t lv_cap = (int64_t)max_depth + 2;
     // every level-pass node and subtree entry descends from a level node
     const int64_t big_cap = T + 2 * nn_cap * lv_cap + 2;
@@ -2646,7 +2749,8 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
     const std::vector<int32_t>& big_roots = h0.big_roots;
     const int32_t nn0 = (int32_t)big_roots.size();
     LevelMem lvA(st), lvB(st);
-    DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), crow(st), blk_off(st),
+    DevBuf dimv(st), splitv(st), nleft(st), samples(st), hist(st), crow(st), psamp(st), cslot(st),
+        blk_off(st),
         d_big(st), d_subs(st), d_rng(st), planv(st), planx(st), pblk(st);
     int32_t n_sub = (int32_t)h0.small.size(), n_big = T, n_levels = 1;
     std::vector<int32_t> h_g(G_COUNT + PS_COUNT, 0);
@@ -2659,6 +2763,8 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         KNN_HIP(samples.alloc(sizeof(float) * kWinStride * nn_cap));
         KNN_HIP(hist.alloc(sizeof(uint32_t) * kWinRow * nn_cap));
         KNN_HIP(crow.alloc(sizeof(uint16_t) * kCrowStride * nb_cap));
+        KNN_HIP(psamp.alloc(sizeof(float) * kSampleMax * d * ps_cap));
+        KNN_HIP(cslot.alloc(sizeof(int32_t) * 2 * nn_cap));
         KNN_HIP(blk_off.alloc(sizeof(uint32_t) * nb_cap));
         KNN_HIP(planv.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
         KNN_HIP(planx.alloc(sizeof(int32_t) * kPlanStride * nn_cap));
@@ -2692,6 +2798,8 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         lw.samples = samples.as<float>();
         lw.hist = hist.as<uint32_t>();
         lw.crow = crow.as<uint16_t>();
+        lw.psamp = psamp.as<float>();
+        lw.cslot = cslot.as<int32_t>();
         lw.blk_off = blk_off.as<uint32_t>();
         lw.planv = planv.as<int32_t>();
         lw.planx = planx.as<int32_t>();
@@ -2707,11 +2815,13 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
         lw.max_depth = max_depth;
         lw.split_block_nodes = split_block_nodes;
         lw.nn0 = nn0;
+        lw.largest = h0.largest;
         lw.nn_cap = nn_cap;
         lw.nb_cap = nb_cap;
         lw.nbh_cap = nbh_cap;
         lw.big_cap = big_cap;
         lw.sub_cap = sub_cap;
+        lw.ps_cap = ps_cap;
         Level cur = lvA.L, nxt = lvB.L;
         int buf = 0;
         for (int level = 0;; ++level) {
@@ -2740,6 +2850,7 @@ int build_tree(const float* points, int64_t n, int32_t d, int32_t leaf, int32_t 
             prof_part_points((double)moved);
         }
         lvA.mem.reset(); lvB.mem.reset(); samples.reset(); hist.reset(); crow.reset();
+        psamp.reset(); cslot.reset();
         blk_off.reset(); dimv.reset(); splitv.reset(); nleft.reset(); planv.reset(); planx.reset();
         pblk.reset();
     }
@@ -2837,7 +2948,7 @@ struct knn_build_plan {
     int64_t n = 0;
     int32_t d = 0, leaf = 0, W = 0, max_depth = 0, T = 0, levels = 0;
     int64_t split_block_nodes = 0;
-    int64_t nn_cap = 0, nb_cap = 0, nbh_cap = 0, big_cap = 0, sub_cap = 0, node_cap = 0;
+    int64_t nn_cap = 0, nb_cap = 0, nbh_cap = 0, big_cap = 0, sub_cap = 0, node_cap = 0, ps_cap = 0;
     int32_t Wt = 0;
     size_t per_wave = 0, lds = 0;
     unsigned fgrid = 0;
@@ -2918,6 +3029,7 @@ int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t T, int32_t
     P->nn_cap = n / (W + 1) + 1;
     P->nb_cap = n / kChunk + P->nn_cap + 1;
     P->nbh_cap = n / kHistChunk + P->nn_cap + 1;
+    P->ps_cap = n / kPreSampleMin + 1;
     P->big_cap = T + 2 * P->nn_cap * lv_cap + 2;
     P->sub_cap = std::min<int64_t>(n, P->big_cap);
     P->node_cap = std::max<int64_t>(2 * n + T, P->big_cap);
@@ -2957,6 +3069,8 @@ int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t T, int32_t
         KNN_HIP(plan_alloc(P.get(), &w.samples, (size_t)kWinStride * P->nn_cap));
         KNN_HIP(plan_alloc(P.get(), &w.hist, (size_t)kWinRow * P->nn_cap));
         KNN_HIP(plan_alloc(P.get(), &w.crow, (size_t)kCrowStride * P->nb_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.psamp, (size_t)kSampleMax * d * P->ps_cap));
+        KNN_HIP(plan_alloc(P.get(), &w.cslot, 2 * P->nn_cap));
         KNN_HIP(plan_alloc(P.get(), &w.blk_off, P->nb_cap));
         KNN_HIP(plan_alloc(P.get(), &w.planv, (size_t)kPlanStride * P->nn_cap));
         KNN_HIP(plan_alloc(P.get(), &w.planx, (size_t)kPlanStride * P->nn_cap));
@@ -2985,11 +3099,13 @@ int plan_create(int64_t n, int32_t d, const int64_t* offsets, int32_t T, int32_t
     w.max_depth = max_depth;
     w.split_block_nodes = split_block_nodes;
     w.nn0 = nn0;
+    w.largest = h0.largest;
     w.nn_cap = P->nn_cap;
     w.nb_cap = P->nb_cap;
     w.nbh_cap = P->nbh_cap;
     w.big_cap = P->big_cap;
     w.sub_cap = P->sub_cap;
+    w.ps_cap = P->ps_cap;
     P->ff = ff;
     P->ff_tail = finish_for(d, true);
     P->Wt = finish_tile_points(d, W);
