@@ -420,7 +420,11 @@ __global__ __launch_bounds__(kSampleMax) void k_sample_block(Level L,
 // C_j = #{x < s_j} exactly for every j in [jl, jh].  Points below the window
 // are counted with wavefront ballots; the points inside are first queued per
 // wavefront in LDS so that every lane of a binary search over the window's
-// sample values has a point to place.  The counts are kept per partition
+// sample values has a point to place.  The search runs over the values
+// s_(jl+1) .. s_(jl+255) in breadth-first (Eytzinger) order, so that step L
+// reads entries 2^L .. 2^(L+1) - 1, consecutive words in distinct banks (a
+// search over the sorted order reads odd multiples of its step, up to eight
+// lanes per bank).  The counts are kept per partition
 // block of kChunk points (the queue carries each point's block) and leave as
 // the node's row and as each block's prefix row (see kCrowStride).
 __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restrict__ dimv,
@@ -429,7 +433,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
                                                  uint32_t* __restrict__ hist,
                                                  uint16_t* __restrict__ crow)
 {
-    __shared__ float sv[2 * kWinHalf + 1];
+    static_assert(2 * kWinHalf == 256, "an eight-step search over 255 window values");
+    __shared__ float ev[2 * kWinHalf];  // ev[k], k = 1..255: node k of the search tree
     __shared__ uint32_t h[kSubs][kWinRow];
     __shared__ float queue[kWavesPerBlock][2 * kWave];
     __shared__ uint8_t qsub[kWavesPerBlock][2 * kWave];
@@ -462,26 +467,33 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
             xn[u] = col[e < len ? e : len - 1];
         }
     }
-    // past nwin the values read +inf: a search step there never moves (an
-    // in-window point is below sv[nwin]), so the search needs no bound test
-    for (int i = t; i <= 2 * kWinHalf; i += kBlock)
-        sv[i] = i <= nwin ? samples[(int64_t)node * kWinStride + i] : INFINITY;
+    // node k at depth L (2^L <= k < 2^(L+1)) holds window entry
+    // (2k + 1) 2^(7-L) - 256, its in-order place; past nwin the values read
+    // +inf, which an in-window point (below the entry nwin) never passes
+    const float* wv = samples + (int64_t)node * kWinStride;
+    for (int k = t; k < 2 * kWinHalf; k += kBlock) {
+        if (k == 0) continue;
+        const int L = 31 - __clz(k);
+        const int e = ((2 * k + 1) << (7 - L)) - 2 * kWinHalf;
+        ev[k] = e <= nwin ? wv[e] : INFINITY;
+    }
     const int nsub = (len + kChunk - 1) / kChunk;  // partition blocks in the chunk
     for (int i = t; i < nsub * kWinRow; i += kBlock) (&h[0][0])[i] = 0u;
     __syncthreads();
-    const float lo_v = sv[0], hi_v = sv[nwin];
+    const float lo_v = wv[0], hi_v = wv[nwin];
     int qn = 0;  // queued points of this wavefront (uniform)
     float* qw = queue[w];
     uint8_t* qs = qsub[w];
-    // place the first 64 queued points: bin = jl + 1 + #{1 <= i < nwin : sv[i] <= x}
+    // place the first 64 queued points: bin = jl + 1 + #{1 <= i < nwin : s_(jl+i) <= x}
+    // (the search leaves node 256 + that count)
     auto drain = [&]() {
         __builtin_amdgcn_wave_barrier();
         const float x = qw[lane];
         const int sb = qs[lane];
-        int pos = 0;
+        int kn = 1;
 #pragma unroll
-        for (int step = kWinHalf; step > 0; step >>= 1) pos = sv[pos + step] <= x ? pos + step : pos;
-        atomicAdd(&h[sb][1 + pos], 1u);
+        for (int step = 0; step < 8; ++step) kn = 2 * kn + (ev[kn] <= x ? 1 : 0);
+        atomicAdd(&h[sb][1 + kn - 2 * kWinHalf], 1u);
         const float tail = qw[kWave + lane];
         const uint8_t tsb = qs[kWave + lane];
         if (lane < qn - kWave) {
@@ -527,11 +539,10 @@ __global__ __launch_bounds__(kBlock) void k_hist(Level L, const int32_t* __restr
         const float x = qw[lane];
         const int sb = qs[lane];
         if (lane < qn) {
-            int pos = 0;
+            int kn = 1;
 #pragma unroll
-            for (int step = kWinHalf; step > 0; step >>= 1)
-                pos = sv[pos + step] <= x ? pos + step : pos;
-            atomicAdd(&h[sb][1 + pos], 1u);
+            for (int step = 0; step < 8; ++step) kn = 2 * kn + (ev[kn] <= x ? 1 : 0);
+            atomicAdd(&h[sb][1 + kn - 2 * kWinHalf], 1u);
         }
     }
     __syncthreads();
