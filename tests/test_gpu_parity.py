@@ -193,6 +193,20 @@ def test_subtree_nodes_above_the_lds_tile(knn):
                 what="duplicate children above the tile", subtree_points=1024)
 
 
+@pytest.mark.parametrize("n", [8191, 8192, 8193, 12289, 65537])
+def test_presampled_children_around_the_threshold(knn, n):
+    """Children of at least 4,096 points get their sample written by the
+    partition that creates them; roots of 8,191 .. 65,537 points put the
+    children of the first levels on both sides of that size (and children of
+    exactly 4,096 points), under the workgroup and the wavefront samplers."""
+    X = inputs.clustered(n, seed=n, n_clusters=7)
+    rng = np.random.default_rng(n)
+    ids = rng.choice(n, 300, replace=False).astype(np.int32)
+    for sbn in (0, -1):
+        _full_check(knn, X, X[ids], 6, 32, self_ids=ids, what=f"presampled n={n}",
+                    split_block_nodes=sbn)
+
+
 def test_split_outside_sample_window(knn):
     """The level histogram resolves only the sample ranks around the middle;
     these inputs put the point closest to half outside that window (the
