@@ -5,10 +5,12 @@
 // (III-A iii), then packs buckets (III-A iv).  Here:
 //   * ingest:    caller AoS [n,d] -> SoA columns + index column
 //   * level pass (nodes above `W` points), one node list per level:
-//       k_sample   one wavefront per node: sample of min(1024, cnt) points,
-//                  FP64 variance per dim, split dim = argmax, the sample of
-//                  that dim sorted in registers; keeps the ranks around the
-//                  middle that the histogram resolves
+//       k_sample   one wavefront per node: sample of min(1024, cnt) points
+//                  (read whole from the slot the previous partition filled,
+//                  for nodes of at least 4096 points), FP64 variance per dim,
+//                  split dim = argmax, the sample of that dim sorted in
+//                  registers; keeps the ranks around the middle that the
+//                  histogram resolves
 //       k_hist     counts below that window of ranks and the bins inside it
 //                  (per-wavefront LDS queue, LDS binary search), per node and
 //                  as a prefix row per partition block
@@ -17,10 +19,11 @@
 //                  (k_choose_wave: the same with one wavefront per node); then
 //                  each partition block's left count (a read of its prefix
 //                  row) and their exclusive scan over the node
-//       k_scatter  stable partition of coordinates + index into the other
-//                  ping-pong buffer (ballot + mbcnt ranks, LDS staging)
 //       k_plan_*   children ids, next level's node list and block tables,
-//                  subtree entries: prefix sums on the device
+//                  sample slots, subtree entries: prefix sums on the device
+//       k_scatter  stable partition of coordinates + index into the other
+//                  ping-pong buffer (ballot + mbcnt ranks, LDS staging); also
+//                  copies the large children's samples into their slots
 //   * k_finish:  one wavefront per node of at most W points builds its whole
 //                subtree in LDS (every point is a sample there, so the split
 //                is the exact value the histogram rule selects), computes the
