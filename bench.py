@@ -351,6 +351,62 @@ def bench_plasma(knn, torch, dev, threads: int) -> dict:
             "sweep": sweep, "identical_across_leaf_sizes": same, "verified_sample": verified}
 
 
+def bench_tiny(knn, torch, dev) -> dict:
+    """The small uniform workload (n = 65,536 3-D points, 4,096 fresh uniform
+    queries, k = 5, leaf 32): build + query timed (median of 20 after 3
+    warm-ups) and checked against the oracle.  Its 1 MiB of coordinates stay
+    in the caches and each step is a handful of short launches, so launch
+    latency and L2, not HBM, bind it; the HBM fractions are reported only to
+    show that."""
+    import oracle
+    from paper_1607_08220_amd import inputs
+    w = inputs.workload("tiny_uniform")
+    n, d = w.points.shape
+    m, k = len(w.queries), w.k
+    P = torch.from_numpy(w.points).to(dev)
+    Q = torch.from_numpy(w.queries).to(dev)
+    idx = torch.empty((m, k), dtype=torch.int32, device=dev)
+    d2 = torch.empty((m, k), dtype=torch.float32, device=dev)
+    bt, qt, tt = [], [], []
+    tr = None
+    for rep in range(23):
+        if tr is not None:
+            tr.free()
+        tr = knn.knn_build(P, w.leaf)
+        pb = knn.knn_get_profile()
+        knn.knn_query_ex(tr, Q, k, out=(idx, d2))
+        pq = knn.knn_get_profile()
+        if rep >= 3:
+            bt.append(pb["build_total"])
+            qt.append(pq["query_total"])
+            tt.append(pq["query_traverse"])
+    info = tr.info()
+    stats = torch.zeros(knn.KNN_QUERY_STATS, dtype=torch.int64, device=dev)
+    knn.knn_query_ex(tr, Q, k, stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy().astype(np.float64) / m
+    gi, gd = idx.cpu().numpy(), d2.cpu().numpy()
+    tr.free()
+    oi, od = oracle.build(w.points, w.leaf).query(w.queries, k)
+    verified = bool(np.array_equal(oi, gi) and np.array_equal(od.view(np.uint32),
+                                                               gd.view(np.uint32)))
+    bms, qms, tms = (float(np.median(v)) for v in (bt, qt, tt))
+    levels = build_levels(n, info["subtree_points"])
+    bpp = build_bytes_per_point(d, levels)
+    bpq = query_bytes_per_query(d, k, st[0], st[2])
+    log(f"tiny uniform: build {bms:.3f} ms, query {qms:.3f} ms (traversal {tms:.3f}); "
+        f"all {m} queries vs the oracle: {'bit-exact' if verified else 'MISMATCH'}")
+    del P, Q, idx, d2
+    return {"workload": "tiny_uniform", "n_points": n, "dim": d, "n_queries": m, "k": k,
+            "leaf_size": w.leaf, "queries": "fresh uniform points",
+            "build_ms": bms, "query_ms": qms, "traverse_ms": tms,
+            "build_mpts_per_s": n / (bms * 1e-3) / 1e6, "queries_per_s": m / (qms * 1e-3),
+            "build_hbm_frac": bpp * n / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traverse_hbm_frac": bpq * m / (tms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bound": "cache-resident (1 MiB of points): launch latency and L2",
+            "verified_all_vs_oracle": verified}
+
+
 def bench_serving(knn, torch, dev, tree3, X3, load: float, seconds: float,
                   slot_kwargs=None, legs=("slots", "batches", "per_call")) -> dict:
     """Serving: the resident clustered 3-D tree plus a 10-D correlated-Gaussian
@@ -691,6 +747,7 @@ def main() -> int:
         del P, Q, S, idx, d2
         torch.cuda.empty_cache()
         out["batched"] = bench_forest(knn, torch, dev)
+        out["tiny_uniform"] = bench_tiny(knn, torch, dev)
     else:
         trees[-1].free()
         del P, Q, S, idx, d2
