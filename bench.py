@@ -57,9 +57,10 @@ def build_floor_bytes_per_point(d: int) -> float:
 
 
 def partition_bytes_per_point(d: int) -> float:
-    """Algorithmic bytes the partition kernel moves per point: the split
-    coordinate read for the flags, then d coordinates + index read and written."""
-    return 4 + 8 * (d + 1)
+    """Algorithmic bytes the partition kernel moves per point: d coordinates +
+    index read and written once (the split coordinate it tests is one of them;
+    the histogram's read of it belongs to the histogram pass)."""
+    return 8 * (d + 1)
 
 
 def measured_traffic(kernel_file: str, profile: str):

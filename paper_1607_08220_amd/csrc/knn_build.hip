@@ -1071,11 +1071,15 @@ __global__ __launch_bounds__(kBlock) void k_choose_wave(
 // The block's chunk of kChunk points is reordered in LDS so that every
 // column leaves as two contiguous runs (its left part, then its right part):
 // element e = 256 r + thread goes to slot rank(e) of the chunk's output.
-// With kSamples, a child with a pre-gathered sample slot (cslot) also gets,
-// from each coordinate column, the values at its sample positions that fall
-// in this chunk's run for it (levels whose nodes have no such children take
-// the plain instance: four fewer registers, a wavefront more per SIMD).
-template <bool kSamples>
+// The kLarge instance, for the levels whose children can hold kPreSampleMin
+// points: a child with a pre-gathered sample slot (cslot) also gets, from
+// each coordinate column, the values at its sample positions that fall in
+// this chunk's run for it, and the split column is moved first, staged from
+// the key loads, so the block reads it once.  The other levels (small nodes,
+// many short blocks) take the plain instance, which reads the split column
+// again with the others but needs 94 registers instead of 116: a wavefront
+// more per SIMD, which those levels need more than the bytes.
+template <bool kLarge>
 __global__ __launch_bounds__(kBlock) void k_scatter(
     Level L, const int32_t* __restrict__ dimv, const float* __restrict__ splitv,
     const uint32_t* __restrict__ blk_off, const int32_t* __restrict__ n_left,
@@ -1113,6 +1117,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
         const int e = kBlock * r + t;
         kv[r] = key[e < len ? e : len - 1];
     }
+    // kLarge: the split column (column 0 for a node that stays whole) is
+    // moved first, staged here from the key loads
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int e = kBlock * r + t;
@@ -1120,6 +1126,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
         const bool f = ok && (dim < 0 || kv[r] < split);
         lmask[r] = __ballot(f);
         if (lane == 0) cnt[r][w] = (uint32_t)__popcll(lmask[r]);
+        if (kLarge && ok) stage[e] = __float_as_uint(kv[r]);
     }
     __syncthreads();
     // exclusive prefix of the 64 (r, wave) counts, in element order
@@ -1146,7 +1153,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
             perm[slot] = (uint16_t)e;
         }
     }
-    if (kSamples && t < 2) {
+    if (kLarge && t < 2) {
         // the children's sample ranks from j0 on lie in this chunk's runs: run
         // k holds child positions p0 .. p0 + rlen - 1 at output slots from
         // k ? nl_chunk : 0 (the sample position of rank j is
@@ -1174,72 +1181,116 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
         ps_par[k][4] = p0;
     }
     __syncthreads();
-    // columns 0 .. d (d is the index column): stage in LDS, then write the
-    // left and right runs contiguously; the next column's loads are issued
-    // before the barrier so that their latency overlaps this column's writes
+    // columns, each staged in LDS and then written as the left and right
+    // runs; the last pass moves the index column (column d).  The next
+    // column's loads are issued before the barrier so that their latency
+    // overlaps this column's writes.
     uint32_t nxt[kR];
-    {
-        const uint32_t* srcw = d > 0 ? reinterpret_cast<const uint32_t*>(src_cols)
-                                     : reinterpret_cast<const uint32_t*>(src_idx);
+    if constexpr (kLarge) {
+        // pass 0 the split column kc (staged above), passes 1 .. d - 1 the
+        // other coordinate columns in order
+        const int kc = dim >= 0 ? dim : 0;
+        int col = kc, ncol = kc == 0 ? 1 : 0;  // this pass's column and the next one's
+        for (int it = 0; it <= d; ++it, col = ncol, ncol += ncol + 1 == kc ? 2 : 1) {
+            uint32_t* dstw = col < d
+                ? reinterpret_cast<uint32_t*>(dst_cols + (int64_t)col * n)
+                : reinterpret_cast<uint32_t*>(dst_idx);
+            if (it > 0) {
 #pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            const int e = kBlock * r + t;
-            nxt[r] = srcw[src0 + (e < len ? e : len - 1)];
-        }
-    }
-    for (int col = 0; col <= d; ++col) {
-        uint32_t* dstw = col < d ? reinterpret_cast<uint32_t*>(dst_cols + (int64_t)col * n)
-                                 : reinterpret_cast<uint32_t*>(dst_idx);
+                for (int r = 0; r < kR; ++r) {
+                    const int e = kBlock * r + t;
+                    if (e < len) stage[e] = nxt[r];
+                }
+            }
+            if (it < d) {
+                const uint32_t* srcw = ncol < d
+                    ? reinterpret_cast<const uint32_t*>(src_cols + (int64_t)ncol * n)
+                    : reinterpret_cast<const uint32_t*>(src_idx);
 #pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            const int e = kBlock * r + t;
-            if (e < len) stage[e] = nxt[r];
+                for (int r = 0; r < kR; ++r) {
+                    const int e = kBlock * r + t;
+                    nxt[r] = srcw[src0 + (e < len ? e : len - 1)];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                const int i = kBlock * r + t;
+                if (i < len) {
+                    const int64_t dst =
+                        i < (int)nl_chunk ? base_l + i : base_r + (i - (int)nl_chunk);
+                    dstw[dst] = stage[perm[i]];
+                }
+            }
+            // the children's samples (the loop bodies stay rolled: unrolled, they
+            // need more registers)
+            if (col < d) {
+#pragma unroll 1
+                for (int k = 0; k < 2; ++k) {  // block-uniform values, in scalar registers
+                    const int sl = __builtin_amdgcn_readfirstlane(ps_par[k][0]);
+                    if (sl < 0) continue;
+                    uint32_t* ps = reinterpret_cast<uint32_t*>(psamp) +
+                                   ((int64_t)sl * d + col) * kSampleMax;
+                    const int i0 = k == 0 ? 0 : __builtin_amdgcn_readfirstlane((int)nl_chunk);
+                    const int rlen = __builtin_amdgcn_readfirstlane(ps_par[k][2]);
+                    const uint32_t cc = (uint32_t)__builtin_amdgcn_readfirstlane(ps_par[k][3]);
+                    const int p0 = __builtin_amdgcn_readfirstlane(ps_par[k][4]);
+#pragma unroll 1
+                    for (int j = __builtin_amdgcn_readfirstlane(ps_par[k][1]) + t; j < kSampleMax;
+                         j += kBlock) {
+                        // (2j + 1) c' >> 11 from the 64-bit product's two halves
+                        const uint32_t a = 2u * (uint32_t)j + 1u;
+                        const uint32_t pos = (__umulhi(a, cc) << 21) | ((a * cc) >> 11);
+                        const int q = (int)pos - p0;
+                        if (q >= rlen) break;
+                        ps[j] = stage[perm[i0 + q]];
+                    }
+                }
+            }
+            __syncthreads();
         }
-        if (col < d) {
-            const uint32_t* srcw = col + 1 < d
-                ? reinterpret_cast<const uint32_t*>(src_cols + (int64_t)(col + 1) * n)
-                : reinterpret_cast<const uint32_t*>(src_idx);
+    } else {
+        // the columns in order, column 0 loaded here
+        {
+            const uint32_t* srcw = d > 0 ? reinterpret_cast<const uint32_t*>(src_cols)
+                                         : reinterpret_cast<const uint32_t*>(src_idx);
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int e = kBlock * r + t;
                 nxt[r] = srcw[src0 + (e < len ? e : len - 1)];
             }
         }
-        __syncthreads();
+        for (int col = 0; col <= d; ++col) {
+            uint32_t* dstw = col < d
+                ? reinterpret_cast<uint32_t*>(dst_cols + (int64_t)col * n)
+                : reinterpret_cast<uint32_t*>(dst_idx);
 #pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            const int i = kBlock * r + t;
-            if (i < len) {
-                const int64_t dst = i < (int)nl_chunk ? base_l + i : base_r + (i - (int)nl_chunk);
-                dstw[dst] = stage[perm[i]];
+            for (int r = 0; r < kR; ++r) {
+                const int e = kBlock * r + t;
+                if (e < len) stage[e] = nxt[r];
             }
-        }
-        // the children's samples (the loop bodies stay rolled: unrolled, they
-        // need more registers)
-        if (kSamples && col < d) {
-#pragma unroll 1
-            for (int k = 0; k < 2; ++k) {  // block-uniform values, in scalar registers
-                const int sl = __builtin_amdgcn_readfirstlane(ps_par[k][0]);
-                if (sl < 0) continue;
-                uint32_t* ps = reinterpret_cast<uint32_t*>(psamp) +
-                               ((int64_t)sl * d + col) * kSampleMax;
-                const int i0 = k == 0 ? 0 : __builtin_amdgcn_readfirstlane((int)nl_chunk);
-                const int rlen = __builtin_amdgcn_readfirstlane(ps_par[k][2]);
-                const uint32_t cc = (uint32_t)__builtin_amdgcn_readfirstlane(ps_par[k][3]);
-                const int p0 = __builtin_amdgcn_readfirstlane(ps_par[k][4]);
-#pragma unroll 1
-                for (int j = __builtin_amdgcn_readfirstlane(ps_par[k][1]) + t; j < kSampleMax;
-                     j += kBlock) {
-                    // (2j + 1) c' >> 11 from the 64-bit product's two halves
-                    const uint32_t a = 2u * (uint32_t)j + 1u;
-                    const uint32_t pos = (__umulhi(a, cc) << 21) | ((a * cc) >> 11);
-                    const int q = (int)pos - p0;
-                    if (q >= rlen) break;
-                    ps[j] = stage[perm[i0 + q]];
+            if (col < d) {
+                const uint32_t* srcw = col + 1 < d
+                    ? reinterpret_cast<const uint32_t*>(src_cols + (int64_t)(col + 1) * n)
+                    : reinterpret_cast<const uint32_t*>(src_idx);
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    const int e = kBlock * r + t;
+                    nxt[r] = srcw[src0 + (e < len ? e : len - 1)];
                 }
             }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                const int i = kBlock * r + t;
+                if (i < len) {
+                    const int64_t dst =
+                        i < (int)nl_chunk ? base_l + i : base_r + (i - (int)nl_chunk);
+                    dstw[dst] = stage[perm[i]];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
