@@ -2494,8 +2494,9 @@ void enqueue_level(const LevelWork& w, const Level& cur, const Level& nxt, int l
                                                                        w.pblk, w.g);
     k_plan_top<<<1, kPlanBlock, 0, st>>>(cur, nxt, w.pblk, w.g, w.rng, level, w.big_cap,
                                          w.sub_cap, w.nn_cap, w.nb_cap, w.nbh_cap, w.ps_cap);
-    // pre-gathered samples while the largest tree's children can still hold
-    // kPreSampleMin points (splits near the median halve the nodes)
+    // large-node levels (the partition's kLarge instance: pre-gathered samples,
+    // the split column read once) while the largest tree's children can still
+    // hold kPreSampleMin points (splits near the median halve the nodes)
     const bool pres = level < 62 && (w.largest >> (level + 1)) >= kPreSampleMin;
     k_plan_write<<<blocks_for(nn_l, kBlock), kBlock, 0, st>>>(
         cur, nxt, w.dimv, w.splitv, w.nleft, w.planx, w.pblk, w.leaf, w.W, w.max_depth, buf ^ 1,
