@@ -29,6 +29,10 @@ constexpr int kLocQ = 2;
 constexpr int kStackMinK4 = 16;
 constexpr int kStackMinLeaf4 = 16;
 
+// Counting sort of the queries: scan blocks of kScanChunk bucket counts.
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kBlock * kScanItems;
+
 // A query whose tree id is out of range descends tree 0 here (only its
 // place in the grouped order depends on it); the traversal answers it with
 // padding rows.
@@ -80,16 +84,19 @@ __global__ __launch_bounds__(kBlock) void k_locate(const NodeRec* __restrict__ n
 }
 
 // Counting-sort scatter: query i takes the next slot of its home leaf's
-// bucket; slot p gets (i, home leaf) in one 8-byte store.
+// bucket, at the bucket's offset inside its scan block plus the block's base;
+// slot p gets (i, home leaf) in one 8-byte store.
 __global__ __launch_bounds__(kBlock) void k_group(const NodeRec* __restrict__ nodes,
                                                   const int32_t* __restrict__ home, int64_t m,
                                                   int shift, uint32_t* __restrict__ offs,
+                                                  const uint32_t* __restrict__ bsum,
                                                   int2* __restrict__ slots)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= m) return;
     const int h = home[i];
-    const uint32_t p = atomicAdd(&offs[nodes[h].a >> shift], 1u);
+    const int64_t key = nodes[h].a >> shift;
+    const uint32_t p = atomicAdd(&offs[key], 1u) + bsum[key / kScanChunk];
     slots[p] = make_int2((int)i, h);
 }
 
@@ -99,11 +106,9 @@ __global__ __launch_bounds__(kBlock) void k_zero(uint32_t* __restrict__ a, int64
     if (i < len) a[i] = 0u;
 }
 
-// Exclusive scan of uint32 in place: per-block scan of 4096 values, a scan
-// of the block sums, then the block offsets are added.
-constexpr int kScanItems = 16;
-constexpr int kScanChunk = kBlock * kScanItems;
-
+// Exclusive scan of the bucket counts: per-block scan of kScanChunk values in
+// place and a scan of the block sums; k_group adds a bucket's block sum to
+// the slot it takes.
 __device__ uint32_t block_scan_excl(uint32_t v, uint32_t* wsum, uint32_t* total)
 {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -159,12 +164,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t* __restrict__ bsu
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t* __restrict__ a, int64_t len,
-                                                     const uint32_t* __restrict__ bsum)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < len) a[i] += bsum[i / kScanChunk];
-}
 
 using LocateFn = void (*)(const NodeRec*, const float*, const int32_t*, int32_t, int64_t, int,
                           int32_t*, uint32_t*);
@@ -422,8 +421,7 @@ int query_tree(const knn_tree* t, const QuerySpec& qs, hipStream_t st)
     if (grouped) {
         k_scan_local<<<(unsigned)nsb, kBlock, 0, st>>>(cnt, N, bsum);
         k_scan_sums<<<1, kBlock, 0, st>>>(bsum, nsb);
-        k_scan_add<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, st>>>(cnt, N, bsum);
-        k_group<<<grid, kBlock, 0, st>>>(t->nodes, home, m, shift, cnt, slots);
+        k_group<<<grid, kBlock, 0, st>>>(t->nodes, home, m, shift, cnt, bsum, slots);
         KNN_HIP(hipGetLastError());
     }
     prof_mark(st, 7);
